@@ -1,0 +1,424 @@
+/*
+ * gmacop_oracle.c -- CPU oracle for the GMACO-P routing hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY (see gmacop_oracle.h).  Plain single-threaded C,
+ * written for checking by eye against the paper, not for speed.  No blocking,
+ * fusion or reordering beyond what each step states.
+ *
+ * Paper: Jindal & Bedi, arXiv 2010.14244.  Section numbers below refer to it.
+ */
+#include "gmacop_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+#define U32_MAX 0xFFFFFFFFu
+#define COST_CAP (1u << 31)              /* one road never costs more than 2^31 ms */
+#define PATH_COST_CAP 0xFFFFFFFEu        /* UINT32_MAX is reserved for "no route" */
+
+/* ------------------------------------------------------------------------ */
+/* Random numbers: Philox4x32-10, counter based (Salmon et al., SC'11).     */
+/* The counter of the draw for step s of ant k of vehicle q in iteration t  */
+/* is (q, k, t, s); the key is the 64-bit seed split into two words.        */
+/* ------------------------------------------------------------------------ */
+
+static void philox_round(uint32_t c[4], const uint32_t k[2])
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t out[4];
+    out[0] = hi1 ^ c[1] ^ k[0];
+    out[1] = lo1;
+    out[2] = hi0 ^ c[3] ^ k[1];
+    out[3] = lo0;
+    memcpy(c, out, sizeof(out));
+}
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {              /* key schedule: Weyl sequence */
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        philox_round(c, k);
+    }
+    memcpy(out, c, sizeof(c));
+}
+
+static uint64_t draw64(const orc_params *p, uint32_t qid, uint32_t ant, uint32_t iter, uint32_t step)
+{
+    const uint32_t ctr[4] = {qid, ant, p->iter_offset + iter, step};
+    const uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    return ((uint64_t)x[1] << 32) | x[0];
+}
+
+/* floor(sqrt(x)) by bisection over [0, 2^32): the largest s with s*s <= x. */
+uint64_t orc_isqrt(uint64_t x)
+{
+    uint64_t lo = 0, hi = (uint64_t)1 << 32;     /* invariant: lo*lo <= x < hi*hi */
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (mid * mid <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Static per-road quantities.                                              */
+/* Free-flow time t0 = len / speed in ms: len_dm * 0.1 m / (speed / 3.6)    */
+/* m/s * 1000 = len_dm * 360 / speed.  Floor, at least 1 ms, at most 2^31.  */
+/* Fixed-time wait of approach e at its head v (the signal the vehicle      */
+/* meets at the end of the road, Section 4.1): with cycle C and red time    */
+/* R = C*(1000-green)/1000, an arrival uniform over the cycle waits R^2/(2C) */
+/* on average; capped at T_max because a phase waiting longer than T_max   */
+/* is given green (Fig. 3, "t_w > T_max").                                  */
+/* ------------------------------------------------------------------------ */
+void orc_edge_static(const orc_graph *g, const orc_params *p, uint32_t *t0, uint32_t *wf)
+{
+    for (uint32_t e = 0; e < g->m; ++e) {
+        uint64_t t = (uint64_t)g->len_dm[e] * 360u / g->speed_kmh[e];
+        if (t < 1) t = 1;
+        if (t > COST_CAP) t = COST_CAP;
+        t0[e] = (uint32_t)t;
+
+        const uint32_t v = g->col[e];
+        const uint64_t C = g->cycle_ms[v];
+        if (C == 0) {
+            wf[e] = 0;
+        } else {
+            const uint64_t red = C * (1000u - g->green_pm[e]) / 1000u;
+            uint64_t w = red * red / (2 * C);
+            if (w > p->t_max_ms) w = p->t_max_ms;
+            wf[e] = (uint32_t)w;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cost table (Section 4.2: Calc_Dens, Comp_Thres, Eval_Rout; Fig. 3).      */
+/* A phase of an intersection is one incoming road; its queue is the road's */
+/* load.  The preemptive rule gives green to the approach with the longest  */
+/* queue (ties: the lowest road id) and to any approach whose queue exceeds */
+/* Th_max; an empty queue never takes the green.  A road whose approach has */
+/* green costs no signal wait.  Congestion: a road carrying more than the   */
+/* threshold theta vehicles is slowed in proportion to its load.            */
+/* ------------------------------------------------------------------------ */
+void orc_cost_table(const orc_graph *g, const orc_params *p, const uint32_t *load,
+                    const uint32_t *t0, const uint32_t *wf, uint32_t *cost, uint8_t *preempted)
+{
+    /* For every intersection, the approach with the longest non-empty queue. */
+    uint32_t *best_edge = (uint32_t *)malloc(sizeof(uint32_t) * (g->n ? g->n : 1));
+    for (uint32_t v = 0; v < g->n; ++v) best_edge[v] = U32_MAX;
+    for (uint32_t e = 0; e < g->m; ++e) {         /* ascending e: first maximum wins */
+        if (load[e] == 0) continue;
+        const uint32_t v = g->col[e];
+        if (best_edge[v] == U32_MAX || load[e] > load[best_edge[v]]) best_edge[v] = e;
+    }
+    for (uint32_t e = 0; e < g->m; ++e) {
+        const uint32_t v = g->col[e];
+        const int green = g->cycle_ms[v] > 0 && load[e] > 0 &&
+                          (load[e] > p->th_max || best_edge[v] == e);
+        if (preempted) preempted[e] = (uint8_t)green;
+        const uint64_t wait = green ? 0 : wf[e];
+        const uint64_t travel = load[e] <= p->theta ? t0[e] : (uint64_t)t0[e] * load[e] / p->theta;
+        uint64_t c = travel + wait;
+        if (c > COST_CAP) c = COST_CAP;
+        cost[e] = (uint32_t)c;
+    }
+    free(best_edge);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Goal term (Section 4.2, Calc_Dist: distance from the current position to */
+/* the destination).  Straight-line distance over the fastest speed in the  */
+/* network, a lower bound on the remaining travel time:                      */
+/*   h = floor(isqrt(dx^2 + dy^2) * k / 2^16),  k = floor(360 * 2^16 / vmax) */
+/* vmax = 0 switches the term off.                                           */
+/* ------------------------------------------------------------------------ */
+uint64_t orc_goal(const orc_graph *g, const orc_params *p, uint32_t node, uint32_t dst)
+{
+    if (p->vmax_kmh == 0) return 0;
+    const int64_t dx = (int64_t)g->x_dm[node] - g->x_dm[dst];
+    const int64_t dy = (int64_t)g->y_dm[node] - g->y_dm[dst];
+    const uint64_t d2 = (uint64_t)(dx * dx) + (uint64_t)(dy * dy);
+    const uint64_t k = (uint64_t)360u * 65536u / p->vmax_kmh;
+    return orc_isqrt(d2) * k >> 16;
+}
+
+/* Desirability of a road from its reduced cost delta = cost + h(head) - h(tail):
+ * eta = floor(2^26 / max(delta, 1)), clamped to [1, 65535]. */
+uint32_t orc_eta(int64_t delta)
+{
+    const uint64_t d = delta < 1 ? 1 : (uint64_t)delta;
+    uint64_t eta = ((uint64_t)1 << 26) / d;
+    if (eta < 1) eta = 1;
+    if (eta > 65535) eta = 65535;
+    return (uint32_t)eta;
+}
+
+static uint64_t ipow(uint64_t b, uint32_t e)
+{
+    uint64_t r = 1;
+    for (uint32_t i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+/* Roulette over d weights: target = floor(r * T / 2^64) with T the weight
+ * total; the choice is the first index whose inclusive prefix sum exceeds
+ * the target.  Zero weights are never chosen. */
+uint32_t orc_roulette(const uint64_t *w, uint32_t d, uint64_t r)
+{
+    uint64_t T = 0;
+    for (uint32_t j = 0; j < d; ++j) T += w[j];
+    const uint64_t target = (uint64_t)(((unsigned __int128)r * T) >> 64);
+    uint64_t prefix = 0;
+    for (uint32_t j = 0; j < d; ++j) {
+        prefix += w[j];
+        if (prefix > target) return j;
+    }
+    return d;   /* only reached when T == 0 */
+}
+
+/* Pheromone apply for one road (Section 4.2, Updt_Pher and Evap_Pher):
+ * evaporate by rho (Q16), add the deposit scaled down by theta/load on a
+ * congested road (MACO: congested roads attract less), clamp. */
+uint32_t orc_apply_tau(const orc_params *p, uint32_t tau, uint64_t deposit, uint32_t load)
+{
+    const uint64_t dp = load <= p->theta ? deposit
+                                         : (uint64_t)(((unsigned __int128)deposit * p->theta) / load);
+    const uint64_t evap = (uint64_t)tau * (65536u - p->rho_q16) / 65536u;
+    uint64_t t = evap + dp;
+    if (t < p->tau_min_q16) t = p->tau_min_q16;
+    if (t > p->tau_max_q16) t = p->tau_max_q16;
+    return (uint32_t)t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One ant (Section 4.2 Alg. 2 steps 4-6; Fig. 3 "else" branch).            */
+/* From the current node, the candidates are the out-roads (CSR order) whose */
+/* head has not been visited by this ant (Adj_Neigh).  Each has weight       */
+/* tau^alpha * eta^beta; the roulette picks one.  No candidates = dead end.  */
+/* The walk succeeds on reaching dst and fails after max_steps roads.       */
+/* ------------------------------------------------------------------------ */
+static uint8_t *g_visited;          /* scratch, n bytes, all zero between walks */
+static uint32_t g_visited_n;
+
+static int walk_impl(const orc_graph *g, const orc_params *p, const uint32_t *tau, const uint32_t *cost,
+                     uint32_t qid, uint32_t src, uint32_t dst, uint32_t ant, uint32_t iter,
+                     uint32_t *path, uint32_t *len, uint32_t *cost_sum, uint64_t *selections,
+                     uint64_t *wbuf)
+{
+    uint8_t *visited = g_visited;
+    uint32_t u = src, s = 0, cs = 0;
+    int ok = 0;
+    visited[u] = 1;
+    int64_t hu = (int64_t)orc_goal(g, p, u, dst);
+    for (;;) {
+        if (s == p->max_steps) break;
+        const uint32_t rs = g->row_ptr[u], d = g->row_ptr[u + 1] - rs;
+        uint64_t T = 0;
+        for (uint32_t j = 0; j < d; ++j) {
+            const uint32_t e = rs + j, x = g->col[e];
+            if (visited[x]) { wbuf[j] = 0; continue; }
+            const int64_t delta = (int64_t)cost[e] + (int64_t)orc_goal(g, p, x, dst) - hu;
+            wbuf[j] = ipow(tau[e], p->alpha) * ipow(orc_eta(delta), p->beta);
+            T += wbuf[j];
+        }
+        if (T == 0) break;                                    /* dead end */
+        const uint32_t j = orc_roulette(wbuf, d, draw64(p, qid, ant, iter, s));
+        const uint32_t e = rs + j;
+        path[s++] = e;
+        *selections += 1;
+        const uint64_t c = (uint64_t)cs + cost[e];
+        cs = c > PATH_COST_CAP ? PATH_COST_CAP : (uint32_t)c;
+        u = g->col[e];
+        visited[u] = 1;
+        hu = (int64_t)orc_goal(g, p, u, dst);
+        if (u == dst) { ok = 1; break; }
+    }
+    /* clear the visited marks of this walk */
+    visited[src] = 0;
+    for (uint32_t i = 0; i < s; ++i) visited[g->col[path[i]]] = 0;
+    *len = s;
+    *cost_sum = cs;
+    return ok;
+}
+
+static uint32_t max_out_degree(const orc_graph *g)
+{
+    uint32_t dmax = 0;
+    for (uint32_t u = 0; u < g->n; ++u) {
+        const uint32_t d = g->row_ptr[u + 1] - g->row_ptr[u];
+        if (d > dmax) dmax = d;
+    }
+    return dmax;
+}
+
+static void ensure_visited(uint32_t n)
+{
+    if (g_visited_n < n) {
+        free(g_visited);
+        g_visited = (uint8_t *)calloc(n, 1);
+        g_visited_n = n;
+    }
+}
+
+int orc_walk(const orc_graph *g, const orc_params *p, const uint32_t *tau, const uint32_t *cost,
+             uint32_t qid, uint32_t src, uint32_t dst, uint32_t ant, uint32_t iter,
+             uint32_t *path, uint32_t *len, uint32_t *cost_sum, uint64_t *selections)
+{
+    ensure_visited(g->n);
+    uint64_t *wbuf = (uint64_t *)malloc(sizeof(uint64_t) * (max_out_degree(g) + 1));
+    const int ok = walk_impl(g, p, tau, cost, qid, src, dst, ant, iter, path, len, cost_sum, selections, wbuf);
+    free(wbuf);
+    return ok;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Parameter checks: -1 invalid, -2 outside the exact-integer range.        */
+/* Every roulette total must fit 64 bits: each weight is below              */
+/* 2^(alpha*bits(tau_max) + 16*beta), and a row holds at most 2^ceil(log2 d) */
+/* of them.  Deposit totals must stay below 2^63.                           */
+/* ------------------------------------------------------------------------ */
+static uint32_t bit_length(uint64_t x) { uint32_t b = 0; while (x) { ++b; x >>= 1; } return b; }
+
+static int check(const orc_graph *g, const uint32_t *src, const uint32_t *dst, uint32_t nv,
+                 const orc_params *p)
+{
+    if (p->ants == 0 || p->max_steps == 0 || p->theta == 0) return -1;
+    if (p->rho_q16 > 65536u || p->tau_min_q16 == 0) return -1;
+    if (p->tau_min_q16 > p->tau0_q16 || p->tau0_q16 > p->tau_max_q16) return -1;
+    if (p->mode > 1) return -1;
+    for (uint32_t i = 0; i < nv; ++i)
+        if (src[i] >= g->n || dst[i] >= g->n || src[i] == dst[i]) return -1;
+    const uint32_t dmax = max_out_degree(g);
+    const uint32_t lg = dmax <= 1 ? 0 : bit_length(dmax - 1);
+    if ((uint64_t)p->alpha * bit_length(p->tau_max_q16) + 16ull * p->beta + lg > 64) return -2;
+    const unsigned __int128 dep = (unsigned __int128)(p->mode == ORC_MODE_SHARED ? nv : 1) * p->ants * p->q_deposit;
+    if (dep >> 63) return -2;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One vehicle, one iteration: all its ants walk on the same pheromone and  */
+/* cost table; the iteration-best ant is the successful one with the lowest */
+/* (cost, ant index); it replaces the vehicle's best route when strictly    */
+/* cheaper (the route output of Alg. 1).  Every successful ant k deposits   */
+/* q_deposit / cost_k on each road of its path (Updt_Pher).                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const orc_graph *g;
+    const orc_params *p;
+    uint32_t S;
+    uint32_t *ant_path, *iter_path;
+    uint64_t *wbuf;
+    uint64_t steps;
+} route_ctx;
+
+static void vehicle_iteration(route_ctx *c, uint32_t qid, uint32_t src, uint32_t dst, uint32_t t,
+                              const uint32_t *tau, const uint32_t *cost, uint64_t *dep,
+                              uint32_t *best_path, uint32_t *best_len, uint32_t *best_cost)
+{
+    const orc_params *p = c->p;
+    uint64_t iter_key = UINT64_MAX;
+    uint32_t iter_len = 0;
+    for (uint32_t k = 0; k < p->ants; ++k) {
+        uint32_t len, cs;
+        if (!walk_impl(c->g, p, tau, cost, qid, src, dst, k, t, c->ant_path, &len, &cs, &c->steps, c->wbuf))
+            continue;
+        const uint64_t key = ((uint64_t)cs << 32) | k;
+        if (key < iter_key) {
+            iter_key = key;
+            iter_len = len;
+            memcpy(c->iter_path, c->ant_path, sizeof(uint32_t) * len);
+        }
+        const uint64_t d = p->q_deposit / cs;
+        for (uint32_t i = 0; i < len; ++i) dep[c->ant_path[i]] += d;
+    }
+    if (iter_key != UINT64_MAX && (uint32_t)(iter_key >> 32) < *best_cost) {
+        *best_cost = (uint32_t)(iter_key >> 32);
+        *best_len = iter_len;
+        memcpy(best_path, c->iter_path, sizeof(uint32_t) * iter_len);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The whole run (Alg. 2 iterated).  Shared mode: all vehicles share one    */
+/* pheromone vector and one load vector; per iteration: cost table from the */
+/* load, every ant of every vehicle walks, best routes, deposit, evaporate  */
+/* + apply (penalised by the load the ants saw), then the load becomes the  */
+/* sensed load plus one for every vehicle whose best route uses the road    */
+/* (MACO marker, Fig. 3 "Ph_road++").  Independent mode: each vehicle has a */
+/* private pheromone vector and the load stays at the sensed value.         */
+/* ------------------------------------------------------------------------ */
+int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, const uint32_t *dst,
+              uint32_t nv, const orc_params *p,
+              uint32_t *path_edges, uint32_t *path_len, uint32_t *cost_ms, uint64_t *steps_total,
+              uint32_t *tau_out, uint32_t *load_out, uint32_t *best_hist)
+{
+    const int rc = check(g, src, dst, nv, p);
+    if (rc) return rc;
+    const uint32_t m = g->m, S = p->max_steps;
+    ensure_visited(g->n);
+    route_ctx c = {g, p, S, NULL, NULL, NULL, 0};
+    c.wbuf = (uint64_t *)malloc(sizeof(uint64_t) * (max_out_degree(g) + 1));
+    c.ant_path = (uint32_t *)malloc(sizeof(uint32_t) * S);
+    c.iter_path = (uint32_t *)malloc(sizeof(uint32_t) * S);
+    uint32_t *t0 = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *wf = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *cost = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *load = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint64_t *dep = (uint64_t *)malloc(sizeof(uint64_t) * (m + 1));
+    const int shared = p->mode == ORC_MODE_SHARED;
+    const uint32_t n_tau = shared ? 1 : nv;
+    uint32_t *tau = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)n_tau * m + 1));
+
+    orc_edge_static(g, p, t0, wf);
+    for (uint32_t e = 0; e < m; ++e) load[e] = g->base_load[e];
+    for (size_t i = 0; i < (size_t)n_tau * m; ++i) tau[i] = p->tau0_q16;
+    for (uint32_t v = 0; v < nv; ++v) { path_len[v] = 0; cost_ms[v] = U32_MAX; }
+
+    if (shared) {
+        for (uint32_t t = 0; t < p->iterations; ++t) {
+            orc_cost_table(g, p, load, t0, wf, cost, NULL);
+            memset(dep, 0, sizeof(uint64_t) * m);
+            for (uint32_t v = 0; v < nv; ++v) {
+                vehicle_iteration(&c, qid[v], src[v], dst[v], t, tau, cost, dep,
+                                  path_edges + (size_t)v * S, &path_len[v], &cost_ms[v]);
+                if (best_hist) best_hist[(size_t)t * nv + v] = cost_ms[v];
+            }
+            for (uint32_t e = 0; e < m; ++e) tau[e] = orc_apply_tau(p, tau[e], dep[e], load[e]);
+            if (!(p->flags & ORC_FLAG_NO_LOAD_UPDATE)) {
+                for (uint32_t e = 0; e < m; ++e) load[e] = g->base_load[e];
+                for (uint32_t v = 0; v < nv; ++v)
+                    for (uint32_t i = 0; i < path_len[v]; ++i) load[path_edges[(size_t)v * S + i]] += 1;
+            }
+        }
+    } else {
+        orc_cost_table(g, p, load, t0, wf, cost, NULL);
+        for (uint32_t v = 0; v < nv; ++v) {
+            uint32_t *tv = tau + (size_t)v * m;
+            for (uint32_t t = 0; t < p->iterations; ++t) {
+                memset(dep, 0, sizeof(uint64_t) * m);
+                vehicle_iteration(&c, qid[v], src[v], dst[v], t, tv, cost, dep,
+                                  path_edges + (size_t)v * S, &path_len[v], &cost_ms[v]);
+                if (best_hist) best_hist[(size_t)t * nv + v] = cost_ms[v];
+                for (uint32_t e = 0; e < m; ++e) tv[e] = orc_apply_tau(p, tv[e], dep[e], load[e]);
+            }
+        }
+    }
+
+    *steps_total = c.steps;
+    if (tau_out) memcpy(tau_out, tau, sizeof(uint32_t) * (size_t)n_tau * m);
+    if (load_out) memcpy(load_out, load, sizeof(uint32_t) * m);
+    free(c.wbuf); free(c.ant_path); free(c.iter_path);
+    free(t0); free(wf); free(cost); free(load); free(dep); free(tau);
+    return 0;
+}

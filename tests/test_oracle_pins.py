@@ -1,0 +1,556 @@
+"""Pins of the CPU oracle to facts fixed outside it: an independent Philox
+implementation (rocRAND), Python's exact integer square root, hand-worked
+examples, closed forms, exact roulette partition boundaries, chi-square
+frequency tests, brute-force path enumeration, Dijkstra optimality bounds and
+invariants.  No GPU needed."""
+import json
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import dijkstra
+from scipy.stats import chisquare
+
+from workloads import default_params, from_edges, grid_graph, grid8, grid32, pack_graphs, planar_graph, random_od
+from workloads.roadgraph import Vehicles
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def veh(src, dst, qid=None):
+    src = np.atleast_1d(np.asarray(src, np.uint32))
+    dst = np.atleast_1d(np.asarray(dst, np.uint32))
+    q = np.arange(src.shape[0], dtype=np.uint32) if qid is None else np.atleast_1d(np.asarray(qid, np.uint32))
+    return Vehicles(qid=q, src=src, dst=dst)
+
+
+# ---------------------------------------------------------------------------
+# random numbers
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "philox_ref")
+    subprocess.check_call([hipcc, "-O1", "-o", exe, os.path.join(HERE, "philox_rocrand_ref.cpp")],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return exe
+
+
+def test_philox_matches_rocrand(orc, rocrand_ref):
+    rng = np.random.default_rng(7)
+    cases = [(0, 0, 0, 0, 0, 0), (0xFFFFFFFF,) * 6, (1, 0, 0, 0, 0, 0), (0, 0, 1, 0, 0, 0),
+             (0x12345678, 0x9ABCDEF0, 3, 5, 49, 1023)]
+    for _ in range(60):
+        cases.append(tuple(int(v) for v in rng.integers(0, 2 ** 32, size=6, dtype=np.uint64)))
+    args = [hex(v) for c in cases for v in c]
+    out = subprocess.check_output([rocrand_ref] + args, text=True).split("\n")
+    for c, line in zip(cases, out):
+        want = [int(w, 16) for w in line.split()]
+        got = orc.philox4x32_10(c[2:], c[:2]).tolist()
+        assert got == want, (c, got, want)
+
+
+# ---------------------------------------------------------------------------
+# integer square root
+# ---------------------------------------------------------------------------
+
+def test_isqrt_matches_python(orc):
+    rng = np.random.default_rng(3)
+    xs = [0, 1, 2, 3, 4, 2 ** 64 - 1, 2 ** 63, 2 ** 62 - 1]
+    for b in range(1, 64):
+        xs += [int(v) for v in rng.integers(0, 2 ** b, size=40, dtype=np.uint64)]
+    roots = [int(v) for v in rng.integers(0, 2 ** 32, size=300, dtype=np.uint64)]
+    for r in roots:
+        for d in (-1, 0, 1):
+            v = r * r + d
+            if 0 <= v < 2 ** 64:
+                xs.append(v)
+    for x in xs:
+        assert orc.isqrt(x) == math.isqrt(x), x
+
+
+# ---------------------------------------------------------------------------
+# hand-worked intersection
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def worked():
+    with open(os.path.join(HERE, "golden", "intersection_worked_example.json")) as f:
+        return json.load(f)
+
+
+def worked_graph(w, load):
+    gd = w["graph"]
+    t = [a for a, b in gd["roads_tail_head"]]
+    h = [b for a, b in gd["roads_tail_head"]]
+    # roads are listed in CSR order already (sorted by tail)
+    return from_edges(gd["n"], t, h, len_dm=gd["len_dm"], speed_kmh=gd["speed_kmh"], green_pm=gd["green_pm"],
+                      cycle_ms=gd["cycle_ms"], x_dm=gd["x_dm"], y_dm=gd["y_dm"], base_load=load)
+
+
+def test_worked_static(orc, worked):
+    g = worked_graph(worked, 0)
+    p = default_params(**worked["params"])
+    t0, wf = orc.edge_static(g, p)
+    assert t0.tolist() == worked["t0_ms"]["value"]
+    assert wf.tolist() == worked["wf_ms"]["value"]
+
+
+def test_worked_cost_and_preemption(orc, worked):
+    p = default_params(**worked["params"])
+    for sc in worked["scenarios"]:
+        g = worked_graph(worked, sc["load"])
+        cost, pre = orc.cost_table(g, p, np.asarray(sc["load"], np.uint32))
+        assert pre.tolist() == sc["preempted"], sc["derivation"]
+        assert cost.tolist() == sc["cost_ms"], sc["derivation"]
+
+
+def test_worked_goal_and_eta(orc, worked):
+    p = default_params(**worked["params"])
+    sc = worked["scenarios"][0]
+    g = worked_graph(worked, sc["load"])
+    ge = worked["goal_and_eta"]
+    assert (360 * 65536) // p["vmax_kmh"] == ge["k"]
+    for node, h in ge["h_ms"].items():
+        assert orc.goal(g, p, int(node), ge["dst"]) == h
+    cost = sc["cost_ms"]
+    h4 = ge["h_ms"]["4"]
+    for road, eta in ge["eta_from_node_4_scenario_0"].items():
+        head = worked["graph"]["roads_tail_head"][int(road)][1]
+        delta = cost[int(road)] + ge["h_ms"][str(head)] - h4
+        assert orc.eta(delta) == eta
+
+
+# ---------------------------------------------------------------------------
+# closed forms and special cases of single steps
+# ---------------------------------------------------------------------------
+
+def test_static_edge_cases(orc):
+    g = from_edges(3, [0, 1, 1], [1, 0, 2], len_dm=[1, 10 ** 9, 1000], speed_kmh=[65535, 1, 36],
+                   cycle_ms=[0, 0, 4 * 10 ** 9], green_pm=[500, 500, 0])
+    p = default_params(t_max_ms=4 * 10 ** 9)
+    t0, wf = orc.edge_static(g, p)
+    assert t0[0] == 1                         # 360/65535 floors to 0 -> at least 1 ms
+    assert t0[1] == 2 ** 31                   # 3.6e11 ms capped
+    assert t0[2] == 10000                     # 1000*360/36
+    assert wf[2] == (4 * 10 ** 9) ** 2 // (8 * 10 ** 9)   # all red: C/2
+    assert wf[0] == 0 and wf[1] == 0          # heads 1, 0 unsignalised
+
+
+def test_congestion_travel_threshold(orc):
+    # one road 0->1, t0 = 7200; no signal.  travel = t0 while load <= theta
+    g = from_edges(2, [0, 1], [1, 0], len_dm=1000)
+    for theta in (1, 4, 7):
+        p = default_params(theta=theta)
+        for load in range(0, 30):
+            cost, _ = orc.cost_table(g, p, np.array([load, 0], np.uint32))
+            want = 7200 if load <= theta else (7200 * load) // theta
+            assert cost[0] == want
+
+
+def test_goal_is_lower_bound_of_travel_time(orc):
+    """h(x) never exceeds the cheapest cost-table route from x to dst
+    (straight line at the fastest speed is a lower bound)."""
+    for w in (grid8(), grid32(iterations=1)):
+        g, p = w.graph, w.params
+        cost, _ = orc.cost_table(g, p, g.base_load)
+        A = sp.csr_matrix((cost.astype(np.float64), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
+                          shape=(g.n, g.n))
+        rng = np.random.default_rng(0)
+        for dst in rng.integers(0, g.n, size=4):
+            dist = dijkstra(A.T.tocsr(), indices=int(dst))     # to dst
+            for x in rng.integers(0, g.n, size=40):
+                assert orc.goal(g, p, int(x), int(dst)) <= dist[x] + 1e-9
+
+
+def test_eta_closed_form(orc):
+    two26 = 1 << 26
+    cases = {two26: 1, two26 - 1: 1, two26 + 5: 1, 2 ** 40: 1, 1024: 65535, 1025: two26 // 1025,
+             0: 65535, -5: 65535, -(2 ** 40): 65535, 1: 65535, 12343: 5436, 3000: two26 // 3000}
+    for d, want in cases.items():
+        assert orc.eta(d) == want, d
+
+
+def _boundary(prefix_before, T):
+    """Smallest 64-bit r with floor(r*T/2^64) >= prefix_before."""
+    return -(-(prefix_before << 64) // T)
+
+
+def test_roulette_partition_boundaries(orc):
+    rng = np.random.default_rng(11)
+    for trial in range(200):
+        d = int(rng.integers(1, 9))
+        w = [int(v) for v in rng.integers(0, 2 ** int(rng.integers(1, 60)), size=d, dtype=np.uint64)]
+        if trial % 3 == 0:
+            w[int(rng.integers(d))] = 0
+        T = sum(w)
+        if T == 0 or T >= 2 ** 64:
+            continue
+        P = 0
+        for j, wj in enumerate(w):
+            if wj == 0:
+                continue
+            lo = _boundary(P, T)                  # first r landing in bucket j
+            hi = _boundary(P + wj, T) - 1         # last r landing in bucket j
+            if lo <= hi:
+                assert orc.roulette(w, lo) == j
+                assert orc.roulette(w, hi) == j
+                if lo > 0:
+                    assert orc.roulette(w, lo - 1) != j
+            P += wj
+    # zero weights are never chosen; r at the extremes
+    assert orc.roulette([0, 5, 0, 5], 0) == 1
+    assert orc.roulette([0, 5, 0, 5], 2 ** 64 - 1) == 3
+    assert orc.roulette([7], 2 ** 64 - 1) == 0
+
+
+def test_roulette_frequencies_chi_square(orc):
+    rng = np.random.default_rng(5)
+    w = [1, 2, 3, 0, 10, 4]
+    N = 60000
+    counts = np.zeros(len(w))
+    for r in rng.integers(0, 2 ** 64, size=N, dtype=np.uint64):
+        counts[orc.roulette(w, int(r))] += 1
+    assert counts[3] == 0
+    nz = [j for j in range(len(w)) if w[j]]
+    exp = np.array([w[j] for j in nz], float) / sum(w) * N
+    assert chisquare(counts[nz], exp).pvalue > 1e-3
+
+
+def test_evaporation_closed_form_half(orc):
+    """rho = 1/2, no deposit: tau_t = max(tau_min, tau0 >> t) exactly."""
+    p = default_params(rho_q16=0x8000, tau_min_q16=3)
+    tau = 0x10000
+    for t in range(1, 25):
+        tau = orc.apply_tau(p, tau, 0, 0)
+        assert tau == max(3, 0x10000 >> t)
+
+
+def test_evaporation_error_bound_general_rho(orc):
+    """tau0 (1-rho)^t - tau_t lies in [0, 1/rho) raw units while unclamped."""
+    for rho in (1, 0x1000, 0x4000, 0x5555, 0xC000, 0xFFFF):
+        p = default_params(rho_q16=rho, tau_min_q16=1, tau_max_q16=1 << 24)
+        a = (65536 - rho) / 65536
+        tau, exact = 1 << 24, float(1 << 24)
+        for t in range(1, 60):
+            tau = orc.apply_tau(p, tau, 0, 0)
+            exact *= a
+            if tau == 1:
+                break
+            err = exact - tau
+            assert -1e-6 <= err < 65536 / rho + 1e-6
+
+
+def test_apply_penalty_and_clamp(orc):
+    p = default_params(rho_q16=0, theta=4, tau_min_q16=1, tau_max_q16=1 << 24)
+    assert orc.apply_tau(p, 100, 1000, 4) == 1100            # load <= theta: full deposit
+    assert orc.apply_tau(p, 100, 1000, 8) == 600             # 1000*4/8
+    assert orc.apply_tau(p, 100, 7, 6) == 104                # floor(28/6) = 4
+    assert orc.apply_tau(p, 100, 2 ** 62 + 3, 2 ** 32 - 1) == 1 << 24   # clamp high
+    p2 = default_params(rho_q16=65536, tau_min_q16=9)
+    assert orc.apply_tau(p2, 1000, 0, 0) == 9                # full evaporation -> tau_min
+    # exact penalty on large deposits: floor(D*theta/load) by big-int arithmetic
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        D = int(rng.integers(0, 2 ** 62, dtype=np.uint64))
+        L = int(rng.integers(5, 2 ** 32, dtype=np.uint64))
+        want = min(1 << 24, max(1, D * 4 // L))
+        assert orc.apply_tau(p, 0, D, L) == want
+
+
+# ---------------------------------------------------------------------------
+# walks
+# ---------------------------------------------------------------------------
+
+def test_walk_chain_is_unique(orc):
+    n = 7
+    t = list(range(n - 1)) + list(range(1, n))
+    h = list(range(1, n)) + list(range(n - 1))
+    g = from_edges(n, t, h, len_dm=[1000 + 10 * i for i in range(2 * (n - 1))])
+    p = default_params(max_steps=n - 1, vmax_kmh=0)
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    tau = np.full(g.m, 0x10000, np.uint32)
+    for ant in range(20):
+        ok, path, cs, sel = orc.walk(g, p, tau, cost, 3, 0, n - 1, ant, 0)
+        assert ok and sel == n - 1
+        heads = g.col[path].tolist()
+        assert heads == list(range(1, n))
+        assert cs == int(cost[path].astype(np.int64).sum())
+
+
+def test_walk_max_steps_and_dead_end(orc):
+    # 0 -> 1 -> 2 (dead end: 2 only leads back to 1), 0 -> 3 -> 4
+    g = from_edges(5, [0, 0, 1, 2, 3], [1, 3, 2, 1, 4])
+    p = default_params(max_steps=10, vmax_kmh=0)
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    tau = np.full(g.m, 0x10000, np.uint32)
+    outcomes = set()
+    for ant in range(200):
+        ok, path, cs, sel = orc.walk(g, p, tau, cost, 0, 0, 4, ant, 0)
+        outcomes.add((ok, tuple(g.col[path].tolist())))
+    assert outcomes == {(True, (3, 4)), (False, (1, 2))}
+    p1 = default_params(max_steps=1, vmax_kmh=0)
+    ok, path, cs, sel = orc.walk(g, p1, tau, cost, 0, 0, 4, 0, 0)
+    assert not ok and len(path) == 1 and sel == 1
+
+
+def star_graph():
+    """Node 0 with roads to 1, 2, 3 of free-flow time 2^20, 2^21, 2^22 ms
+    (len 2^17, 2^18, 2^19 dm at 45 km/h: len*360/45 = 8*len), no signals,
+    empty roads; each leads on to 4."""
+    return from_edges(5, [0, 0, 0, 1, 2, 3], [1, 2, 3, 4, 4, 4],
+                      len_dm=[2 ** 17, 2 ** 18, 2 ** 19, 1000, 1000, 1000], speed_kmh=45)
+
+
+def test_first_step_frequencies_chi_square(orc):
+    """eta = 2^26 / cost = 64, 32, 16 -> weights (beta=2) 4096 : 1024 : 256."""
+    g = star_graph()
+    p = default_params(max_steps=4, vmax_kmh=0, alpha=1, beta=2)
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    assert cost[:3].tolist() == [2 ** 20, 2 ** 21, 2 ** 22]
+    tau = np.full(g.m, 0x10000, np.uint32)
+    N = 12000
+    counts = np.zeros(3)
+    for q in range(N):
+        ok, path, cs, sel = orc.walk(g, p, tau, cost, q, 0, 4, 0, 0)
+        assert ok
+        counts[int(path[0])] += 1
+    exp = np.array([16, 4, 1]) / 21 * N
+    assert chisquare(counts, exp).pvalue > 1e-3
+
+
+def test_uniform_walk_when_alpha_beta_zero(orc):
+    g = star_graph()
+    p = default_params(max_steps=4, vmax_kmh=0, alpha=0, beta=0)
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    tau = np.arange(g.m, dtype=np.uint32) + 5
+    N = 9000
+    counts = np.zeros(3)
+    for q in range(N):
+        counts[int(orc.walk(g, p, tau, cost, q, 0, 4, 1, 2)[1][0])] += 1
+    assert chisquare(counts, np.full(3, N / 3)).pvalue > 1e-3
+
+
+def _enumerate_outcomes(g, cost, tau, src, dst, alpha, beta, max_steps):
+    """All walk outcomes with their exact probabilities (goal term off):
+    weight tau^alpha * eta^beta with eta = clamp(2^26 // cost, 1, 65535)."""
+    out = {}
+
+    def rec(u, visited, path, prob):
+        if len(path) == max_steps:
+            out[(False, tuple(path))] = out.get((False, tuple(path)), 0) + prob
+            return
+        rs, re = int(g.row_ptr[u]), int(g.row_ptr[u + 1])
+        ws = []
+        for e in range(rs, re):
+            x = int(g.col[e])
+            if x in visited:
+                ws.append(0)
+            else:
+                eta = min(65535, max(1, (1 << 26) // max(1, int(cost[e]))))
+                ws.append(int(tau[e]) ** alpha * eta ** beta)
+        T = sum(ws)
+        if T == 0:
+            out[(False, tuple(path))] = out.get((False, tuple(path)), 0) + prob
+            return
+        for j, wj in enumerate(ws):
+            if wj == 0:
+                continue
+            e = rs + j
+            x = int(g.col[e])
+            if x == dst:
+                key = (True, tuple(path + [e]))
+                out[key] = out.get(key, 0) + prob * wj / T
+            else:
+                rec(x, visited | {x}, path + [e], prob * wj / T)
+
+    rec(src, {src}, [], 1.0)
+    return out
+
+
+def test_whole_path_distribution_3x3(orc):
+    """Frequencies of complete walks on a 3x3 grid against exact path
+    probabilities from brute-force enumeration of all self-avoiding walks."""
+    rng = np.random.default_rng(2)
+    g = grid_graph(3, 3, rng)
+    p = default_params(max_steps=6, vmax_kmh=0)
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    tau = rng.integers(1, 4, size=g.m).astype(np.uint32) * 0x4000
+    probs = _enumerate_outcomes(g, cost, tau, 0, 8, 1, 2, p["max_steps"])
+    assert abs(sum(probs.values()) - 1) < 1e-9
+    N = 30000
+    counts = {}
+    for q in range(N):
+        ok, path, cs, sel = orc.walk(g, p, tau, cost, q, 0, 8, 0, 0)
+        key = (ok, tuple(int(e) for e in path))
+        assert key in probs
+        counts[key] = counts.get(key, 0) + 1
+    keys = sorted(probs, key=lambda k: -probs[k])
+    big = [k for k in keys if probs[k] * N >= 10]
+    obs = [counts.get(k, 0) for k in big] + [N - sum(counts.get(k, 0) for k in big)]
+    exp = [probs[k] * N for k in big] + [N * (1 - sum(probs[k] for k in big))]
+    if exp[-1] < 5:
+        obs[-2] += obs.pop()
+        exp[-2] += exp.pop()
+    exp = np.asarray(exp) * (sum(obs) / sum(exp))
+    assert len(obs) > 5
+    assert chisquare(obs, exp).pvalue > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# whole runs
+# ---------------------------------------------------------------------------
+
+def _check_paths(g, veh_, res, max_steps):
+    for v in range(len(veh_)):
+        L = int(res["path_len"][v])
+        if L == 0:
+            assert res["cost_ms"][v] == 2 ** 32 - 1
+            continue
+        assert L <= max_steps
+        path = res["path_edges"][v, :L].astype(np.int64)
+        tails = g.tail()[path]
+        heads = g.col[path]
+        assert tails[0] == veh_.src[v] and heads[-1] == veh_.dst[v]
+        assert np.all(tails[1:] == heads[:-1])                         # connected
+        nodes = np.concatenate([[veh_.src[v]], heads])
+        assert np.unique(nodes).shape[0] == nodes.shape[0]             # simple
+
+
+def test_route_invariants_frozen_load(orc):
+    """Loads frozen: every reported cost is the cost-table sum of its path,
+    it is never below the Dijkstra optimum, best-so-far never increases, and
+    pheromone stays within [tau_min, tau_max]."""
+    w = grid32(vehicles=24, ants=16, iterations=8)
+    g, V = w.graph, w.vehicles
+    p = dict(w.params, flags=orc.FLAG_NO_LOAD_UPDATE)
+    res = orc.route(g, V, p, want_hist=True)
+    _check_paths(g, V, res, p["max_steps"])
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    A = sp.csr_matrix((cost.astype(np.float64), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
+                      shape=(g.n, g.n))
+    opt = dijkstra(A, indices=V.src.astype(np.int64))
+    for v in range(len(V)):
+        L = int(res["path_len"][v])
+        assert L > 0
+        pc = int(cost[res["path_edges"][v, :L].astype(np.int64)].astype(np.int64).sum())
+        assert res["cost_ms"][v] == pc
+        assert pc >= opt[v, V.dst[v]] - 1e-6
+    hist = res["best_hist"].astype(np.int64)
+    assert np.all(np.diff(hist, axis=0) <= 0)
+    assert np.all(res["tau"] >= p["tau_min_q16"]) and np.all(res["tau"] <= p["tau_max_q16"])
+    assert res["load"].tolist() == g.base_load.tolist()
+
+
+def test_route_finds_optimum_on_tiny_graph(orc):
+    rng = np.random.default_rng(4)
+    g = grid_graph(3, 4, rng)
+    V = veh([0, 11, 3], [11, 0, 8])
+    p = default_params(ants=64, iterations=20, max_steps=11, flags=orc.FLAG_NO_LOAD_UPDATE, vmax_kmh=50)
+    res = orc.route(g, V, p)
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    A = sp.csr_matrix((cost.astype(np.float64), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
+                      shape=(g.n, g.n))
+    opt = dijkstra(A, indices=V.src.astype(np.int64))
+    for v in range(3):
+        assert res["cost_ms"][v] == int(opt[v, V.dst[v]])
+
+
+def test_shared_load_is_base_plus_best_route_count(orc):
+    w = grid32(vehicles=40, ants=8, iterations=6)
+    g, V, p = w.graph, w.vehicles, w.params
+    res = orc.route(g, V, p, want_hist=True)
+    _check_paths(g, V, res, p["max_steps"])
+    cnt = np.zeros(g.m, np.int64)
+    for v in range(len(V)):
+        L = int(res["path_len"][v])
+        np.add.at(cnt, res["path_edges"][v, :L].astype(np.int64), 1)
+    assert (res["load"].astype(np.int64) - g.base_load.astype(np.int64)).tolist() == cnt.tolist()
+    assert np.all(np.diff(res["best_hist"].astype(np.int64), axis=0) <= 0)
+
+
+def test_tau_constant_without_evaporation_or_deposit(orc):
+    w = grid8()
+    p = dict(w.params, rho_q16=0, q_deposit=0, iterations=5)
+    res = orc.route(w.graph, w.vehicles, p)
+    assert np.all(res["tau"] == p["tau0_q16"])
+
+
+def test_independent_vehicle_equals_alone(orc):
+    """Independent mode: a vehicle's result does not depend on the others,
+    and equals a shared-mode run of that vehicle alone with frozen loads."""
+    w = grid32(vehicles=5, ants=8, iterations=5)
+    g, V = w.graph, w.vehicles
+    p = dict(w.params, mode=orc.MODE_INDEPENDENT)
+    res = orc.route(g, V, p)
+    for v in range(len(V)):
+        one = Vehicles(qid=V.qid[v:v + 1], src=V.src[v:v + 1], dst=V.dst[v:v + 1])
+        alone = orc.route(g, one, dict(w.params, flags=orc.FLAG_NO_LOAD_UPDATE))
+        assert alone["cost_ms"][0] == res["cost_ms"][v]
+        L = int(alone["path_len"][0])
+        assert L == res["path_len"][v]
+        assert alone["path_edges"][0, :L].tolist() == res["path_edges"][v, :L].tolist()
+        assert alone["tau"].tolist() == res["tau"][v].tolist()
+
+
+def test_packed_instances_equal_separate_runs(orc):
+    rng = np.random.default_rng(9)
+    gs = [grid_graph(4, 5, rng), planar_graph(300, rng), grid_graph(6, 3, rng)]
+    packed = pack_graphs(gs)
+    off = packed.inst_node_off.astype(np.int64)
+    eoff = np.concatenate([[0], np.cumsum([x.m for x in gs])])
+    vs, q0 = [], 0
+    for i, gi in enumerate(gs):
+        vs.append(random_od(gi.n, 4, rng, qid0=q0))
+        q0 += 4
+    p = default_params(ants=8, iterations=6, max_steps=40, vmax_kmh=70)
+    allv = Vehicles(qid=np.concatenate([v.qid for v in vs]),
+                    src=np.concatenate([v.src + off[i] for i, v in enumerate(vs)]).astype(np.uint32),
+                    dst=np.concatenate([v.dst + off[i] for i, v in enumerate(vs)]).astype(np.uint32))
+    res = orc.route(packed, allv, p)
+    tot = 0
+    for i, gi in enumerate(gs):
+        r = orc.route(gi, vs[i], p)
+        tot += r["steps_total"]
+        sl = slice(4 * i, 4 * i + 4)
+        assert r["cost_ms"].tolist() == res["cost_ms"][sl].tolist()
+        assert r["path_len"].tolist() == res["path_len"][sl].tolist()
+        for v in range(4):
+            L = int(r["path_len"][v])
+            assert (r["path_edges"][v, :L].astype(np.int64) + eoff[i]).tolist() == \
+                res["path_edges"][4 * i + v, :L].tolist()
+        assert r["tau"].tolist() == res["tau"][eoff[i]:eoff[i + 1]].tolist()
+        assert r["load"].tolist() == res["load"][eoff[i]:eoff[i + 1]].tolist()
+    assert tot == res["steps_total"]
+
+
+def test_seed_and_iteration_offset_change_the_stream(orc):
+    w = grid32(vehicles=8, ants=8, iterations=3)
+    a = orc.route(w.graph, w.vehicles, w.params)
+    b = orc.route(w.graph, w.vehicles, dict(w.params, seed=2))
+    c = orc.route(w.graph, w.vehicles, dict(w.params, iter_offset=7))
+    assert a["steps_total"] != b["steps_total"] or a["path_edges"].tolist() != b["path_edges"].tolist()
+    assert a["steps_total"] != c["steps_total"] or a["path_edges"].tolist() != c["path_edges"].tolist()
+
+
+def test_parameter_checks(orc):
+    w = grid8()
+    g, V, p = w.graph, w.vehicles, w.params
+    assert orc.route_rc(g, V, p) == 0
+    for bad in (dict(ants=0), dict(max_steps=0), dict(theta=0), dict(rho_q16=65537), dict(tau_min_q16=0),
+                dict(tau0_q16=0x10, tau_min_q16=0x20), dict(tau0_q16=1 << 25), dict(mode=2)):
+        assert orc.route_rc(g, V, dict(p, **bad)) == orc.E_INVAL, bad
+    assert orc.route_rc(g, veh([5], [5]), p) == orc.E_INVAL
+    assert orc.route_rc(g, veh([5], [64]), p) == orc.E_INVAL
+    # bit budget: alpha*bits(tau_max) + 16*beta + ceil(log2(max degree)) <= 64
+    assert orc.route_rc(g, V, dict(p, beta=2, alpha=1, tau_max_q16=2 ** 30)) == orc.E_RANGE  # 31+32+2 = 65
+    assert orc.route_rc(g, V, dict(p, beta=2, alpha=1, tau_max_q16=2 ** 30 - 1)) == 0       # 30+32+2 = 64
+    assert orc.route_rc(g, V, dict(p, beta=3, alpha=1, tau_max_q16=2 ** 24)) == orc.E_RANGE  # 25+48+2 = 75
+    assert orc.route_rc(g, V, dict(p, q_deposit=2 ** 62)) == orc.E_RANGE
