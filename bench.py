@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Throughput of the GMACO-P routing hot path on one MI355X.
+
+One step = one gmacop_route_batch call over the whole workload: every
+iteration's cost table, ant walks, best-route reduction, deposit,
+evaporation and load update.  Default workload: 32x32 grid city (1024
+intersections, 3770 roads), 256 vehicles x 128 ants x 100 iterations,
+shared pheromone and loads.  Queries and result buffers are resident in
+device memory before the timed region starts.
+
+Prints one JSON line: ant edge-selections per second (every roulette choice
+an ant makes), the walk kernel's position against HBM bandwidth, per-step
+latency percentiles, and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of the walk kernel (what one lane must read or write):
+#   per selection: row_ptr[u], row_ptr[u+1] (8 B) + path entry written (4 B)
+#   per candidate road examined: col, tau, cost (12 B) + head x, y (8 B)
+#   per road an arriving ant deposits on: path entry re-read (4 B) + 64-bit atomic add (8 B)
+BYTES_PER_SELECTION = 12
+BYTES_PER_CANDIDATE = 20
+BYTES_PER_DEPOSIT_ROAD = 12
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def make_workload(name):
+    import workloads
+    table = {"grid8": workloads.grid8, "grid32": workloads.grid32, "planar100k": workloads.planar100k,
+             "multicity": workloads.multi_city}
+    return table[name]()
+
+
+def cpu_baseline(w, iterations):
+    """The oracle, as is, on the same graph and vehicles with fewer iterations."""
+    import oracle
+    oracle.build(force=False)
+    p = dict(w.params, iterations=iterations)
+    t = time.perf_counter()
+    r = oracle.route(w.graph, w.vehicles, p, want_state=False)
+    dt = time.perf_counter() - t
+    return {"value": r["steps_total"] / dt, "unit": "edge-selections/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name} with {iterations} of {w.params['iterations']} iterations "
+                      f"({r['steps_total']} selections in {dt:.1f} s, single thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="grid32", choices=["grid8", "grid32", "planar100k", "multicity"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iterations", type=int, default=25)
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="do not bracket kernels with HIP events (roofline fields become null)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_14244_amd import gmacop
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
+    w = make_workload(args.workload)
+    g, V, p = w.graph, w.vehicles, dict(w.params)
+    G = gmacop.gmacop_graph_create(g)
+    b = gmacop.DeviceBatch(V, p["max_steps"])
+    stream = torch.cuda.current_stream().cuda_stream
+    flags_timed = p["flags"] | (0 if args.no_kernel_timing else gmacop.TIME_KERNELS)
+
+    print(f"[bench] {w.name}: n={g.n} m={g.m} vehicles={len(V)} warmup={args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        gmacop.gmacop_route_batch_device(G, b, p, stream)
+    torch.cuda.synchronize()
+    gmacop.gmacop_stats_get(G, reset=True)
+
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        gmacop.gmacop_route_batch_device(G, b, dict(p, flags=flags_timed), stream)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        print(f"[bench] step {i}: {lat[-1] * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st = gmacop.gmacop_stats_get(G)
+    res = b.result()
+    sel = st["selections"]
+    assert sel == res["steps_total"] * args.steps, (sel, res["steps_total"])
+
+    roofline = None
+    if not args.no_kernel_timing and st["launches"]["walk"]:
+        nl = st["launches"]["walk"]
+        walk_ms = st["ms"]["walk"] / nl
+        bytes_per_launch = (BYTES_PER_SELECTION * sel + BYTES_PER_CANDIDATE * st["candidates"] +
+                            BYTES_PER_DEPOSIT_ROAD * st["deposit_roads"]) / nl
+        achieved = bytes_per_launch / (walk_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "k_walk", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                    "avg_launch_ms": round(walk_ms, 5), "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                    "selections_per_launch": sel / nl, "mean_candidates_per_selection": st["candidates"] / sel}
+        tot = sum(st["ms"].values())
+        print("[bench] kernel time per step: " + ", ".join(
+            f"{k} {st['ms'][k] / args.steps:.3f} ms ({st['launches'][k] // args.steps}x)" for k in st["ms"]) +
+              f"; kernels {tot / args.steps:.3f} ms of {elapsed / args.steps * 1e3:.3f} ms", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "ant edge-selections/sec",
+        "value": sel / elapsed,
+        "unit": "edge-selections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nodes": g.n, "roads": g.m, "vehicles": len(V), "ants": p["ants"],
+                   "iterations": p["iterations"], "mode": "shared", "selections_per_step": sel // args.steps,
+                   "arrivals_per_step": st["arrivals"] // args.steps},
+        "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3},
+        "roofline": roofline,
+    }
+    gmacop.gmacop_release(G)
+    if not args.no_cpu:
+        print(f"[bench] timing the CPU oracle on {args.cpu_iterations} iterations", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iterations)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

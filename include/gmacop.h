@@ -1,0 +1,169 @@
+/*
+ * gmacop.h -- C ABI of the GMACO-P routing library for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Jindal & Bedi, "GMACO-P: GPU assisted Preemptive MACO algorithm
+ * for enabling Smart Transportation" (arXiv 2010.14244).  The library runs
+ * the data-parallel core of the method on one GPU: ant route construction
+ * for every vehicle over a road graph (Section 4.1 Fig. 3 vehicle loop;
+ * Section 4.2 Alg. 2 steps 4-6, Adj_Neigh / Eval_Rout), the preemptive
+ * signal and congestion cost of every road (Alg. 2 steps 7-8, Calc_Dens /
+ * Comp_Thres), and the pheromone and road-load update (Alg. 2 steps 9-10,
+ * Updt_Pher / Evap_Pher; Fig. 3 "Ph_road++").  The three calls mirror the
+ * host driver of Alg. 1 (allocate and copy in, launch, copy out, free),
+ * except that the graph stays resident on the device between calls.
+ *
+ * Everything crossing this interface is an integer: times in milliseconds,
+ * lengths in decimetres, speeds in km/h, pheromone in Q16.16 (65536 = 1.0).
+ * Results are deterministic and identical on every run for the same inputs.
+ *
+ * Return codes: GMACOP_OK (0) or a negative GMACOP_E_* value.  A failed call
+ * changes no state; gmacop_last_error() describes the last failure of the
+ * calling thread.  "No route found" for a vehicle is a result, not an error.
+ */
+#ifndef GMACOP_H
+#define GMACOP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GMACOP_OK            0
+#define GMACOP_E_INVAL      -1   /* malformed graph, query or parameter            */
+#define GMACOP_E_RANGE      -2   /* parameters exceed the exact 64-bit integer range */
+#define GMACOP_E_NOMEM      -3   /* device allocation failed                        */
+#define GMACOP_E_DEVICE     -4   /* HIP runtime error                               */
+#define GMACOP_E_UNSUPPORTED -5  /* valid input outside what this build handles      */
+
+/* gmacop_params.mode */
+#define GMACOP_MODE_SHARED      0u  /* all vehicles share pheromone and road loads      */
+#define GMACOP_MODE_INDEPENDENT 1u  /* private pheromone per vehicle, loads frozen      */
+
+/* gmacop_params.flags */
+#define GMACOP_NO_LOAD_UPDATE  1u   /* shared mode: keep loads at base_load             */
+#define GMACOP_DEVICE_PTRS     2u   /* queries and result buffers are device pointers;
+                                       the call returns without synchronising          */
+#define GMACOP_TIME_KERNELS    4u   /* record a HIP event pair around every kernel
+                                       launch, summed by gmacop_stats_get              */
+
+/* Opaque handle: the graph, its static per-road data and the pheromone / load
+ * state on the device.  Owns all of its device memory. */
+typedef struct gmacop_graph gmacop_graph;
+
+/* Road network G(N, E) (Fig. 3) in CSR form.  All pointers are host memory,
+ * read during gmacop_graph_create only (deep copy); the caller keeps them. */
+typedef struct {
+    uint32_t n_nodes;            /* n >= 2                                                   */
+    uint32_t n_edges;            /* m >= 1                                                   */
+    const uint32_t *row_ptr;     /* [n+1] out-roads of u are row_ptr[u] .. row_ptr[u+1]-1;
+                                    row_ptr[0] = 0, non-decreasing, row_ptr[n] = m           */
+    const uint32_t *col;         /* [m] head node of each road, < n, no self-loops           */
+    const uint32_t *len_dm;      /* [m] length in decimetres, >= 1                           */
+    const uint16_t *speed_kmh;   /* [m] free-flow speed, >= 1                                */
+    const uint16_t *green_pm;    /* [m] green share of road e as an approach of its head
+                                    node, per mille, <= 1000                                 */
+    const uint32_t *cycle_ms;    /* [n] signal cycle of the node, 0 = no signal              */
+    const int32_t *x_dm;         /* [n] planar coordinates, |x|, |y| < 2^30                  */
+    const int32_t *y_dm;         /* [n]                                                      */
+    const uint32_t *base_load;   /* [m] sensed vehicles on each road (Section 4.2: vehicle
+                                    density from road sensors)                               */
+    uint32_t n_instances;        /* number of disjoint cities packed in the CSR, >= 1        */
+    const uint32_t *inst_node_off; /* [n_instances+1] node range of each city, or NULL when
+                                    n_instances == 1; no road may cross two ranges           */
+} gmacop_graph_desc;
+
+/* One vehicle (Fig. 3: veh_i.present, veh_i.destin).  qid names the
+ * vehicle's random stream: the same qid gives the same draws wherever the
+ * vehicle sits in a batch.  qid 0xFFFFFFFF is reserved. */
+typedef struct {
+    uint32_t qid, src, dst;
+} gmacop_od;
+
+typedef struct {
+    uint32_t ants;          /* ants per vehicle per iteration, >= 1                         */
+    uint32_t iterations;    /* >= 0                                                         */
+    uint32_t alpha, beta;   /* integer exponents of pheromone and heuristic                 */
+    uint32_t max_steps;     /* roads an ant may take before it gives up, >= 1              */
+    uint32_t rho_q16;       /* evaporation, Q16 (32768 = 0.5), <= 65536                     */
+    uint32_t tau0_q16;      /* initial pheromone, tau_min <= tau0 <= tau_max                */
+    uint32_t tau_min_q16;   /* >= 1                                                         */
+    uint32_t tau_max_q16;
+    uint64_t q_deposit;     /* deposit numerator, Q16.16 x ms: an ant with path cost c
+                               deposits floor(q_deposit / c) on each road of its path       */
+    uint32_t theta;         /* congestion threshold (Fig. 3 "N_t > threshold"), >= 1        */
+    uint32_t th_max;        /* queue above which an approach takes the green (Fig. 3 Th_max) */
+    uint32_t t_max_ms;      /* longest signal wait (Fig. 3 T_max)                           */
+    uint32_t vmax_kmh;      /* speed of the straight-line goal term, 0 = off; at least the
+                               fastest road speed keeps the term a lower bound              */
+    uint32_t mode;          /* GMACOP_MODE_*                                                */
+    uint32_t flags;         /* GMACOP_* flags                                               */
+    uint64_t seed;          /* Philox key                                                   */
+    uint32_t iter_offset;   /* added to the iteration number in every random counter       */
+} gmacop_params;
+
+/* Caller-owned outputs (host memory, or device memory with GMACOP_DEVICE_PTRS). */
+typedef struct {
+    uint32_t *path_edges;   /* [nq * max_steps] best route of vehicle i in row i, as road
+                               ids; entries past path_len[i] are unspecified               */
+    uint32_t *path_len;     /* [nq] roads on the best route, 0 = no route found            */
+    uint32_t *cost_ms;      /* [nq] cost of the best route as found, 0xFFFFFFFF = none      */
+    uint64_t *steps_total;  /* [1] roulette selections executed by all ants                 */
+} gmacop_result;
+
+/* Build the device-resident graph (Alg. 1 steps 1-2).  Validates the CSR and
+ * attributes (GMACOP_E_INVAL), copies everything to the current HIP device
+ * and derives each road's free-flow time and fixed-time signal wait on the
+ * device.  On success *out owns the graph; on failure *out is NULL. */
+int gmacop_graph_create(const gmacop_graph_desc *desc, gmacop_graph **out);
+
+/* Route nq vehicles (Alg. 1 step 3 and Alg. 2, iterated params->iterations
+ * times).  Work is ordered on hip_stream (a hipStream_t; NULL = the null
+ * stream).  Pheromone starts at tau0 and road loads at base_load on every
+ * call.  Without GMACOP_DEVICE_PTRS, q and out are host memory and the call
+ * returns once the results are in them (Alg. 1 step 4).  With it, q and out
+ * are device memory, the call only enqueues, and the caller synchronises the
+ * stream before reading; q must stay valid until then.
+ * Errors: GMACOP_E_INVAL (src/dst out of range, src == dst, src and dst in
+ * different cities, reserved qid, a parameter outside its documented range),
+ * GMACOP_E_RANGE (alpha*bits(tau_max) + 16*beta + ceil(log2(max out-degree))
+ * > 64, or the deposit total could reach 2^63), GMACOP_E_UNSUPPORTED (a node
+ * with more than 32 out-roads), GMACOP_E_NOMEM, GMACOP_E_DEVICE.
+ * One call at a time per graph handle. */
+int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
+                       gmacop_result *out, void *hip_stream);
+
+/* Shared-mode state after the last gmacop_route_batch on this graph: the
+ * pheromone and road load of every road (host arrays of n_edges entries,
+ * either may be NULL).  Synchronises hip_stream. */
+int gmacop_state_get(gmacop_graph *g, uint32_t *tau_q16, uint32_t *load, void *hip_stream);
+
+/* Work counters and kernel times accumulated over gmacop_route_batch calls
+ * since the last reset.  Kernel index: 0 = walk (tour construction and
+ * deposit), 1 = best-route reduction, 2 = pheromone/load update, 3 = signal
+ * and cost table.  ms[] is filled only for calls made with
+ * GMACOP_TIME_KERNELS (times from HIP events on the call's stream). */
+typedef struct {
+    uint64_t launches[4];
+    double ms[4];
+    uint64_t selections;     /* roulette selections (one per road an ant takes)       */
+    uint64_t candidates;     /* out-roads examined at those selections                */
+    uint64_t arrivals;       /* ants that reached their destination                   */
+    uint64_t deposit_roads;  /* roads deposited on by arriving ants                   */
+} gmacop_stats;
+
+/* Copy the counters into *s (synchronises hip_stream); reset them when reset
+ * is non-zero. */
+int gmacop_stats_get(gmacop_graph *g, gmacop_stats *s, int reset, void *hip_stream);
+
+/* Free the graph and all of its device memory (Alg. 1 step 5).  NULL-safe. */
+void gmacop_release(gmacop_graph *g);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *gmacop_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMACOP_H */

@@ -1,0 +1,877 @@
+// gmacop.hip -- GMACO-P routing hot path for AMD Instinct MI355X (gfx950).
+//
+// Method: Jindal & Bedi, "GMACO-P: GPU assisted Preemptive MACO algorithm for
+// enabling Smart Transportation" (arXiv 2010.14244), Section 4.1 (Fig. 3,
+// MACO-P vehicle loop) and Section 4.2 (Alg. 1 host driver, Alg. 2 kernel
+// steps).  One iteration of the method is four kernels on one stream:
+//
+//   k_walk  one lane per ant: candidate roads of the current node (Adj_Neigh),
+//           weight tau^alpha * eta^beta with eta from the road cost and the
+//           straight-line goal term (Calc_Dist, Eval_Rout), Philox4x32-10
+//           draw, roulette pick; on arrival the ant deposits on its path
+//           (Updt_Pher) and offers its (cost, ant) key to its vehicle.
+//   k_best  one wave per vehicle: iteration-best ant replaces the vehicle's
+//           best route when strictly cheaper; road use counts for the load.
+//   k_edge  one lane per road: evaporate + congestion-penalised deposit +
+//           clamp (Evap_Pher), new load = sensed load + routed vehicles.
+//   k_cost  one lane per intersection: the preemptive signal rule over its
+//           approaches (Calc_Dens, Comp_Thres) and the cost of every
+//           approach road for the next iteration.
+//
+// All arithmetic is integer with explicitly stated floors, so results do not
+// depend on thread scheduling: deposits and load counts are integer atomic
+// sums, the best ant is an atomic minimum of a packed (cost, ant) key.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gmacop.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+
+thread_local std::string t_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(GMACOP_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr uint32_t kNoCost = 0xFFFFFFFFu;
+constexpr uint32_t kPathCostCap = 0xFFFFFFFEu;
+constexpr uint32_t kRoadCostCap = 1u << 31;
+constexpr uint64_t kNoKey = ~0ull;
+constexpr int kWave = 64;
+constexpr uint32_t kMaxDegree = 32;
+constexpr uint32_t kLdsBitsetMaxNodes = 4096;   // 512 B of visited bits per ant in LDS
+
+// ---------------------------------------------------------------------------
+// device arithmetic
+// ---------------------------------------------------------------------------
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies, the key advanced by the Weyl constants between rounds.  Returns
+// (x1 << 32) | x0 of the output block.
+__device__ __forceinline__ uint64_t philox_u64(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return ((uint64_t)c1 << 32) | c0;
+}
+
+// floor(sqrt(x)) for x < 2^63: double-precision estimate, then exact
+// correction so that s*s <= x < (s+1)*(s+1).
+__device__ __forceinline__ uint64_t isqrt_u64(uint64_t x)
+{
+    uint64_t s = (uint64_t)sqrt((double)x);
+    while (s * s > x) --s;
+    while ((s + 1) * (s + 1) <= x) ++s;
+    return s;
+}
+
+// Straight-line time-to-go from (x, y) to the destination at vmax:
+// floor(isqrt(dx^2 + dy^2) * kgoal / 2^16), kgoal = floor(360 * 2^16 / vmax).
+__device__ __forceinline__ int64_t goal_ms(int32_t x, int32_t y, int32_t dx, int32_t dy, uint32_t kgoal)
+{
+    if (kgoal == 0) return 0;
+    const int64_t ex = (int64_t)x - dx, ey = (int64_t)y - dy;
+    const uint64_t d2 = (uint64_t)(ex * ex) + (uint64_t)(ey * ey);
+    return (int64_t)((isqrt_u64(d2) * kgoal) >> 16);
+}
+
+// eta = clamp(floor(2^26 / max(delta, 1)), 1, 65535).
+__device__ __forceinline__ uint32_t eta_of(int64_t delta)
+{
+    if (delta >= (int64_t(1) << 26)) return 1;
+    if (delta <= 1024) return 65535;
+    return (1u << 26) / (uint32_t)delta;
+}
+
+__device__ __forceinline__ uint64_t ipow_u64(uint64_t b, uint32_t e)
+{
+    uint64_t r = 1;
+    for (uint32_t i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+struct EdgeInitArgs {
+    uint32_t m, tau0, t_max;
+    const uint32_t *col, *len_dm, *cycle, *base_load;
+    const uint16_t *speed, *green;
+    uint32_t *t0, *wf, *tau, *load, *cnt;
+    uint64_t *dep;
+};
+
+// Per road: free-flow time t0 = floor(len * 360 / speed) in [1, 2^31];
+// fixed-time wait at the head signal wf = min(T_max, floor(red^2 / (2C)))
+// with red = floor(C * (1000 - green) / 1000); fresh pheromone and load.
+__global__ void k_init_edges(EdgeInitArgs a)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.m) return;
+    uint64_t t = (uint64_t)a.len_dm[e] * 360u / a.speed[e];
+    t = t < 1 ? 1 : (t > kRoadCostCap ? kRoadCostCap : t);
+    a.t0[e] = (uint32_t)t;
+    const uint64_t C = a.cycle[a.col[e]];
+    uint64_t w = 0;
+    if (C) {
+        const uint64_t red = C * (1000u - a.green[e]) / 1000u;
+        w = red * red / (2 * C);
+        if (w > a.t_max) w = a.t_max;
+    }
+    a.wf[e] = (uint32_t)w;
+    a.tau[e] = a.tau0;
+    a.load[e] = a.base_load[e];
+    a.dep[e] = 0;
+    a.cnt[e] = 0;
+}
+
+__global__ void k_init_vehicles(uint32_t nq, uint32_t *best_len, uint32_t *best_cost, uint64_t *iter_key,
+                                uint64_t *steps)
+{
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0) *steps = 0;
+    if (v >= nq) return;
+    best_len[v] = 0;
+    best_cost[v] = kNoCost;
+    iter_key[v] = kNoKey;
+}
+
+struct CostArgs {
+    uint32_t n, theta, th_max;
+    const uint32_t *rev_ptr, *rev_edge, *cycle, *load, *t0, *wf;
+    uint32_t *cost;
+};
+
+// Per intersection v: the approach (incoming road) with the longest
+// non-empty queue takes the green, ties to the lowest road id; so does any
+// approach whose queue exceeds Th_max.  Road cost = congestion-scaled travel
+// time (t0 while load <= theta, else floor(t0 * load / theta)) + the fixed
+// wait unless the approach has green; capped at 2^31.
+__global__ void k_cost(CostArgs a)
+{
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.n) return;
+    const uint32_t rb = a.rev_ptr[v], re = a.rev_ptr[v + 1];
+    const bool signal = a.cycle[v] != 0;
+    uint64_t best = 0;
+    for (uint32_t i = rb; i < re; ++i) {
+        const uint32_t e = a.rev_edge[i];
+        const uint32_t L = a.load[e];
+        const uint64_t key = L ? (((uint64_t)L << 32) | (0xFFFFFFFFu - e)) : 0;
+        best = key > best ? key : best;
+    }
+    for (uint32_t i = rb; i < re; ++i) {
+        const uint32_t e = a.rev_edge[i];
+        const uint32_t L = a.load[e];
+        const uint64_t key = L ? (((uint64_t)L << 32) | (0xFFFFFFFFu - e)) : 0;
+        const bool green = signal && L && (L > a.th_max || key == best);
+        const uint32_t t0 = a.t0[e];
+        const uint64_t travel = L <= a.theta ? t0 : (uint64_t)t0 * L / a.theta;
+        uint64_t c = travel + (green ? 0u : a.wf[e]);
+        a.cost[e] = (uint32_t)(c > kRoadCostCap ? kRoadCostCap : c);
+    }
+}
+
+struct WalkArgs {
+    const uint32_t *row_ptr, *col, *cost, *tau;
+    const int32_t *x, *y;
+    const gmacop_od *od;
+    uint32_t n, nq, ants, max_steps, alpha, beta, kgoal, nwords;
+    uint32_t seed_lo, seed_hi, iter;
+    uint64_t q_deposit;
+    uint32_t *path;        // [max_steps][NA], step-major
+    uint32_t *ant_len;     // [NA]
+    uint32_t *ant_cost;    // [NA], kNoCost when the ant failed
+    uint32_t *gbits;       // [NA][nwords] visited bits when not in LDS
+    uint64_t *dep;         // [m]
+    uint64_t *iter_key;    // [nq]
+    uint64_t *steps;       // [1] selections of this call
+    uint64_t *counters;    // [4] cumulative: selections, candidates examined, arrivals, roads deposited on
+};
+
+// One lane per ant (vehicle v = a / ants, ant k = a % ants).  Visited nodes
+// live in a per-ant bitset: in LDS, interleaved by lane so that each lane
+// stays in its own bank, or in global memory for large graphs (cleared again
+// from the path at the end of the walk).
+template <int MAXD, bool LDS_BITS>
+__global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
+{
+    extern __shared__ uint32_t s_bits[];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t NA = a.nq * a.ants;
+    const uint32_t ant = blockIdx.x * kWave + lane;
+    const bool active = ant < NA;
+    const uint32_t v = active ? ant / a.ants : 0;
+    const uint32_t k = active ? ant % a.ants : 0;
+    gmacop_od q = {0, 0, 0};
+    if (active) q = a.od[v];
+    const bool valid = active && q.src < a.n && q.dst < a.n && q.src != q.dst;
+
+    uint32_t *gb = nullptr;
+    if (LDS_BITS) {
+        for (uint32_t w = 0; w < a.nwords; ++w) s_bits[w * kWave + lane] = 0;
+    } else if (valid) {
+        gb = a.gbits + (size_t)ant * a.nwords;
+    }
+    auto bits_word = [&](uint32_t node) -> uint32_t & {
+        return LDS_BITS ? s_bits[(node >> 5) * kWave + lane] : gb[node >> 5];
+    };
+
+    uint32_t s = 0, ncand = 0, arrived = 0;
+    if (valid) {
+        const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
+        uint32_t u = q.src, cs = 0;
+        bool ok = false;
+        bits_word(u) |= 1u << (u & 31);
+        int64_t hu = goal_ms(a.x[u], a.y[u], dx, dy, a.kgoal);
+        while (s < a.max_steps) {
+            const uint32_t rs = a.row_ptr[u];
+            const uint32_t d = a.row_ptr[u + 1] - rs;
+            ncand += d;
+            uint64_t w[MAXD];
+            int64_t hx[MAXD];
+            uint32_t cx[MAXD], xx[MAXD];
+            uint64_t T = 0;
+#pragma unroll
+            for (int j = 0; j < MAXD; ++j) {
+                w[j] = 0;
+                hx[j] = 0;
+                cx[j] = 0;
+                xx[j] = 0;
+                if ((uint32_t)j < d) {
+                    const uint32_t e = rs + j;
+                    const uint32_t x = a.col[e];
+                    xx[j] = x;
+                    if (!((bits_word(x) >> (x & 31)) & 1u)) {
+                        const uint32_t c = a.cost[e];
+                        const int64_t h = goal_ms(a.x[x], a.y[x], dx, dy, a.kgoal);
+                        const uint32_t eta = eta_of((int64_t)c + h - hu);
+                        w[j] = ipow_u64(a.tau[e], a.alpha) * ipow_u64(eta, a.beta);
+                        hx[j] = h;
+                        cx[j] = c;
+                    }
+                }
+                T += w[j];
+            }
+            if (T == 0) break;   // dead end
+            const uint64_t r = philox_u64(q.qid, k, a.iter, s, a.seed_lo, a.seed_hi);
+            const uint64_t target = __umul64hi(r, T);
+            uint64_t prefix = 0;
+            uint32_t jsel = 0, xsel = 0, csel = 0;
+            int64_t hsel = 0;
+            bool found = false;
+#pragma unroll
+            for (int j = 0; j < MAXD; ++j) {
+                prefix += w[j];
+                const bool take = !found && prefix > target;
+                jsel = take ? (uint32_t)j : jsel;
+                xsel = take ? xx[j] : xsel;
+                csel = take ? cx[j] : csel;
+                hsel = take ? hx[j] : hsel;
+                found = found || take;
+            }
+            a.path[(size_t)s * NA + ant] = rs + jsel;
+            ++s;
+            const uint64_t c2 = (uint64_t)cs + csel;
+            cs = c2 > kPathCostCap ? kPathCostCap : (uint32_t)c2;
+            u = xsel;
+            bits_word(u) |= 1u << (u & 31);
+            hu = hsel;
+            if (u == q.dst) {
+                ok = true;
+                break;
+            }
+        }
+        a.ant_len[ant] = s;
+        a.ant_cost[ant] = ok ? cs : kNoCost;
+        if (ok) {
+            arrived = 1;
+            const uint64_t dpos = a.q_deposit / cs;
+            if (dpos)
+                for (uint32_t i = 0; i < s; ++i) atomicAdd((unsigned long long *)&a.dep[a.path[(size_t)i * NA + ant]],
+                                                           (unsigned long long)dpos);
+            atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
+        }
+        if (!LDS_BITS) {
+            gb[q.src >> 5] = 0;
+            for (uint32_t i = 0; i < s; ++i) gb[a.col[a.path[(size_t)i * NA + ant]] >> 5] = 0;
+        }
+    } else if (active) {
+        a.ant_len[ant] = 0;
+        a.ant_cost[ant] = kNoCost;
+    }
+    // one atomic per wave for each counter
+    uint64_t cnt = s, cand = ncand, arr = arrived, dh = arrived ? s : 0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off);
+        cand += __shfl_xor(cand, off);
+        arr += __shfl_xor(arr, off);
+        dh += __shfl_xor(dh, off);
+    }
+    if (lane == 0 && cnt) {
+        atomicAdd((unsigned long long *)a.steps, (unsigned long long)cnt);
+        atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)cnt);
+        atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)cand);
+        atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)arr);
+        atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)dh);
+    }
+}
+
+struct BestArgs {
+    uint32_t nq, ants, max_steps, load_update;
+    const uint32_t *path, *ant_len;
+    uint64_t *iter_key;
+    uint32_t *best_path, *best_len, *best_cost;
+    uint32_t *cnt;
+};
+
+// One wave per vehicle: the iteration-best ant (smallest packed key) replaces
+// the best route when its cost is strictly lower; every road of the current
+// best route adds one to its count for the load update.
+__global__ __launch_bounds__(kWave) void k_best(BestArgs a)
+{
+    const uint32_t v = blockIdx.x, lane = threadIdx.x;
+    if (v >= a.nq) return;
+    const uint32_t NA = a.nq * a.ants;
+    const uint64_t key = a.iter_key[v];
+    const uint32_t bc = a.best_cost[v];
+    const bool improve = key != kNoKey && (uint32_t)(key >> 32) < bc;
+    const uint32_t ant = improve ? v * a.ants + (uint32_t)(key & 0xFFFFFFFFu) : 0;
+    const uint32_t len = improve ? a.ant_len[ant] : a.best_len[v];
+    uint32_t *bp = a.best_path + (size_t)v * a.max_steps;
+    for (uint32_t s = lane; s < len; s += kWave) {
+        const uint32_t e = improve ? a.path[(size_t)s * NA + ant] : bp[s];
+        if (improve) bp[s] = e;
+        if (a.load_update) atomicAdd(&a.cnt[e], 1u);
+    }
+    if (lane == 0) {
+        if (improve) {
+            a.best_cost[v] = (uint32_t)(key >> 32);
+            a.best_len[v] = len;
+        }
+        a.iter_key[v] = kNoKey;
+    }
+}
+
+struct EdgeArgs {
+    uint32_t m, rho, tau_min, tau_max, theta, load_update;
+    uint32_t *tau, *load, *cnt;
+    const uint32_t *base_load;
+    uint64_t *dep;
+};
+
+// Per road: tau <- clamp(floor(tau * (65536 - rho) / 65536) + Dp), with the
+// deposit D scaled by theta / load on a congested road, floor(D * theta / L)
+// computed exactly as (D / L) * theta + ((D % L) * theta) / L.  Then the load
+// becomes the sensed load plus the vehicles whose best route uses the road.
+__global__ void k_edge(EdgeArgs a)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.m) return;
+    const uint64_t D = a.dep[e];
+    const uint32_t L = a.load[e];
+    uint64_t dp = D;
+    if (L > a.theta) dp = (D / L) * a.theta + ((D % L) * a.theta) / L;
+    uint64_t t = (((uint64_t)a.tau[e] * (65536u - a.rho)) >> 16) + dp;
+    t = t < a.tau_min ? a.tau_min : (t > a.tau_max ? a.tau_max : t);
+    a.tau[e] = (uint32_t)t;
+    a.dep[e] = 0;
+    if (a.load_update) {
+        a.load[e] = a.base_load[e] + a.cnt[e];
+        a.cnt[e] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+template <typename T>
+int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(GMACOP_E_NOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    return GMACOP_OK;
+}
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+uint32_t bit_length(uint64_t x)
+{
+    uint32_t b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+unsigned blocks_for(uint64_t work, unsigned per_block)
+{
+    return (unsigned)((work + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+struct gmacop_graph {
+    int device = 0;
+    uint32_t n = 0, m = 0, n_inst = 1, max_deg = 0;
+    std::vector<uint32_t> inst_off;    // host copy, [n_inst+1]
+    // static graph (device)
+    uint32_t *row_ptr = nullptr, *col = nullptr, *len_dm = nullptr, *cycle = nullptr, *base_load = nullptr;
+    uint32_t *rev_ptr = nullptr, *rev_edge = nullptr;
+    uint16_t *speed = nullptr, *green = nullptr;
+    int32_t *x = nullptr, *y = nullptr;
+    // per-call state (device)
+    uint32_t *t0 = nullptr, *wf = nullptr, *tau = nullptr, *load = nullptr, *cost = nullptr, *cnt = nullptr;
+    uint64_t *dep = nullptr;
+    // workspace, grown on demand
+    size_t cap_path = 0, cap_ants = 0, cap_veh = 0, cap_best = 0, cap_bits = 0;
+    uint32_t *path = nullptr, *ant_len = nullptr, *ant_cost = nullptr, *gbits = nullptr;
+    uint64_t *iter_key = nullptr, *steps = nullptr;
+    uint32_t *best_path = nullptr, *best_len = nullptr, *best_cost = nullptr;
+    gmacop_od *od = nullptr;
+    // statistics
+    uint64_t *counters = nullptr;         // device [4]
+    uint64_t launches[4] = {0, 0, 0, 0};
+    double ms[4] = {0, 0, 0, 0};
+    struct Timed { hipEvent_t a, b; int kernel; };
+    std::vector<Timed> pending;           // recorded, not yet summed
+    std::vector<hipEvent_t> spare;
+
+    ~gmacop_graph()
+    {
+        (void)hipSetDevice(device);
+        dfree(row_ptr); dfree(col); dfree(len_dm); dfree(cycle); dfree(base_load);
+        dfree(rev_ptr); dfree(rev_edge); dfree(speed); dfree(green); dfree(x); dfree(y);
+        dfree(t0); dfree(wf); dfree(tau); dfree(load); dfree(cost); dfree(cnt); dfree(dep);
+        dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_key); dfree(steps);
+        dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters);
+        for (auto &t : pending) {
+            (void)hipEventDestroy(t.a);
+            (void)hipEventDestroy(t.b);
+        }
+        for (auto e : spare) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+template <typename T>
+int upload(T **dst, const T *src, size_t count)
+{
+    int rc = dalloc(dst, count);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return GMACOP_OK;
+}
+
+// Grow a workspace buffer to at least `need` elements (contents discarded).
+template <typename T>
+int grow(T **p, size_t *cap, size_t need, bool zero)
+{
+    if (need <= *cap && *p) return GMACOP_OK;
+    dfree(*p);
+    *cap = 0;
+    int rc = dalloc(p, need);
+    if (rc) return rc;
+    if (zero) HIP_TRY(hipMemset(*p, 0, need * sizeof(T)));
+    *cap = need;
+    return GMACOP_OK;
+}
+
+int validate_desc(const gmacop_graph_desc *d)
+{
+    if (!d) return fail(GMACOP_E_INVAL, "desc is NULL");
+    if (d->n_nodes < 2 || d->n_edges < 1) return fail(GMACOP_E_INVAL, "need n >= 2 and m >= 1");
+    if (!d->row_ptr || !d->col || !d->len_dm || !d->speed_kmh || !d->green_pm || !d->cycle_ms || !d->x_dm ||
+        !d->y_dm || !d->base_load)
+        return fail(GMACOP_E_INVAL, "a graph array is NULL");
+    const uint32_t n = d->n_nodes, m = d->n_edges;
+    if (d->row_ptr[0] != 0 || d->row_ptr[n] != m) return fail(GMACOP_E_INVAL, "row_ptr must run from 0 to m");
+    for (uint32_t u = 0; u < n; ++u) {
+        if (d->row_ptr[u + 1] < d->row_ptr[u]) return fail(GMACOP_E_INVAL, "row_ptr decreases at node %u", u);
+        for (uint32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; ++e) {
+            if (d->col[e] >= n) return fail(GMACOP_E_INVAL, "col[%u] out of range", e);
+            if (d->col[e] == u) return fail(GMACOP_E_INVAL, "self-loop at road %u", e);
+        }
+    }
+    for (uint32_t e = 0; e < m; ++e) {
+        if (d->len_dm[e] == 0) return fail(GMACOP_E_INVAL, "len_dm[%u] is 0", e);
+        if (d->speed_kmh[e] == 0) return fail(GMACOP_E_INVAL, "speed_kmh[%u] is 0", e);
+        if (d->green_pm[e] > 1000) return fail(GMACOP_E_INVAL, "green_pm[%u] > 1000", e);
+    }
+    const int32_t lim = 1 << 30;
+    for (uint32_t v = 0; v < n; ++v)
+        if (d->x_dm[v] <= -lim || d->x_dm[v] >= lim || d->y_dm[v] <= -lim || d->y_dm[v] >= lim)
+            return fail(GMACOP_E_INVAL, "coordinates of node %u out of range", v);
+    if (d->n_instances == 0) return fail(GMACOP_E_INVAL, "n_instances must be >= 1");
+    if (d->n_instances > 1 && !d->inst_node_off) return fail(GMACOP_E_INVAL, "inst_node_off is NULL");
+    if (d->inst_node_off) {
+        const uint32_t *o = d->inst_node_off;
+        if (o[0] != 0 || o[d->n_instances] != n) return fail(GMACOP_E_INVAL, "inst_node_off must run from 0 to n");
+        for (uint32_t i = 0; i < d->n_instances; ++i) {
+            if (o[i + 1] <= o[i]) return fail(GMACOP_E_INVAL, "empty or decreasing instance %u", i);
+            for (uint32_t u = o[i]; u < o[i + 1]; ++u)
+                for (uint32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; ++e)
+                    if (d->col[e] < o[i] || d->col[e] >= o[i + 1])
+                        return fail(GMACOP_E_INVAL, "road %u crosses instances", e);
+        }
+    }
+    return GMACOP_OK;
+}
+
+uint32_t instance_of(const gmacop_graph *g, uint32_t node)
+{
+    return (uint32_t)(std::upper_bound(g->inst_off.begin(), g->inst_off.end(), node) - g->inst_off.begin()) - 1;
+}
+
+int take_event(gmacop_graph *g, hipEvent_t *e)
+{
+    if (!g->spare.empty()) {
+        *e = g->spare.back();
+        g->spare.pop_back();
+        return GMACOP_OK;
+    }
+    HIP_TRY(hipEventCreate(e));
+    return GMACOP_OK;
+}
+
+// Brackets one kernel launch with an event pair when timing is on.
+struct KernelTimer {
+    gmacop_graph *g;
+    hipStream_t st;
+    bool on;
+    int start(int kernel, gmacop_graph::Timed *t)
+    {
+        g->launches[kernel]++;
+        if (!on) return GMACOP_OK;
+        t->kernel = kernel;
+        int rc = take_event(g, &t->a);
+        if (rc || (rc = take_event(g, &t->b))) return rc;
+        HIP_TRY(hipEventRecord(t->a, st));
+        return GMACOP_OK;
+    }
+    int stop(gmacop_graph::Timed *t)
+    {
+        if (!on) return GMACOP_OK;
+        HIP_TRY(hipEventRecord(t->b, st));
+        g->pending.push_back(*t);
+        return GMACOP_OK;
+    }
+};
+
+int validate_params(const gmacop_graph *g, const gmacop_params *p, uint32_t nq)
+{
+    if (!p) return fail(GMACOP_E_INVAL, "params is NULL");
+    if (p->ants == 0) return fail(GMACOP_E_INVAL, "ants must be >= 1");
+    if (p->max_steps == 0) return fail(GMACOP_E_INVAL, "max_steps must be >= 1");
+    if (p->theta == 0) return fail(GMACOP_E_INVAL, "theta must be >= 1");
+    if (p->rho_q16 > 65536u) return fail(GMACOP_E_INVAL, "rho_q16 must be <= 65536");
+    if (p->tau_min_q16 == 0) return fail(GMACOP_E_INVAL, "tau_min_q16 must be >= 1");
+    if (p->tau_min_q16 > p->tau0_q16 || p->tau0_q16 > p->tau_max_q16)
+        return fail(GMACOP_E_INVAL, "need tau_min <= tau0 <= tau_max");
+    if (p->mode > GMACOP_MODE_INDEPENDENT) return fail(GMACOP_E_INVAL, "unknown mode %u", p->mode);
+    if (p->flags & ~(GMACOP_NO_LOAD_UPDATE | GMACOP_DEVICE_PTRS | GMACOP_TIME_KERNELS))
+        return fail(GMACOP_E_INVAL, "unknown flags");
+    const uint32_t lg = g->max_deg <= 1 ? 0 : bit_length(g->max_deg - 1);
+    if ((uint64_t)p->alpha * bit_length(p->tau_max_q16) + 16ull * p->beta + lg > 64)
+        return fail(GMACOP_E_RANGE, "alpha*bits(tau_max) + 16*beta + ceil(log2(max degree)) exceeds 64");
+    const unsigned __int128 dep =
+        (unsigned __int128)(p->mode == GMACOP_MODE_SHARED ? nq : 1) * p->ants * p->q_deposit;
+    if (dep >> 63) return fail(GMACOP_E_RANGE, "deposit total could reach 2^63");
+    if (g->max_deg > kMaxDegree) return fail(GMACOP_E_UNSUPPORTED, "out-degree %u exceeds %u", g->max_deg, kMaxDegree);
+    if ((uint64_t)nq * p->ants > 0xFFFFFFFFull) return fail(GMACOP_E_UNSUPPORTED, "more than 2^32 ants");
+    return GMACOP_OK;
+}
+
+template <int MAXD>
+int launch_walk(const WalkArgs &wa, bool lds, hipStream_t st)
+{
+    const uint64_t NA = (uint64_t)wa.nq * wa.ants;
+    const unsigned grid = blocks_for(NA, kWave);
+    if (lds) {
+        const size_t sh = (size_t)wa.nwords * kWave * sizeof(uint32_t);
+        hipLaunchKernelGGL((k_walk<MAXD, true>), dim3(grid), dim3(kWave), sh, st, wa);
+    } else {
+        hipLaunchKernelGGL((k_walk<MAXD, false>), dim3(grid), dim3(kWave), 0, st, wa);
+    }
+    HIP_TRY(hipGetLastError());
+    return GMACOP_OK;
+}
+
+}  // namespace
+
+extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **out)
+{
+    if (!out) return fail(GMACOP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_desc(d);
+    if (rc) return rc;
+    gmacop_graph *g = new gmacop_graph();
+    HIP_TRY(hipGetDevice(&g->device));
+    g->n = d->n_nodes;
+    g->m = d->n_edges;
+    g->n_inst = d->n_instances;
+    if (d->inst_node_off)
+        g->inst_off.assign(d->inst_node_off, d->inst_node_off + d->n_instances + 1);
+    else
+        g->inst_off = {0, g->n};
+    for (uint32_t u = 0; u < g->n; ++u) g->max_deg = std::max(g->max_deg, d->row_ptr[u + 1] - d->row_ptr[u]);
+    // incoming roads of every node (the approaches of its signal)
+    std::vector<uint32_t> rev_ptr(g->n + 1, 0), rev_edge(g->m);
+    for (uint32_t e = 0; e < g->m; ++e) rev_ptr[d->col[e] + 1]++;
+    for (uint32_t v = 0; v < g->n; ++v) rev_ptr[v + 1] += rev_ptr[v];
+    {
+        std::vector<uint32_t> fill(rev_ptr.begin(), rev_ptr.end() - 1);
+        for (uint32_t e = 0; e < g->m; ++e) rev_edge[fill[d->col[e]]++] = e;
+    }
+    const uint32_t n = g->n, m = g->m;
+    if ((rc = upload(&g->row_ptr, d->row_ptr, n + 1)) || (rc = upload(&g->col, d->col, m)) ||
+        (rc = upload(&g->len_dm, d->len_dm, m)) || (rc = upload(&g->speed, d->speed_kmh, m)) ||
+        (rc = upload(&g->green, d->green_pm, m)) || (rc = upload(&g->cycle, d->cycle_ms, n)) ||
+        (rc = upload(&g->x, d->x_dm, n)) || (rc = upload(&g->y, d->y_dm, n)) ||
+        (rc = upload(&g->base_load, d->base_load, m)) || (rc = upload(&g->rev_ptr, rev_ptr.data(), n + 1)) ||
+        (rc = upload(&g->rev_edge, rev_edge.data(), m)) || (rc = dalloc(&g->t0, m)) || (rc = dalloc(&g->wf, m)) ||
+        (rc = dalloc(&g->tau, m)) || (rc = dalloc(&g->load, m)) || (rc = dalloc(&g->cost, m)) ||
+        (rc = dalloc(&g->cnt, m)) || (rc = dalloc(&g->dep, m)) || (rc = dalloc(&g->counters, 4))) {
+        std::string keep = t_err;
+        delete g;
+        t_err = keep;
+        return rc;
+    }
+    if (hipMemset(g->counters, 0, 4 * sizeof(uint64_t)) != hipSuccess) {
+        delete g;
+        return fail(GMACOP_E_DEVICE, "hipMemset of counters failed");
+    }
+    *out = g;
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
+                                  gmacop_result *out, void *hip_stream)
+{
+    if (!g) return fail(GMACOP_E_INVAL, "graph is NULL");
+    if (!out || !out->path_edges || !out->path_len || !out->cost_ms || !out->steps_total)
+        return fail(GMACOP_E_INVAL, "result buffers missing");
+    if (nq > 0 && !q) return fail(GMACOP_E_INVAL, "queries are NULL");
+    int rc = validate_params(g, p, nq);
+    if (rc) return rc;
+    if (p->mode != GMACOP_MODE_SHARED) return fail(GMACOP_E_UNSUPPORTED, "independent mode is not built yet");
+    const bool dev_ptrs = (p->flags & GMACOP_DEVICE_PTRS) != 0;
+    if (!dev_ptrs) {
+        for (uint32_t i = 0; i < nq; ++i) {
+            if (q[i].qid == 0xFFFFFFFFu) return fail(GMACOP_E_INVAL, "query %u uses the reserved qid", i);
+            if (q[i].src >= g->n || q[i].dst >= g->n) return fail(GMACOP_E_INVAL, "query %u: node out of range", i);
+            if (q[i].src == q[i].dst) return fail(GMACOP_E_INVAL, "query %u: src == dst", i);
+            if (instance_of(g, q[i].src) != instance_of(g, q[i].dst))
+                return fail(GMACOP_E_INVAL, "query %u: src and dst in different cities", i);
+        }
+    }
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const uint32_t S = p->max_steps;
+    const uint64_t NA = (uint64_t)nq * p->ants;
+    const bool lds = g->n <= kLdsBitsetMaxNodes;
+    const uint32_t nwords = (g->n + 31) / 32;
+
+    // workspace
+    if ((rc = grow(&g->path, &g->cap_path, (size_t)S * NA, false))) return rc;
+    {
+        size_t c1 = g->cap_ants;
+        if ((rc = grow(&g->ant_len, &c1, NA, false))) return rc;
+        size_t c2 = g->cap_ants;
+        if ((rc = grow(&g->ant_cost, &c2, NA, false))) return rc;
+        g->cap_ants = std::min(c1, c2);
+    }
+    if (!lds && (rc = grow(&g->gbits, &g->cap_bits, (size_t)NA * nwords, true))) return rc;
+    {
+        size_t c1 = g->cap_veh, c2 = g->cap_veh, c3 = g->cap_veh, c4 = g->cap_veh;
+        if ((rc = grow(&g->iter_key, &c1, nq, false)) || (rc = grow(&g->best_len, &c2, nq, false)) ||
+            (rc = grow(&g->best_cost, &c3, nq, false)) || (rc = grow(&g->od, &c4, nq, false)))
+            return rc;
+        g->cap_veh = std::min(std::min(c1, c2), std::min(c3, c4));
+    }
+    if ((rc = grow(&g->best_path, &g->cap_best, (size_t)nq * S, false))) return rc;
+    if (!g->steps && (rc = dalloc(&g->steps, 1))) return rc;
+
+    const gmacop_od *od = q;
+    uint32_t *best_path = g->best_path, *best_len = g->best_len, *best_cost = g->best_cost;
+    uint64_t *steps = g->steps;
+    if (dev_ptrs) {
+        best_path = out->path_edges;
+        best_len = out->path_len;
+        best_cost = out->cost_ms;
+        steps = out->steps_total;
+    } else if (nq) {
+        HIP_TRY(hipMemcpyAsync(g->od, q, sizeof(gmacop_od) * nq, hipMemcpyHostToDevice, st));
+        od = g->od;
+    }
+
+    const bool load_update = !(p->flags & GMACOP_NO_LOAD_UPDATE);
+    EdgeInitArgs ia{g->m, p->tau0_q16, p->t_max_ms, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
+                    g->t0, g->wf, g->tau, g->load, g->cnt, g->dep};
+    hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ia);
+    hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq, best_len,
+                       best_cost, g->iter_key, steps);
+    CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost};
+    hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
+    HIP_TRY(hipGetLastError());
+
+    WalkArgs wa{};
+    wa.row_ptr = g->row_ptr; wa.col = g->col; wa.cost = g->cost; wa.tau = g->tau; wa.x = g->x; wa.y = g->y;
+    wa.od = od; wa.n = g->n; wa.nq = nq; wa.ants = p->ants; wa.max_steps = S; wa.alpha = p->alpha; wa.beta = p->beta;
+    wa.kgoal = p->vmax_kmh ? (uint32_t)((360ull << 16) / p->vmax_kmh) : 0;
+    wa.nwords = nwords; wa.seed_lo = (uint32_t)p->seed; wa.seed_hi = (uint32_t)(p->seed >> 32);
+    wa.q_deposit = p->q_deposit; wa.path = g->path; wa.ant_len = g->ant_len; wa.ant_cost = g->ant_cost;
+    wa.gbits = g->gbits; wa.dep = g->dep; wa.iter_key = g->iter_key; wa.steps = steps; wa.counters = g->counters;
+    BestArgs ba{nq, p->ants, S, load_update ? 1u : 0u, g->path, g->ant_len, g->iter_key, best_path, best_len,
+                best_cost, g->cnt};
+    EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, load_update ? 1u : 0u,
+                g->tau, g->load, g->cnt, g->base_load, g->dep};
+
+    KernelTimer kt{g, st, (p->flags & GMACOP_TIME_KERNELS) != 0};
+    gmacop_graph::Timed tm{};
+    for (uint32_t t = 0; t < p->iterations; ++t) {
+        wa.iter = p->iter_offset + t;
+        const uint32_t md = g->max_deg;
+        if (NA > 0) {
+            if ((rc = kt.start(0, &tm))) return rc;
+            rc = md <= 4 ? launch_walk<4>(wa, lds, st)
+                 : md <= 8 ? launch_walk<8>(wa, lds, st)
+                 : md <= 16 ? launch_walk<16>(wa, lds, st)
+                            : launch_walk<32>(wa, lds, st);
+            if (rc || (rc = kt.stop(&tm))) return rc;
+            if ((rc = kt.start(1, &tm))) return rc;
+            hipLaunchKernelGGL(k_best, dim3(nq), dim3(kWave), 0, st, ba);
+            if ((rc = kt.stop(&tm))) return rc;
+        }
+        if ((rc = kt.start(2, &tm))) return rc;
+        hipLaunchKernelGGL(k_edge, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ea);
+        if ((rc = kt.stop(&tm))) return rc;
+        if (load_update) {
+            if ((rc = kt.start(3, &tm))) return rc;
+            hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
+            if ((rc = kt.stop(&tm))) return rc;
+        }
+        HIP_TRY(hipGetLastError());
+    }
+
+    if (!dev_ptrs) {
+        if (nq) {
+            HIP_TRY(hipMemcpyAsync(out->path_len, best_len, sizeof(uint32_t) * nq, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(out->cost_ms, best_cost, sizeof(uint32_t) * nq, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(out->path_edges, best_path, sizeof(uint32_t) * (size_t)nq * S,
+                                   hipMemcpyDeviceToHost, st));
+        }
+        HIP_TRY(hipMemcpyAsync(out->steps_total, steps, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_state_get(gmacop_graph *g, uint32_t *tau_q16, uint32_t *load, void *hip_stream)
+{
+    if (!g) return fail(GMACOP_E_INVAL, "graph is NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (tau_q16) HIP_TRY(hipMemcpyAsync(tau_q16, g->tau, sizeof(uint32_t) * g->m, hipMemcpyDeviceToHost, st));
+    if (load) HIP_TRY(hipMemcpyAsync(load, g->load, sizeof(uint32_t) * g->m, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_stats_get(gmacop_graph *g, gmacop_stats *s, int reset, void *hip_stream)
+{
+    if (!g || !s) return fail(GMACOP_E_INVAL, "graph or stats is NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint64_t c[4];
+    HIP_TRY(hipMemcpyAsync(c, g->counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (auto &t : g->pending) {
+        HIP_TRY(hipEventSynchronize(t.b));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+        g->ms[t.kernel] += ms;
+        g->spare.push_back(t.a);
+        g->spare.push_back(t.b);
+    }
+    g->pending.clear();
+    for (int k = 0; k < 4; ++k) {
+        s->launches[k] = g->launches[k];
+        s->ms[k] = g->ms[k];
+    }
+    s->selections = c[0];
+    s->candidates = c[1];
+    s->arrivals = c[2];
+    s->deposit_roads = c[3];
+    if (reset) {
+        HIP_TRY(hipMemsetAsync(g->counters, 0, sizeof(c), st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int k = 0; k < 4; ++k) {
+            g->launches[k] = 0;
+            g->ms[k] = 0;
+        }
+    }
+    return GMACOP_OK;
+}
+
+extern "C" void gmacop_release(gmacop_graph *g)
+{
+    delete g;
+}
+
+extern "C" const char *gmacop_last_error(void)
+{
+    return t_err.c_str();
+}

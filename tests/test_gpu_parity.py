@@ -1,0 +1,205 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Integer method: every comparison is exact (paths, costs, selection counts,
+final pheromone and loads).  Each case prints its name before it runs."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_14244_amd import gmacop
+from workloads import (Vehicles, default_params, from_edges, grid8, grid32, grid_graph, pack_graphs,
+                       planar_graph, random_od)
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    oracle.build(force=False)
+
+
+def announce(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def run_gpu(g, veh, p):
+    G = gmacop.gmacop_graph_create(g)
+    try:
+        r = gmacop.gmacop_route_batch(G, veh, p)
+        if p["mode"] == gmacop.MODE_SHARED:
+            r["tau"], r["load"] = gmacop.gmacop_state_get(G)
+        return r
+    finally:
+        gmacop.gmacop_release(G)
+
+
+def assert_same(got, want, S, state=True):
+    assert got["steps_total"] == want["steps_total"], (got["steps_total"], want["steps_total"])
+    assert got["path_len"].tolist() == want["path_len"].tolist()
+    assert got["cost_ms"].tolist() == want["cost_ms"].tolist()
+    for v in range(want["path_len"].shape[0]):
+        L = int(want["path_len"][v])
+        assert got["path_edges"][v, :L].tolist() == want["path_edges"][v, :L].tolist(), v
+    if state:
+        assert np.array_equal(got["tau"], want["tau"])
+        assert np.array_equal(got["load"], want["load"])
+
+
+def check(name, g, veh, p, state=True):
+    announce(name)
+    want = oracle.route(g, veh, p)
+    got = run_gpu(g, veh, p)
+    assert_same(got, want, p["max_steps"], state=state and p["mode"] == 0)
+    return got, want
+
+
+def test_grid8_workload():
+    w = grid8()
+    check(w.name, w.graph, w.vehicles, w.params)
+
+
+def test_grid32_reduced():
+    w = grid32(vehicles=48, ants=32, iterations=12)
+    check(w.name, w.graph, w.vehicles, w.params)
+
+
+def test_grid32_frozen_loads():
+    w = grid32(vehicles=32, ants=16, iterations=8)
+    check(w.name + "_frozen", w.graph, w.vehicles, dict(w.params, flags=gmacop.NO_LOAD_UPDATE))
+
+
+def test_planar_global_bitset_and_degree5():
+    """More than 4096 nodes: visited bits in global memory; out-degree up to 5."""
+    rng = np.random.default_rng(21)
+    g = planar_graph(6000, rng)
+    assert g.n > 4096 and g.out_degree().max() > 4
+    V = random_od(g.n, 24, rng)
+    p = default_params(ants=16, iterations=6, max_steps=400, vmax_kmh=70)
+    check("planar6000", g, V, p)
+
+
+def test_planar_small_lds_degree5():
+    rng = np.random.default_rng(22)
+    g = planar_graph(3000, rng)
+    V = random_od(g.n, 20, rng)
+    p = default_params(ants=16, iterations=6, max_steps=300, vmax_kmh=70)
+    check("planar3000", g, V, p)
+
+
+def test_parameter_variants():
+    w = grid32(vehicles=16, ants=8, iterations=5)
+    g, V = w.graph, w.vehicles
+    for kw in (dict(alpha=0, beta=0), dict(alpha=2, beta=1, tau_max_q16=2 ** 20),
+               dict(alpha=1, beta=3, tau0_q16=2 ** 12, tau_max_q16=2 ** 13 - 1),
+               dict(rho_q16=0, q_deposit=0), dict(rho_q16=65536), dict(vmax_kmh=0, max_steps=200),
+               dict(theta=1, th_max=0), dict(seed=0xDEADBEEF12345678, iter_offset=77), dict(max_steps=1),
+               dict(ants=1), dict(t_max_ms=0)):
+        check(f"grid32_{kw}", g, V, dict(w.params, **kw))
+
+
+def test_edge_cases():
+    w = grid8()
+    g = w.graph
+    # zero iterations, zero vehicles
+    check("iterations0", g, w.vehicles, dict(w.params, iterations=0))
+    check("no_vehicles", g, Vehicles(qid=np.zeros(0, np.uint32), src=np.zeros(0, np.uint32),
+                                     dst=np.zeros(0, np.uint32)), w.params)
+    # unreachable destination: one-way trap
+    h = from_edges(4, [0, 0, 1, 2], [1, 2, 0, 3])      # 3 has no out-roads, 0 cannot reach... 0->2->3 ok; 3->x none
+    Vt = Vehicles(qid=np.array([5, 6], np.uint32), src=np.array([3, 0], np.uint32), dst=np.array([0, 3], np.uint32))
+    p = default_params(ants=8, iterations=4, max_steps=3, vmax_kmh=0)
+    got, want = check("unreachable", h, Vt, p)
+    assert want["path_len"][0] == 0 and want["cost_ms"][0] == 2 ** 32 - 1
+    # several vehicles sharing qid and route
+    Vd = Vehicles(qid=np.array([1, 1, 2], np.uint32), src=np.array([0, 0, 9], np.uint32),
+                  dst=np.array([63, 63, 54], np.uint32))
+    check("duplicate_qid", g, Vd, w.params)
+
+
+def test_packed_instances():
+    rng = np.random.default_rng(8)
+    gs = [grid_graph(5, 6, rng), planar_graph(700, rng), grid_graph(3, 9, rng)]
+    packed = pack_graphs(gs)
+    off = packed.inst_node_off.astype(np.int64)
+    vs = [random_od(gi.n, 6, rng, node_lo=int(off[i]), qid0=6 * i) for i, gi in enumerate(gs)]
+    V = Vehicles(qid=np.concatenate([v.qid for v in vs]), src=np.concatenate([v.src for v in vs]),
+                 dst=np.concatenate([v.dst for v in vs]))
+    p = default_params(ants=12, iterations=6, max_steps=80, vmax_kmh=70)
+    check("packed3", packed, V, p)
+
+
+def test_device_pointer_mode_matches_host_mode():
+    import torch
+    w = grid32(vehicles=40, ants=16, iterations=6)
+    announce("device_ptrs")
+    G = gmacop.gmacop_graph_create(w.graph)
+    try:
+        host = gmacop.gmacop_route_batch(G, w.vehicles, w.params)
+        b = gmacop.DeviceBatch(w.vehicles, w.params["max_steps"])
+        gmacop.gmacop_route_batch_device(G, b, w.params)
+        torch.cuda.synchronize()
+        dev = b.result()
+        assert_same(dev, host, w.params["max_steps"], state=False)
+    finally:
+        gmacop.gmacop_release(G)
+
+
+def test_invalid_queries_match_oracle_codes():
+    w = grid8()
+    announce("error_codes")
+    G = gmacop.gmacop_graph_create(w.graph)
+    try:
+        bad = [Vehicles(qid=np.array([0], np.uint32), src=np.array([3], np.uint32), dst=np.array([3], np.uint32)),
+               Vehicles(qid=np.array([0], np.uint32), src=np.array([3], np.uint32), dst=np.array([64], np.uint32))]
+        for V in bad:
+            assert oracle.route_rc(w.graph, V, w.params) == oracle.E_INVAL
+            with pytest.raises(gmacop.GmacopError) as ei:
+                gmacop.gmacop_route_batch(G, V, w.params)
+            assert ei.value.code == gmacop.E_INVAL
+        for kw, code in ((dict(ants=0), gmacop.E_INVAL), (dict(rho_q16=70000), gmacop.E_INVAL),
+                         (dict(beta=3), gmacop.E_RANGE), (dict(q_deposit=2 ** 62), gmacop.E_RANGE)):
+            p = dict(w.params, **kw)
+            assert oracle.route_rc(w.graph, w.vehicles, p) == code
+            with pytest.raises(gmacop.GmacopError) as ei:
+                gmacop.gmacop_route_batch(G, w.vehicles, p)
+            assert ei.value.code == code
+        # the handle still works after rejected calls
+        ok = gmacop.gmacop_route_batch(G, w.vehicles, w.params)
+        assert ok["steps_total"] == oracle.route(w.graph, w.vehicles, w.params)["steps_total"]
+    finally:
+        gmacop.gmacop_release(G)
+
+
+def _digest_routes(path_edges, path_len):
+    h = hashlib.sha256()
+    for v in range(path_len.shape[0]):
+        h.update(np.ascontiguousarray(path_edges[v, :int(path_len[v])], dtype=np.uint32).tobytes())
+        h.update(b"|")
+    return h.hexdigest()
+
+
+def test_grid32_full_against_stored_oracle_results():
+    """Full 32x32 workload (256 vehicles x 128 ants x 100 iterations): the
+    oracle's results were stored by tests/golden/make_expected.py."""
+    path = os.path.join(HERE, "golden", "grid32_expected.json")
+    with open(path) as f:
+        want = json.load(f)
+    w = grid32()
+    assert w.name == want["workload"] and w.params == want["params"]
+    announce(w.name)
+    got = run_gpu(w.graph, w.vehicles, w.params)
+    assert got["steps_total"] == want["steps_total"]
+    assert got["cost_ms"].tolist() == want["cost_ms"]
+    assert got["path_len"].tolist() == want["path_len"]
+    assert _digest_routes(got["path_edges"], got["path_len"]) == want["routes_sha256"]
+    assert hashlib.sha256(got["tau"].tobytes()).hexdigest() == want["tau_sha256"]
+    assert hashlib.sha256(got["load"].tobytes()).hexdigest() == want["load_sha256"]
