@@ -68,7 +68,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="grid32", choices=["grid8", "grid32", "planar100k", "multicity"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iterations", type=int, default=25)
+    ap.add_argument("--cpu-iterations", type=int, default=10)
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not bracket kernels with HIP events (roofline fields become null)")
     args = ap.parse_args()

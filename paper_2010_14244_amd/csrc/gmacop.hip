@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -356,6 +357,186 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
     }
 }
 
+struct LdsWalkArgs {
+    const uint32_t *row_ptr, *col, *cost, *tau;
+    const int32_t *x, *y;
+    const gmacop_od *od;
+    uint32_t n, m, nq, ants, apb, bpv, max_steps, alpha, beta, kgoal, nwords;
+    uint32_t seed_lo, seed_hi, iter;
+    uint64_t q_deposit;
+    uint32_t *path, *ant_len, *ant_cost;
+    uint64_t *dep, *iter_key, *steps, *counters;
+};
+
+// Inclusive prefix sum of a 64-bit value over the L lanes of an aligned lane
+// group (L a power of two <= 64), by shuffles.
+template <int L>
+__device__ __forceinline__ uint64_t group_incl_prefix(uint64_t v, uint32_t j)
+{
+#pragma unroll
+    for (int off = 1; off < L; off <<= 1) {
+        const uint64_t o = __shfl_up(v, off, L);
+        if (j >= (uint32_t)off) v += o;
+    }
+    return v;
+}
+
+// Walk for graphs whose roads fit in LDS.  One block serves `apb` ants of one
+// vehicle (blocks_per_vehicle = bpv).  Prologue: the block derives the
+// vehicle's goal term for every node and stages, per road, the head node,
+// the head's out-road range and the choice weight tau^alpha * eta^beta
+// (a per-destination choice table), then clears its ants' visited bits.
+// Walk: L lanes per ant; lane j examines candidates j, j+L, ...; the group
+// sums weights by shuffles, and the first candidate (CSR order) whose
+// inclusive prefix exceeds the target is taken.  The L lanes draw Philox
+// words for L consecutive steps at once (the counter does not depend on the
+// path), so one draw serves L steps.
+template <int L, int CH>
+__global__ __launch_bounds__(256) void k_walk_lds(LdsWalkArgs a)
+{
+    extern __shared__ uint64_t s_mem[];
+    uint2 *s_rec = (uint2 *)s_mem;                   // [m] (head | head_deg << 24, head_row_start)
+    uint64_t *s_w = s_mem + a.m;                     // [m] choice weight
+    uint32_t *s_aux = (uint32_t *)(s_mem + 2 * (size_t)a.m);   // goal terms, then visited bits
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    const uint32_t v = blockIdx.x / a.bpv, part = blockIdx.x % a.bpv;
+    const gmacop_od q = a.od[v];
+    const bool valid = q.src < a.n && q.dst < a.n && q.src != q.dst;
+
+    // ---- prologue: choice table of this vehicle ----
+    if (valid) {
+        const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
+        for (uint32_t i = tid; i < a.n; i += nthr) s_aux[i] = (uint32_t)goal_ms(a.x[i], a.y[i], dx, dy, a.kgoal);
+    }
+    __syncthreads();
+    if (valid) {
+        for (uint32_t u = tid; u < a.n; u += nthr) {
+            const uint32_t rs = a.row_ptr[u], re = a.row_ptr[u + 1];
+            const int64_t hu = s_aux[u];
+            for (uint32_t e = rs; e < re; ++e) {
+                const uint32_t xh = a.col[e];
+                const uint32_t xrs = a.row_ptr[xh], xre = a.row_ptr[xh + 1];
+                const uint32_t eta = eta_of((int64_t)a.cost[e] + (int64_t)s_aux[xh] - hu);
+                s_w[e] = ipow_u64(a.tau[e], a.alpha) * ipow_u64(eta, a.beta);
+                s_rec[e] = make_uint2(xh | ((xre - xrs) << 24), xrs);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < a.nwords * a.apb; i += nthr) s_aux[i] = 0;
+    __syncthreads();
+
+    // ---- walk ----
+    const uint32_t grp = tid / L, j = tid % L;
+    const uint32_t k = part * a.apb + grp;
+    const bool active = valid && grp < a.apb && k < a.ants;
+    const uint32_t NA = a.nq * a.ants;
+    const uint32_t ant = v * a.ants + k;
+    uint32_t s = 0, ncand = 0, arrived = 0, cs = 0;
+    if (active) {
+        uint32_t u = q.src;
+        uint32_t rs = a.row_ptr[u], d = a.row_ptr[u + 1] - rs;
+        if (j == 0) atomicOr(&s_aux[(u >> 5) * a.apb + grp], 1u << (u & 31));
+        uint64_t myr = 0;
+        bool ok = false;
+        while (s < a.max_steps) {
+            if ((s % L) == 0) myr = philox_u64(q.qid, k, a.iter, s + j, a.seed_lo, a.seed_hi);
+            const uint64_t r = L == 1 ? myr : __shfl(myr, (int)(s % L), L);
+            ncand += d;
+            uint64_t w[CH], incl[CH];
+            uint2 rec[CH];
+            uint64_t base = 0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const uint32_t cand = c * L + j;
+                w[c] = 0;
+                rec[c] = make_uint2(0, 0);
+                if (cand < d) {
+                    const uint32_t e = rs + cand;
+                    rec[c] = s_rec[e];
+                    const uint32_t xh = rec[c].x & 0xFFFFFFu;
+                    const bool seen = (s_aux[(xh >> 5) * a.apb + grp] >> (xh & 31)) & 1u;
+                    w[c] = seen ? 0 : s_w[e];
+                }
+                incl[c] = group_incl_prefix<L>(w[c], j) + base;
+                base = L == 1 ? incl[c] : __shfl(incl[c], L - 1, L);
+            }
+            const uint64_t T = base;
+            if (T == 0) break;   // dead end
+            const uint64_t target = __umul64hi(r, T);
+            uint32_t win_c = 0xFFFFFFFFu, win_j = 0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const bool hit = w[c] != 0 && incl[c] - w[c] <= target && target < incl[c];
+                const uint64_t m = __ballot(hit);
+                const uint32_t gm = (uint32_t)(m >> ((threadIdx.x & (kWave - 1)) & ~(uint32_t)(L - 1))) &
+                                    (L >= 32 ? 0xFFFFFFFFu : ((1u << L) - 1u));
+                if (win_c == 0xFFFFFFFFu && gm) {
+                    win_c = c;
+                    win_j = __builtin_ctz(gm);
+                }
+            }
+            if (win_c == 0xFFFFFFFFu) break;   // unreachable when T > 0; keeps every index in range
+            uint2 rsel = make_uint2(0, 0);
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const uint32_t rx = L == 1 ? rec[c].x : __shfl(rec[c].x, (int)win_j, L);
+                const uint32_t ry = L == 1 ? rec[c].y : __shfl(rec[c].y, (int)win_j, L);
+                if ((uint32_t)c == win_c) rsel = make_uint2(rx, ry);
+            }
+            const uint32_t esel = rs + win_c * L + win_j;
+            const uint32_t xsel = rsel.x & 0xFFFFFFu;
+            if (j == 0) {
+                a.path[(size_t)s * NA + ant] = esel;
+                atomicOr(&s_aux[(xsel >> 5) * a.apb + grp], 1u << (xsel & 31));
+            }
+            const uint64_t c2 = (uint64_t)cs + a.cost[esel];
+            cs = c2 > kPathCostCap ? kPathCostCap : (uint32_t)c2;
+            ++s;
+            u = xsel;
+            rs = rsel.y;
+            d = rsel.x >> 24;
+            if (u == q.dst) {
+                ok = true;
+                break;
+            }
+        }
+        if (j == 0) {
+            a.ant_len[ant] = s;
+            a.ant_cost[ant] = ok ? cs : kNoCost;
+        }
+        if (ok) {
+            arrived = 1;
+            const uint64_t dpos = a.q_deposit / cs;
+            if (dpos)
+                for (uint32_t i = j; i < s; i += L)
+                    atomicAdd((unsigned long long *)&a.dep[a.path[(size_t)i * NA + ant]], (unsigned long long)dpos);
+            if (j == 0)
+                atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
+        }
+    } else if (grp < a.apb && k < a.ants && j == 0) {
+        a.ant_len[ant] = 0;
+        a.ant_cost[ant] = kNoCost;
+    }
+    // counters: only the first lane of each group contributes
+    uint64_t cnt = j == 0 ? s : 0, cand = j == 0 ? ncand : 0, arr = j == 0 ? arrived : 0,
+             dh = (j == 0 && arrived) ? s : 0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off);
+        cand += __shfl_xor(cand, off);
+        arr += __shfl_xor(arr, off);
+        dh += __shfl_xor(dh, off);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0 && cnt) {
+        atomicAdd((unsigned long long *)a.steps, (unsigned long long)cnt);
+        atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)cnt);
+        atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)cand);
+        atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)arr);
+        atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)dh);
+    }
+}
+
 struct BestArgs {
     uint32_t nq, ants, max_steps, load_update;
     const uint32_t *path, *ant_len;
@@ -465,6 +646,7 @@ unsigned blocks_for(uint64_t work, unsigned per_block)
 struct gmacop_graph {
     int device = 0;
     uint32_t n = 0, m = 0, n_inst = 1, max_deg = 0;
+    int max_lds = 65536;               // dynamic LDS a block may use on this device
     std::vector<uint32_t> inst_off;    // host copy, [n_inst+1]
     // static graph (device)
     uint32_t *row_ptr = nullptr, *col = nullptr, *len_dm = nullptr, *cycle = nullptr, *base_load = nullptr;
@@ -649,6 +831,89 @@ int launch_walk(const WalkArgs &wa, bool lds, hipStream_t st)
     return GMACOP_OK;
 }
 
+struct WalkPlan {
+    bool lds = false;        // roads staged in LDS (k_walk_lds), else k_walk
+    uint32_t lanes = 1;      // lanes per ant (k_walk_lds)
+    uint32_t apb = 0;        // ants per block (k_walk_lds)
+    uint32_t bpv = 0;        // blocks per vehicle (k_walk_lds)
+    size_t lds_bytes = 0;
+    uint32_t maxd = 4;       // candidate bound the kernel is built for
+};
+
+template <int L, int MAXD>
+int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+{
+    constexpr int CH = (MAXD + L - 1) / L;
+    auto kern = k_walk_lds<L, CH>;
+    if (pl.lds_bytes > 65536)
+        HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)pl.lds_bytes));
+    const unsigned grid = wa.nq * pl.bpv;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(pl.apb * L), pl.lds_bytes, st, wa);
+    HIP_TRY(hipGetLastError());
+    return GMACOP_OK;
+}
+
+template <int L>
+int launch_walk_lds_d(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+{
+    switch (pl.maxd) {
+    case 4: return launch_walk_lds<L, 4>(wa, pl, st);
+    case 8: return launch_walk_lds<L, 8>(wa, pl, st);
+    case 16: return launch_walk_lds<L, 16>(wa, pl, st);
+    default: return launch_walk_lds<L, 32>(wa, pl, st);
+    }
+}
+
+int launch_walk_lds_any(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+{
+    switch (pl.lanes) {
+    case 1: return launch_walk_lds_d<1>(wa, pl, st);
+    case 2: return launch_walk_lds_d<2>(wa, pl, st);
+    case 4: return launch_walk_lds_d<4>(wa, pl, st);
+    default: return launch_walk_lds_d<8>(wa, pl, st);
+    }
+}
+
+uint32_t env_u32(const char *name, uint32_t dflt)
+{
+    const char *v = getenv(name);
+    return (v && *v) ? (uint32_t)strtoul(v, nullptr, 10) : dflt;
+}
+
+// Choose the walk kernel and its shape.  k_walk_lds when the roads, the goal
+// terms and the visited bits of a block fit the device's LDS per block;
+// otherwise the global-memory walker.  GMACOP_WALK_LANES (1, 2, 4, 8) and
+// GMACOP_WALK_KERNEL (lds | global) override the choice for tuning; results
+// do not depend on it.
+WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
+{
+    WalkPlan pl;
+    pl.maxd = g->max_deg <= 4 ? 4 : g->max_deg <= 8 ? 8 : g->max_deg <= 16 ? 16 : 32;
+    const char *kind = getenv("GMACOP_WALK_KERNEL");
+    const bool want_global = kind && strcmp(kind, "global") == 0;
+    uint32_t L = env_u32("GMACOP_WALK_LANES", g->max_deg <= 4 ? 4 : 8);
+    if (L != 1 && L != 2 && L != 4 && L != 8) L = 4;
+    const uint32_t nwords = (g->n + 31) / 32;
+    if (!want_global && g->n < (1u << 24)) {
+        uint32_t apb = std::min<uint32_t>(p->ants, 256 / L);
+        while (apb >= 1) {
+            const size_t aux = std::max<size_t>(g->n, (size_t)nwords * apb) * 4;
+            const size_t bytes = (size_t)g->m * 16 + aux;
+            if (bytes <= (size_t)max_lds) {
+                pl.lds = true;
+                pl.lanes = L;
+                pl.apb = apb;
+                pl.bpv = (p->ants + apb - 1) / apb;
+                pl.lds_bytes = bytes;
+                break;
+            }
+            apb /= 2;
+        }
+    }
+    return pl;
+}
+
 }  // namespace
 
 extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **out)
@@ -659,6 +924,15 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
     if (rc) return rc;
     gmacop_graph *g = new gmacop_graph();
     HIP_TRY(hipGetDevice(&g->device));
+    {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, g->device) == hipSuccess && v > 0)
+            g->max_lds = v;
+        else if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device) == hipSuccess &&
+                 v > 0)
+            g->max_lds = v;
+        (void)hipGetLastError();
+    }
     g->n = d->n_nodes;
     g->m = d->n_edges;
     g->n_inst = d->n_instances;
@@ -722,6 +996,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     const uint32_t S = p->max_steps;
     const uint64_t NA = (uint64_t)nq * p->ants;
     const bool lds = g->n <= kLdsBitsetMaxNodes;
+    const WalkPlan plan = plan_walk(g, p, g->max_lds);
     const uint32_t nwords = (g->n + 31) / 32;
 
     // workspace
@@ -733,7 +1008,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         if ((rc = grow(&g->ant_cost, &c2, NA, false))) return rc;
         g->cap_ants = std::min(c1, c2);
     }
-    if (!lds && (rc = grow(&g->gbits, &g->cap_bits, (size_t)NA * nwords, true))) return rc;
+    if (!plan.lds && !lds && (rc = grow(&g->gbits, &g->cap_bits, (size_t)NA * nwords, true))) return rc;
     {
         size_t c1 = g->cap_veh, c2 = g->cap_veh, c3 = g->cap_veh, c4 = g->cap_veh;
         if ((rc = grow(&g->iter_key, &c1, nq, false)) || (rc = grow(&g->best_len, &c2, nq, false)) ||
@@ -774,6 +1049,13 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     wa.nwords = nwords; wa.seed_lo = (uint32_t)p->seed; wa.seed_hi = (uint32_t)(p->seed >> 32);
     wa.q_deposit = p->q_deposit; wa.path = g->path; wa.ant_len = g->ant_len; wa.ant_cost = g->ant_cost;
     wa.gbits = g->gbits; wa.dep = g->dep; wa.iter_key = g->iter_key; wa.steps = steps; wa.counters = g->counters;
+    LdsWalkArgs la{};
+    la.row_ptr = g->row_ptr; la.col = g->col; la.cost = g->cost; la.tau = g->tau; la.x = g->x; la.y = g->y;
+    la.od = od; la.n = g->n; la.m = g->m; la.nq = nq; la.ants = p->ants; la.apb = plan.apb; la.bpv = plan.bpv;
+    la.max_steps = S; la.alpha = p->alpha; la.beta = p->beta; la.kgoal = wa.kgoal; la.nwords = nwords;
+    la.seed_lo = wa.seed_lo; la.seed_hi = wa.seed_hi; la.q_deposit = p->q_deposit; la.path = g->path;
+    la.ant_len = g->ant_len; la.ant_cost = g->ant_cost; la.dep = g->dep; la.iter_key = g->iter_key;
+    la.steps = steps; la.counters = g->counters;
     BestArgs ba{nq, p->ants, S, load_update ? 1u : 0u, g->path, g->ant_len, g->iter_key, best_path, best_len,
                 best_cost, g->cnt};
     EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, load_update ? 1u : 0u,
@@ -786,10 +1068,15 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         const uint32_t md = g->max_deg;
         if (NA > 0) {
             if ((rc = kt.start(0, &tm))) return rc;
-            rc = md <= 4 ? launch_walk<4>(wa, lds, st)
-                 : md <= 8 ? launch_walk<8>(wa, lds, st)
-                 : md <= 16 ? launch_walk<16>(wa, lds, st)
-                            : launch_walk<32>(wa, lds, st);
+            if (plan.lds) {
+                la.iter = wa.iter;
+                rc = launch_walk_lds_any(la, plan, st);
+            } else {
+                rc = md <= 4 ? launch_walk<4>(wa, lds, st)
+                     : md <= 8 ? launch_walk<8>(wa, lds, st)
+                     : md <= 16 ? launch_walk<16>(wa, lds, st)
+                                : launch_walk<32>(wa, lds, st);
+            }
             if (rc || (rc = kt.stop(&tm))) return rc;
             if ((rc = kt.start(1, &tm))) return rc;
             hipLaunchKernelGGL(k_best, dim3(nq), dim3(kWave), 0, st, ba);

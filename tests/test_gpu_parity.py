@@ -203,3 +203,17 @@ def test_grid32_full_against_stored_oracle_results():
     assert _digest_routes(got["path_edges"], got["path_len"]) == want["routes_sha256"]
     assert hashlib.sha256(got["tau"].tobytes()).hexdigest() == want["tau_sha256"]
     assert hashlib.sha256(got["load"].tobytes()).hexdigest() == want["load_sha256"]
+
+
+@pytest.mark.parametrize("kernel,lanes", [("global", 1), ("lds", 1), ("lds", 2), ("lds", 4), ("lds", 8)])
+def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes):
+    """Every walker shape (global-memory or LDS-staged roads, 1-8 lanes per
+    ant) reproduces the oracle exactly."""
+    monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
+    monkeypatch.setenv("GMACOP_WALK_LANES", str(lanes))
+    w = grid32(vehicles=24, ants=40, iterations=6)
+    check(f"{w.name}_{kernel}_L{lanes}", w.graph, w.vehicles, w.params)
+    rng = np.random.default_rng(23)
+    g = planar_graph(1500, rng)
+    V = random_od(g.n, 12, rng)
+    check(f"planar1500_{kernel}_L{lanes}", g, V, default_params(ants=24, iterations=5, max_steps=300, vmax_kmh=70))
