@@ -47,6 +47,10 @@ extern "C" {
                                        the call returns without synchronising          */
 #define GMACOP_TIME_KERNELS    4u   /* record a HIP event pair around every kernel
                                        launch, summed by gmacop_stats_get              */
+#define GMACOP_HIP_GRAPH       8u   /* run the call's kernel sequence as a HIP graph,
+                                       captured once and replayed while the call's
+                                       arguments stay the same; needs a non-null
+                                       stream; ignored with GMACOP_TIME_KERNELS        */
 
 /* Opaque handle: the graph, its static per-road data and the pheromone / load
  * state on the device.  Owns all of its device memory. */
@@ -151,6 +155,7 @@ typedef struct {
     uint64_t candidates;     /* out-roads examined at those selections                */
     uint64_t arrivals;       /* ants that reached their destination                   */
     uint64_t deposit_roads;  /* roads deposited on by arriving ants                   */
+    uint64_t longest_walks;  /* sum over walk launches of the longest ant's road count   */
 } gmacop_stats;
 
 /* Copy the counters into *s (synchronises hip_stream); reset them when reset

@@ -80,13 +80,13 @@ __device__ __forceinline__ uint64_t philox_u64(uint32_t c0, uint32_t c1, uint32_
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;   // one 32x32->64 multiply each
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -226,6 +226,7 @@ struct WalkArgs {
     uint64_t *iter_key;    // [nq]
     uint64_t *steps;       // [1] selections of this call
     uint64_t *counters;    // [4] cumulative: selections, candidates examined, arrivals, roads deposited on
+    uint32_t *iter_max;    // longest walk of this iteration
 };
 
 // One lane per ant (vehicle v = a / ants, ant k = a % ants).  Visited nodes
@@ -341,12 +342,14 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
     }
     // one atomic per wave for each counter
     uint64_t cnt = s, cand = ncand, arr = arrived, dh = arrived ? s : 0;
+    uint32_t smax = s;
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
         cnt += __shfl_xor(cnt, off);
         cand += __shfl_xor(cand, off);
         arr += __shfl_xor(arr, off);
         dh += __shfl_xor(dh, off);
+        smax = max(smax, (uint32_t)__shfl_xor((int)smax, off));
     }
     if (lane == 0 && cnt) {
         atomicAdd((unsigned long long *)a.steps, (unsigned long long)cnt);
@@ -357,8 +360,73 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
     }
 }
 
+
+// ---- lane-group primitives (groups of L aligned lanes inside a 16-lane DPP row) ----
+
+constexpr int kDppQuad(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+constexpr int kDppRowShr(int n) { return 0x110 + n; }
+constexpr int kDppHalfMirror = 0x141;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v)
+{
+    return ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp32<CTRL>((uint32_t)v);
+}
+
+// Inclusive prefix sum over the group (lane j gets w_0 + ... + w_j).
+template <int L>
+__device__ __forceinline__ uint64_t grp_prefix(uint64_t v, uint32_t j)
+{
+    if (L >= 2) { const uint64_t o = dpp64<kDppRowShr(1)>(v); v += j >= 1 ? o : 0; }
+    if (L >= 4) { const uint64_t o = dpp64<kDppRowShr(2)>(v); v += j >= 2 ? o : 0; }
+    if (L >= 8) { const uint64_t o = dpp64<kDppRowShr(4)>(v); v += j >= 4 ? o : 0; }
+    return v;
+}
+
+// Sum over the group, returned to every lane.
+template <int L>
+__device__ __forceinline__ uint64_t grp_sum(uint64_t v)
+{
+    if (L >= 2) v += dpp64<kDppQuad(1, 0, 3, 2)>(v);
+    if (L >= 4) v += dpp64<kDppQuad(2, 3, 0, 1)>(v);
+    if (L >= 8) v += dpp64<kDppHalfMirror>(v);
+    return v;
+}
+
+// Bitwise OR over the group (used with one non-zero contributor).
+template <int L>
+__device__ __forceinline__ uint32_t grp_or(uint32_t v)
+{
+    if (L >= 2) v |= dpp32<kDppQuad(1, 0, 3, 2)>(v);
+    if (L >= 4) v |= dpp32<kDppQuad(2, 3, 0, 1)>(v);
+    if (L >= 8) v |= dpp32<kDppHalfMirror>(v);
+    return v;
+}
+
+// Value of group lane i (i < L, uniform over the group) to every lane.
+template <int L>
+__device__ __forceinline__ uint64_t grp_bcast(uint64_t v, uint32_t i)
+{
+    if (L == 1) return v;
+    if (L == 2) return i == 0 ? dpp64<kDppQuad(0, 0, 2, 2)>(v) : dpp64<kDppQuad(1, 1, 3, 3)>(v);
+    if (L == 4) {
+        const uint64_t b0 = dpp64<kDppQuad(0, 0, 0, 0)>(v), b1 = dpp64<kDppQuad(1, 1, 1, 1)>(v);
+        const uint64_t b2 = dpp64<kDppQuad(2, 2, 2, 2)>(v), b3 = dpp64<kDppQuad(3, 3, 3, 3)>(v);
+        return i == 0 ? b0 : i == 1 ? b1 : i == 2 ? b2 : b3;
+    }
+    return __shfl(v, (int)i, L);
+}
+
 struct LdsWalkArgs {
     const uint32_t *row_ptr, *col, *cost, *tau;
+    const uint2 *rec;          // [m] static: head | head_out_degree << 24, head's first out-road
+    const uint32_t *tail;      // [m] static: tail node of each road
     const int32_t *x, *y;
     const gmacop_od *od;
     uint32_t n, m, nq, ants, apb, bpv, max_steps, alpha, beta, kgoal, nwords;
@@ -366,19 +434,88 @@ struct LdsWalkArgs {
     uint64_t q_deposit;
     uint32_t *path, *ant_len, *ant_cost;
     uint64_t *dep, *iter_key, *steps, *counters;
+    uint32_t *iter_max;    // longest walk of this iteration
 };
 
-// Inclusive prefix sum of a 64-bit value over the L lanes of an aligned lane
-// group (L a power of two <= 64), by shuffles.
-template <int L>
-__device__ __forceinline__ uint64_t group_incl_prefix(uint64_t v, uint32_t j)
+// One step of an ant on LDS-staged roads (see k_walk_lds).  SL = step index
+// modulo L: the group lane that drew this step's Philox word.  Returns false
+// when the walk ends (arrival, dead end).
+template <int L, int CH, int SL>
+__device__ __forceinline__ bool lds_step(const uint2 *s_rec, const uint64_t *s_w, const uint32_t *s_cost,
+                                         uint32_t *bits, uint32_t j, uint32_t m_last, uint64_t myr, uint32_t dst,
+                                         uint32_t &u, uint32_t &rs, uint32_t &d, uint32_t &s, uint32_t &ncand,
+                                         uint64_t &cs, bool &ok, uint32_t *path_s)
 {
+    ncand += d;
+    uint64_t w[CH], incl[CH];
+    uint2 rec[CH];
 #pragma unroll
-    for (int off = 1; off < L; off <<= 1) {
-        const uint64_t o = __shfl_up(v, off, L);
-        if (j >= (uint32_t)off) v += o;
+    for (int c = 0; c < CH; ++c) {
+        const uint32_t idx = min(rs + (uint32_t)(c * L) + j, m_last);   // always a valid address
+        rec[c] = s_rec[idx];
+        w[c] = s_w[idx];
     }
-    return v;
+    uint64_t base = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const uint32_t xh = rec[c].x & 0xFFFFFFu;
+        const bool live = (uint32_t)(c * L) + j < d && !((bits[xh >> 5] >> (xh & 31)) & 1u);
+        w[c] = live ? w[c] : 0;
+        incl[c] = grp_prefix<L>(w[c], j) + base;
+        base += grp_sum<L>(w[c]);
+    }
+    const uint64_t T = base;
+    if (T == 0) return false;   // dead end
+    uint64_t r = myr;
+    if (L == 2) r = SL == 0 ? dpp64<kDppQuad(0, 0, 2, 2)>(myr) : dpp64<kDppQuad(1, 1, 3, 3)>(myr);
+    if (L == 4) r = dpp64<kDppQuad(SL, SL, SL, SL)>(myr);
+    if (L >= 8) r = __shfl(myr, SL, L);   // no fixed DPP pattern reaches across quads
+    const uint64_t target = __umul64hi(r, T);
+    // exactly one (chunk, lane) holds the target in its prefix interval
+    uint32_t sel_x = 0, sel_y = 0, sel_c = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const bool hit = w[c] != 0 && incl[c] - w[c] <= target && target < incl[c];
+        sel_x |= hit ? rec[c].x : 0u;
+        sel_y |= hit ? rec[c].y : 0u;
+        sel_c |= hit ? (uint32_t)(c * L) + j + 1 : 0u;
+    }
+    sel_x = grp_or<L>(sel_x);
+    sel_y = grp_or<L>(sel_y);
+    sel_c = grp_or<L>(sel_c);
+    if (sel_c == 0) return false;   // unreachable when T > 0; keeps every index in range
+    const uint32_t xsel = sel_x & 0xFFFFFFu;
+    const uint32_t esel = rs + sel_c - 1;
+    if (j == 0) {
+        *path_s = esel;
+        atomicOr(&bits[xsel >> 5], 1u << (xsel & 31));
+    }
+    cs += s_cost[esel];
+    ++s;
+    u = xsel;
+    rs = sel_y;
+    d = sel_x >> 24;
+    if (u == dst) {
+        ok = true;
+        return false;
+    }
+    return true;
+}
+
+// L consecutive steps, step SL using the Philox word of group lane SL.
+template <int L, int CH, int SL>
+__device__ __forceinline__ bool lds_steps(const uint2 *s_rec, const uint64_t *s_w, const uint32_t *s_cost,
+                                          uint32_t *bits, uint32_t j, uint32_t m_last, uint64_t myr, uint32_t dst,
+                                          uint32_t max_steps, uint32_t NA, uint32_t &u, uint32_t &rs, uint32_t &d,
+                                          uint32_t &s, uint32_t &ncand, uint64_t &cs, bool &ok, uint32_t *path)
+{
+    if (s >= max_steps || !lds_step<L, CH, SL>(s_rec, s_w, s_cost, bits, j, m_last, myr, dst, u, rs, d, s, ncand,
+                                               cs, ok, path + (size_t)s * NA))
+        return false;
+    if constexpr (SL + 1 < L)
+        return lds_steps<L, CH, SL + 1>(s_rec, s_w, s_cost, bits, j, m_last, myr, dst, max_steps, NA, u, rs, d, s,
+                                        ncand, cs, ok, path);
+    return true;
 }
 
 // Walk for graphs whose roads fit in LDS.  One block serves `apb` ants of one
@@ -387,43 +524,48 @@ __device__ __forceinline__ uint64_t group_incl_prefix(uint64_t v, uint32_t j)
 // the head's out-road range and the choice weight tau^alpha * eta^beta
 // (a per-destination choice table), then clears its ants' visited bits.
 // Walk: L lanes per ant; lane j examines candidates j, j+L, ...; the group
-// sums weights by shuffles, and the first candidate (CSR order) whose
-// inclusive prefix exceeds the target is taken.  The L lanes draw Philox
-// words for L consecutive steps at once (the counter does not depend on the
-// path), so one draw serves L steps.
+// sums weights with DPP row shifts, and the candidate whose prefix interval
+// holds the target (the first, in CSR order, whose inclusive prefix exceeds
+// it) is taken.  The L lanes draw Philox words for L consecutive steps at
+// once (the counter does not depend on the path), so one draw serves L
+// steps; the step loop is unrolled by L so each step reads its word with a
+// fixed DPP pattern.  A step is two dependent LDS reads (road record,
+// visited word).  The path cost is summed after the walk, only for ants that
+// arrive.
 template <int L, int CH>
-__global__ __launch_bounds__(256) void k_walk_lds(LdsWalkArgs a)
+__global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
 {
     extern __shared__ uint64_t s_mem[];
     uint2 *s_rec = (uint2 *)s_mem;                   // [m] (head | head_deg << 24, head_row_start)
     uint64_t *s_w = s_mem + a.m;                     // [m] choice weight
-    uint32_t *s_aux = (uint32_t *)(s_mem + 2 * (size_t)a.m);   // goal terms, then visited bits
+    uint32_t *s_cost = (uint32_t *)(s_mem + 2 * (size_t)a.m);  // [m] road cost
+    uint32_t *s_aux = s_cost + ((a.m + 1) & ~1u);    // goal terms, then visited bits
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const uint32_t v = blockIdx.x / a.bpv, part = blockIdx.x % a.bpv;
     const gmacop_od q = a.od[v];
     const bool valid = q.src < a.n && q.dst < a.n && q.src != q.dst;
+    const uint32_t nws = a.nwords | 1u;              // visited words per ant (odd stride spreads banks)
 
-    // ---- prologue: choice table of this vehicle ----
+    // ---- prologue: choice table of this vehicle, one coalesced pass per road ----
     if (valid) {
         const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
         for (uint32_t i = tid; i < a.n; i += nthr) s_aux[i] = (uint32_t)goal_ms(a.x[i], a.y[i], dx, dy, a.kgoal);
     }
     __syncthreads();
     if (valid) {
-        for (uint32_t u = tid; u < a.n; u += nthr) {
-            const uint32_t rs = a.row_ptr[u], re = a.row_ptr[u + 1];
-            const int64_t hu = s_aux[u];
-            for (uint32_t e = rs; e < re; ++e) {
-                const uint32_t xh = a.col[e];
-                const uint32_t xrs = a.row_ptr[xh], xre = a.row_ptr[xh + 1];
-                const uint32_t eta = eta_of((int64_t)a.cost[e] + (int64_t)s_aux[xh] - hu);
-                s_w[e] = ipow_u64(a.tau[e], a.alpha) * ipow_u64(eta, a.beta);
-                s_rec[e] = make_uint2(xh | ((xre - xrs) << 24), xrs);
-            }
+        const bool a1b2 = a.alpha == 1 && a.beta == 2;
+        for (uint32_t e = tid; e < a.m; e += nthr) {
+            const uint2 r = a.rec[e];
+            const uint32_t c = a.cost[e], t = a.tau[e], tl = a.tail[e];
+            const uint32_t xh = r.x & 0xFFFFFFu;
+            const uint32_t eta = eta_of((int64_t)c + (int64_t)s_aux[xh] - (int64_t)s_aux[tl]);
+            s_w[e] = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
+            s_rec[e] = r;
+            s_cost[e] = c;
         }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < a.nwords * a.apb; i += nthr) s_aux[i] = 0;
+    for (uint32_t i = tid; i < nws * a.apb; i += nthr) s_aux[i] = 0;
     __syncthreads();
 
     // ---- walk ----
@@ -432,87 +574,45 @@ __global__ __launch_bounds__(256) void k_walk_lds(LdsWalkArgs a)
     const bool active = valid && grp < a.apb && k < a.ants;
     const uint32_t NA = a.nq * a.ants;
     const uint32_t ant = v * a.ants + k;
-    uint32_t s = 0, ncand = 0, arrived = 0, cs = 0;
+    uint32_t s = 0, ncand = 0, arrived = 0;
     if (active) {
+        uint32_t *bits = s_aux + grp * nws;
         uint32_t u = q.src;
         uint32_t rs = a.row_ptr[u], d = a.row_ptr[u + 1] - rs;
-        if (j == 0) atomicOr(&s_aux[(u >> 5) * a.apb + grp], 1u << (u & 31));
-        uint64_t myr = 0;
+        if (j == 0) atomicOr(&bits[u >> 5], 1u << (u & 31));
         bool ok = false;
-        while (s < a.max_steps) {
-            if ((s % L) == 0) myr = philox_u64(q.qid, k, a.iter, s + j, a.seed_lo, a.seed_hi);
-            const uint64_t r = L == 1 ? myr : __shfl(myr, (int)(s % L), L);
-            ncand += d;
-            uint64_t w[CH], incl[CH];
-            uint2 rec[CH];
-            uint64_t base = 0;
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const uint32_t cand = c * L + j;
-                w[c] = 0;
-                rec[c] = make_uint2(0, 0);
-                if (cand < d) {
-                    const uint32_t e = rs + cand;
-                    rec[c] = s_rec[e];
-                    const uint32_t xh = rec[c].x & 0xFFFFFFu;
-                    const bool seen = (s_aux[(xh >> 5) * a.apb + grp] >> (xh & 31)) & 1u;
-                    w[c] = seen ? 0 : s_w[e];
-                }
-                incl[c] = group_incl_prefix<L>(w[c], j) + base;
-                base = L == 1 ? incl[c] : __shfl(incl[c], L - 1, L);
-            }
-            const uint64_t T = base;
-            if (T == 0) break;   // dead end
-            const uint64_t target = __umul64hi(r, T);
-            uint32_t win_c = 0xFFFFFFFFu, win_j = 0;
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const bool hit = w[c] != 0 && incl[c] - w[c] <= target && target < incl[c];
-                const uint64_t m = __ballot(hit);
-                const uint32_t gm = (uint32_t)(m >> ((threadIdx.x & (kWave - 1)) & ~(uint32_t)(L - 1))) &
-                                    (L >= 32 ? 0xFFFFFFFFu : ((1u << L) - 1u));
-                if (win_c == 0xFFFFFFFFu && gm) {
-                    win_c = c;
-                    win_j = __builtin_ctz(gm);
-                }
-            }
-            if (win_c == 0xFFFFFFFFu) break;   // unreachable when T > 0; keeps every index in range
-            uint2 rsel = make_uint2(0, 0);
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const uint32_t rx = L == 1 ? rec[c].x : __shfl(rec[c].x, (int)win_j, L);
-                const uint32_t ry = L == 1 ? rec[c].y : __shfl(rec[c].y, (int)win_j, L);
-                if ((uint32_t)c == win_c) rsel = make_uint2(rx, ry);
-            }
-            const uint32_t esel = rs + win_c * L + win_j;
-            const uint32_t xsel = rsel.x & 0xFFFFFFu;
-            if (j == 0) {
-                a.path[(size_t)s * NA + ant] = esel;
-                atomicOr(&s_aux[(xsel >> 5) * a.apb + grp], 1u << (xsel & 31));
-            }
-            const uint64_t c2 = (uint64_t)cs + a.cost[esel];
-            cs = c2 > kPathCostCap ? kPathCostCap : (uint32_t)c2;
-            ++s;
-            u = xsel;
-            rs = rsel.y;
-            d = rsel.x >> 24;
-            if (u == q.dst) {
-                ok = true;
+        uint64_t cs64 = 0;
+        const uint32_t m_last = a.m - 1;
+        uint32_t *path = a.path + ant;
+        for (;;) {
+            const uint64_t myr = philox_u64(q.qid, k, a.iter, s + j, a.seed_lo, a.seed_hi);
+            if (!lds_steps<L, CH, 0>(s_rec, s_w, s_cost, bits, j, m_last, myr, q.dst, a.max_steps, NA, u, rs, d, s,
+                                     ncand, cs64, ok, path))
                 break;
+        }
+        const uint32_t cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
+        if (ok) {
+            arrived = 1;
+            const uint64_t dpos = a.q_deposit / cs;
+            if (dpos) {
+                // lane j deposits on roads j, j+L, ...; path entries loaded ahead of the atomics
+                uint32_t i = j;
+                for (; i + 3 * L < s; i += 4 * L) {
+                    const uint32_t e0 = path[(size_t)i * NA], e1 = path[(size_t)(i + L) * NA];
+                    const uint32_t e2 = path[(size_t)(i + 2 * L) * NA], e3 = path[(size_t)(i + 3 * L) * NA];
+                    atomicAdd((unsigned long long *)&a.dep[e0], (unsigned long long)dpos);
+                    atomicAdd((unsigned long long *)&a.dep[e1], (unsigned long long)dpos);
+                    atomicAdd((unsigned long long *)&a.dep[e2], (unsigned long long)dpos);
+                    atomicAdd((unsigned long long *)&a.dep[e3], (unsigned long long)dpos);
+                }
+                for (; i < s; i += L) atomicAdd((unsigned long long *)&a.dep[path[(size_t)i * NA]], (unsigned long long)dpos);
             }
+            if (j == 0)
+                atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
         }
         if (j == 0) {
             a.ant_len[ant] = s;
             a.ant_cost[ant] = ok ? cs : kNoCost;
-        }
-        if (ok) {
-            arrived = 1;
-            const uint64_t dpos = a.q_deposit / cs;
-            if (dpos)
-                for (uint32_t i = j; i < s; i += L)
-                    atomicAdd((unsigned long long *)&a.dep[a.path[(size_t)i * NA + ant]], (unsigned long long)dpos);
-            if (j == 0)
-                atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
         }
     } else if (grp < a.apb && k < a.ants && j == 0) {
         a.ant_len[ant] = 0;
@@ -521,12 +621,14 @@ __global__ __launch_bounds__(256) void k_walk_lds(LdsWalkArgs a)
     // counters: only the first lane of each group contributes
     uint64_t cnt = j == 0 ? s : 0, cand = j == 0 ? ncand : 0, arr = j == 0 ? arrived : 0,
              dh = (j == 0 && arrived) ? s : 0;
+    uint32_t smax = s;
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
         cnt += __shfl_xor(cnt, off);
         cand += __shfl_xor(cand, off);
         arr += __shfl_xor(arr, off);
         dh += __shfl_xor(dh, off);
+        smax = max(smax, (uint32_t)__shfl_xor((int)smax, off));
     }
     if ((threadIdx.x & (kWave - 1)) == 0 && cnt) {
         atomicAdd((unsigned long long *)a.steps, (unsigned long long)cnt);
@@ -534,11 +636,14 @@ __global__ __launch_bounds__(256) void k_walk_lds(LdsWalkArgs a)
         atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)cand);
         atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)arr);
         atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)dh);
+        atomicMax(a.iter_max, smax);
     }
 }
 
 struct BestArgs {
     uint32_t nq, ants, max_steps, load_update;
+    uint32_t *iter_max;
+    uint64_t *counters;
     const uint32_t *path, *ant_len;
     uint64_t *iter_key;
     uint32_t *best_path, *best_len, *best_cost;
@@ -570,6 +675,10 @@ __global__ __launch_bounds__(kWave) void k_best(BestArgs a)
             a.best_len[v] = len;
         }
         a.iter_key[v] = kNoKey;
+        if (v == 0) {   // the walk of this iteration is complete: record its longest ant
+            a.counters[4] += *a.iter_max;
+            *a.iter_max = 0;
+        }
     }
 }
 
@@ -650,7 +759,8 @@ struct gmacop_graph {
     std::vector<uint32_t> inst_off;    // host copy, [n_inst+1]
     // static graph (device)
     uint32_t *row_ptr = nullptr, *col = nullptr, *len_dm = nullptr, *cycle = nullptr, *base_load = nullptr;
-    uint32_t *rev_ptr = nullptr, *rev_edge = nullptr;
+    uint32_t *rev_ptr = nullptr, *rev_edge = nullptr, *tail = nullptr;
+    uint2 *rec = nullptr;              // head | head_out_degree << 24, head's first out-road (n < 2^24)
     uint16_t *speed = nullptr, *green = nullptr;
     int32_t *x = nullptr, *y = nullptr;
     // per-call state (device)
@@ -663,26 +773,31 @@ struct gmacop_graph {
     uint32_t *best_path = nullptr, *best_len = nullptr, *best_cost = nullptr;
     gmacop_od *od = nullptr;
     // statistics
-    uint64_t *counters = nullptr;         // device [4]
+    uint64_t *counters = nullptr;         // device [5]
+    uint32_t *iter_max = nullptr;         // device [1]
     uint64_t launches[4] = {0, 0, 0, 0};
     double ms[4] = {0, 0, 0, 0};
     struct Timed { hipEvent_t a, b; int kernel; };
     std::vector<Timed> pending;           // recorded, not yet summed
     std::vector<hipEvent_t> spare;
+    // captured kernel sequence of the last GMACOP_HIP_GRAPH call and the key of its arguments
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uint64_t> gkey;
 
     ~gmacop_graph()
     {
         (void)hipSetDevice(device);
         dfree(row_ptr); dfree(col); dfree(len_dm); dfree(cycle); dfree(base_load);
-        dfree(rev_ptr); dfree(rev_edge); dfree(speed); dfree(green); dfree(x); dfree(y);
+        dfree(rev_ptr); dfree(rev_edge); dfree(tail); dfree(rec); dfree(speed); dfree(green); dfree(x); dfree(y);
         dfree(t0); dfree(wf); dfree(tau); dfree(load); dfree(cost); dfree(cnt); dfree(dep);
         dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_key); dfree(steps);
-        dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters);
+        dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters); dfree(iter_max);
         for (auto &t : pending) {
             (void)hipEventDestroy(t.a);
             (void)hipEventDestroy(t.b);
         }
         for (auto e : spare) (void)hipEventDestroy(e);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
     }
 };
 
@@ -803,7 +918,7 @@ int validate_params(const gmacop_graph *g, const gmacop_params *p, uint32_t nq)
     if (p->tau_min_q16 > p->tau0_q16 || p->tau0_q16 > p->tau_max_q16)
         return fail(GMACOP_E_INVAL, "need tau_min <= tau0 <= tau_max");
     if (p->mode > GMACOP_MODE_INDEPENDENT) return fail(GMACOP_E_INVAL, "unknown mode %u", p->mode);
-    if (p->flags & ~(GMACOP_NO_LOAD_UPDATE | GMACOP_DEVICE_PTRS | GMACOP_TIME_KERNELS))
+    if (p->flags & ~(GMACOP_NO_LOAD_UPDATE | GMACOP_DEVICE_PTRS | GMACOP_TIME_KERNELS | GMACOP_HIP_GRAPH))
         return fail(GMACOP_E_INVAL, "unknown flags");
     const uint32_t lg = g->max_deg <= 1 ? 0 : bit_length(g->max_deg - 1);
     if ((uint64_t)p->alpha * bit_length(p->tau_max_q16) + 16ull * p->beta + lg > 64)
@@ -841,13 +956,16 @@ struct WalkPlan {
 };
 
 template <int L, int MAXD>
-int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup)
 {
     constexpr int CH = (MAXD + L - 1) / L;
     auto kern = k_walk_lds<L, CH>;
-    if (pl.lds_bytes > 65536)
-        HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)pl.lds_bytes));
+    if (setup) {   // before any launch: allow the block's dynamic LDS
+        if (pl.lds_bytes > 65536)
+            HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)pl.lds_bytes));
+        return GMACOP_OK;
+    }
     const unsigned grid = wa.nq * pl.bpv;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(pl.apb * L), pl.lds_bytes, st, wa);
     HIP_TRY(hipGetLastError());
@@ -855,23 +973,23 @@ int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
 }
 
 template <int L>
-int launch_walk_lds_d(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+int launch_walk_lds_d(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup)
 {
     switch (pl.maxd) {
-    case 4: return launch_walk_lds<L, 4>(wa, pl, st);
-    case 8: return launch_walk_lds<L, 8>(wa, pl, st);
-    case 16: return launch_walk_lds<L, 16>(wa, pl, st);
-    default: return launch_walk_lds<L, 32>(wa, pl, st);
+    case 4: return launch_walk_lds<L, 4>(wa, pl, st, setup);
+    case 8: return launch_walk_lds<L, 8>(wa, pl, st, setup);
+    case 16: return launch_walk_lds<L, 16>(wa, pl, st, setup);
+    default: return launch_walk_lds<L, 32>(wa, pl, st, setup);
     }
 }
 
-int launch_walk_lds_any(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+int launch_walk_lds_any(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup = false)
 {
     switch (pl.lanes) {
-    case 1: return launch_walk_lds_d<1>(wa, pl, st);
-    case 2: return launch_walk_lds_d<2>(wa, pl, st);
-    case 4: return launch_walk_lds_d<4>(wa, pl, st);
-    default: return launch_walk_lds_d<8>(wa, pl, st);
+    case 1: return launch_walk_lds_d<1>(wa, pl, st, setup);
+    case 2: return launch_walk_lds_d<2>(wa, pl, st, setup);
+    case 4: return launch_walk_lds_d<4>(wa, pl, st, setup);
+    default: return launch_walk_lds_d<8>(wa, pl, st, setup);
     }
 }
 
@@ -896,10 +1014,10 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     if (L != 1 && L != 2 && L != 4 && L != 8) L = 4;
     const uint32_t nwords = (g->n + 31) / 32;
     if (!want_global && g->n < (1u << 24)) {
-        uint32_t apb = std::min<uint32_t>(p->ants, 256 / L);
+        uint32_t apb = std::min<uint32_t>(p->ants, 512 / L);
         while (apb >= 1) {
-            const size_t aux = std::max<size_t>(g->n, (size_t)nwords * apb) * 4;
-            const size_t bytes = (size_t)g->m * 16 + aux;
+            const size_t aux = std::max<size_t>(g->n, (size_t)(nwords | 1u) * apb) * 4;
+            const size_t bytes = (size_t)g->m * 16 + (size_t)((g->m + 1) & ~1u) * 4 + aux;
             if (bytes <= (size_t)max_lds) {
                 pl.lds = true;
                 pl.lanes = L;
@@ -950,6 +1068,22 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
         for (uint32_t e = 0; e < g->m; ++e) rev_edge[fill[d->col[e]]++] = e;
     }
     const uint32_t n = g->n, m = g->m;
+    // per-road layout records for the LDS walker: tail, head, head's out-road range
+    std::vector<uint32_t> tail(m);
+    std::vector<uint2> rec(m);
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; ++e) {
+            const uint32_t x = d->col[e];
+            tail[e] = u;
+            const uint32_t deg = d->row_ptr[x + 1] - d->row_ptr[x];
+            rec[e] = make_uint2((x & 0xFFFFFFu) | (std::min(deg, 255u) << 24), d->row_ptr[x]);
+        }
+    if ((rc = upload(&g->tail, tail.data(), m)) || (rc = upload(&g->rec, rec.data(), m))) {
+        std::string keep = t_err;
+        delete g;
+        t_err = keep;
+        return rc;
+    }
     if ((rc = upload(&g->row_ptr, d->row_ptr, n + 1)) || (rc = upload(&g->col, d->col, m)) ||
         (rc = upload(&g->len_dm, d->len_dm, m)) || (rc = upload(&g->speed, d->speed_kmh, m)) ||
         (rc = upload(&g->green, d->green_pm, m)) || (rc = upload(&g->cycle, d->cycle_ms, n)) ||
@@ -957,13 +1091,14 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
         (rc = upload(&g->base_load, d->base_load, m)) || (rc = upload(&g->rev_ptr, rev_ptr.data(), n + 1)) ||
         (rc = upload(&g->rev_edge, rev_edge.data(), m)) || (rc = dalloc(&g->t0, m)) || (rc = dalloc(&g->wf, m)) ||
         (rc = dalloc(&g->tau, m)) || (rc = dalloc(&g->load, m)) || (rc = dalloc(&g->cost, m)) ||
-        (rc = dalloc(&g->cnt, m)) || (rc = dalloc(&g->dep, m)) || (rc = dalloc(&g->counters, 4))) {
+        (rc = dalloc(&g->cnt, m)) || (rc = dalloc(&g->dep, m)) || (rc = dalloc(&g->counters, 5)) || (rc = dalloc(&g->iter_max, 1))) {
         std::string keep = t_err;
         delete g;
         t_err = keep;
         return rc;
     }
-    if (hipMemset(g->counters, 0, 4 * sizeof(uint64_t)) != hipSuccess) {
+    if (hipMemset(g->counters, 0, 5 * sizeof(uint64_t)) != hipSuccess ||
+        hipMemset(g->iter_max, 0, sizeof(uint32_t)) != hipSuccess) {
         delete g;
         return fail(GMACOP_E_DEVICE, "hipMemset of counters failed");
     }
@@ -1035,13 +1170,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     const bool load_update = !(p->flags & GMACOP_NO_LOAD_UPDATE);
     EdgeInitArgs ia{g->m, p->tau0_q16, p->t_max_ms, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
                     g->t0, g->wf, g->tau, g->load, g->cnt, g->dep};
-    hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ia);
-    hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq, best_len,
-                       best_cost, g->iter_key, steps);
     CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost};
-    hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
-    HIP_TRY(hipGetLastError());
-
     WalkArgs wa{};
     wa.row_ptr = g->row_ptr; wa.col = g->col; wa.cost = g->cost; wa.tau = g->tau; wa.x = g->x; wa.y = g->y;
     wa.od = od; wa.n = g->n; wa.nq = nq; wa.ants = p->ants; wa.max_steps = S; wa.alpha = p->alpha; wa.beta = p->beta;
@@ -1049,48 +1178,112 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     wa.nwords = nwords; wa.seed_lo = (uint32_t)p->seed; wa.seed_hi = (uint32_t)(p->seed >> 32);
     wa.q_deposit = p->q_deposit; wa.path = g->path; wa.ant_len = g->ant_len; wa.ant_cost = g->ant_cost;
     wa.gbits = g->gbits; wa.dep = g->dep; wa.iter_key = g->iter_key; wa.steps = steps; wa.counters = g->counters;
+    wa.iter_max = g->iter_max;
     LdsWalkArgs la{};
     la.row_ptr = g->row_ptr; la.col = g->col; la.cost = g->cost; la.tau = g->tau; la.x = g->x; la.y = g->y;
+    la.rec = g->rec; la.tail = g->tail;
     la.od = od; la.n = g->n; la.m = g->m; la.nq = nq; la.ants = p->ants; la.apb = plan.apb; la.bpv = plan.bpv;
     la.max_steps = S; la.alpha = p->alpha; la.beta = p->beta; la.kgoal = wa.kgoal; la.nwords = nwords;
     la.seed_lo = wa.seed_lo; la.seed_hi = wa.seed_hi; la.q_deposit = p->q_deposit; la.path = g->path;
     la.ant_len = g->ant_len; la.ant_cost = g->ant_cost; la.dep = g->dep; la.iter_key = g->iter_key;
-    la.steps = steps; la.counters = g->counters;
-    BestArgs ba{nq, p->ants, S, load_update ? 1u : 0u, g->path, g->ant_len, g->iter_key, best_path, best_len,
-                best_cost, g->cnt};
+    la.steps = steps; la.counters = g->counters; la.iter_max = g->iter_max;
+    BestArgs ba{nq, p->ants, S, load_update ? 1u : 0u, g->iter_max, g->counters, g->path, g->ant_len, g->iter_key,
+                best_path, best_len, best_cost, g->cnt};
     EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, load_update ? 1u : 0u,
                 g->tau, g->load, g->cnt, g->base_load, g->dep};
+    if (plan.lds && (rc = launch_walk_lds_any(la, plan, st, true))) return rc;
 
-    KernelTimer kt{g, st, (p->flags & GMACOP_TIME_KERNELS) != 0};
-    gmacop_graph::Timed tm{};
-    for (uint32_t t = 0; t < p->iterations; ++t) {
-        wa.iter = p->iter_offset + t;
-        const uint32_t md = g->max_deg;
-        if (NA > 0) {
-            if ((rc = kt.start(0, &tm))) return rc;
-            if (plan.lds) {
-                la.iter = wa.iter;
-                rc = launch_walk_lds_any(la, plan, st);
-            } else {
-                rc = md <= 4 ? launch_walk<4>(wa, lds, st)
-                     : md <= 8 ? launch_walk<8>(wa, lds, st)
-                     : md <= 16 ? launch_walk<16>(wa, lds, st)
-                                : launch_walk<32>(wa, lds, st);
-            }
-            if (rc || (rc = kt.stop(&tm))) return rc;
-            if ((rc = kt.start(1, &tm))) return rc;
-            hipLaunchKernelGGL(k_best, dim3(nq), dim3(kWave), 0, st, ba);
-            if ((rc = kt.stop(&tm))) return rc;
-        }
-        if ((rc = kt.start(2, &tm))) return rc;
-        hipLaunchKernelGGL(k_edge, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ea);
-        if ((rc = kt.stop(&tm))) return rc;
-        if (load_update) {
-            if ((rc = kt.start(3, &tm))) return rc;
-            hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
-            if ((rc = kt.stop(&tm))) return rc;
-        }
+    const bool timing = (p->flags & GMACOP_TIME_KERNELS) != 0;
+    const bool use_graph = (p->flags & GMACOP_HIP_GRAPH) && !timing && st != nullptr;
+    // The whole call as one kernel sequence on `st`: initial state and cost
+    // table, then per iteration walk, best route, pheromone/load, cost table.
+    auto enqueue = [&]() -> int {
+        int erc = GMACOP_OK;
+        KernelTimer kt{g, st, timing};
+        gmacop_graph::Timed tm{};
+        hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ia);
+        hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
+                           best_len, best_cost, g->iter_key, steps);
+        hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
         HIP_TRY(hipGetLastError());
+        WalkArgs wt = wa;
+        LdsWalkArgs lt = la;
+        for (uint32_t t = 0; t < p->iterations; ++t) {
+            wt.iter = lt.iter = p->iter_offset + t;
+            const uint32_t md = g->max_deg;
+            if (NA > 0) {
+                if ((erc = kt.start(0, &tm))) return erc;
+                if (plan.lds) {
+                    erc = launch_walk_lds_any(lt, plan, st);
+                } else {
+                    erc = md <= 4 ? launch_walk<4>(wt, lds, st)
+                          : md <= 8 ? launch_walk<8>(wt, lds, st)
+                          : md <= 16 ? launch_walk<16>(wt, lds, st)
+                                     : launch_walk<32>(wt, lds, st);
+                }
+                if (erc || (erc = kt.stop(&tm))) return erc;
+                if ((erc = kt.start(1, &tm))) return erc;
+                hipLaunchKernelGGL(k_best, dim3(nq), dim3(kWave), 0, st, ba);
+                if ((erc = kt.stop(&tm))) return erc;
+            }
+            if ((erc = kt.start(2, &tm))) return erc;
+            hipLaunchKernelGGL(k_edge, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ea);
+            if ((erc = kt.stop(&tm))) return erc;
+            if (load_update) {
+                if ((erc = kt.start(3, &tm))) return erc;
+                hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
+                if ((erc = kt.stop(&tm))) return erc;
+            }
+            HIP_TRY(hipGetLastError());
+        }
+        return GMACOP_OK;
+    };
+
+    if (use_graph) {
+        // key: every value the captured launches depend on
+        std::vector<uint64_t> key = {
+            (uint64_t)(uintptr_t)od, (uint64_t)(uintptr_t)best_path, (uint64_t)(uintptr_t)best_len,
+            (uint64_t)(uintptr_t)best_cost, (uint64_t)(uintptr_t)steps, (uint64_t)(uintptr_t)g->path,
+            (uint64_t)(uintptr_t)g->ant_len, (uint64_t)(uintptr_t)g->ant_cost, (uint64_t)(uintptr_t)g->gbits,
+            (uint64_t)(uintptr_t)g->iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
+            p->rho_q16, p->tau0_q16, p->tau_min_q16, p->tau_max_q16, p->q_deposit, p->theta, p->th_max,
+            p->t_max_ms, p->vmax_kmh, p->mode, p->flags & GMACOP_NO_LOAD_UPDATE, p->seed, p->iter_offset,
+            plan.lds, plan.lanes, plan.apb, plan.bpv, plan.maxd, (uint64_t)plan.lds_bytes, (uint64_t)lds};
+        if (!g->gexec || key != g->gkey) {
+            if (g->gexec) {
+                (void)hipGraphExecDestroy(g->gexec);
+                g->gexec = nullptr;
+            }
+            uint64_t saved[4];
+            memcpy(saved, g->launches, sizeof(saved));
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            rc = enqueue();
+            memcpy(g->launches, saved, sizeof(saved));   // counted per replay below
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ec != hipSuccess) return fail(GMACOP_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+            const hipError_t ei = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                g->gexec = nullptr;
+                return fail(GMACOP_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+            }
+            g->gkey = key;
+        }
+        // launch counts follow the captured sequence
+        if (NA > 0) {
+            g->launches[0] += p->iterations;
+            g->launches[1] += p->iterations;
+        }
+        g->launches[2] += p->iterations;
+        if (load_update) g->launches[3] += p->iterations;
+        HIP_TRY(hipGraphLaunch(g->gexec, st));
+    } else if ((rc = enqueue())) {
+        return rc;
     }
 
     if (!dev_ptrs) {
@@ -1122,7 +1315,7 @@ extern "C" int gmacop_stats_get(gmacop_graph *g, gmacop_stats *s, int reset, voi
     if (!g || !s) return fail(GMACOP_E_INVAL, "graph or stats is NULL");
     HIP_TRY(hipSetDevice(g->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    uint64_t c[4];
+    uint64_t c[5];
     HIP_TRY(hipMemcpyAsync(c, g->counters, sizeof(c), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (auto &t : g->pending) {
@@ -1142,6 +1335,7 @@ extern "C" int gmacop_stats_get(gmacop_graph *g, gmacop_stats *s, int reset, voi
     s->candidates = c[1];
     s->arrivals = c[2];
     s->deposit_roads = c[3];
+    s->longest_walks = c[4];
     if (reset) {
         HIP_TRY(hipMemsetAsync(g->counters, 0, sizeof(c), st));
         HIP_TRY(hipStreamSynchronize(st));

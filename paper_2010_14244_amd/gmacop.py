@@ -29,6 +29,7 @@ NO_LOAD_UPDATE = 1
 DEVICE_PTRS = 2
 
 TIME_KERNELS = 4
+HIP_GRAPH = 8
 
 EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_state_get", "gmacop_stats_get",
             "gmacop_release", "gmacop_last_error")
@@ -68,7 +69,8 @@ class _Result(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("launches", C.c_uint64 * 4), ("ms", C.c_double * 4), ("selections", C.c_uint64),
-                ("candidates", C.c_uint64), ("arrivals", C.c_uint64), ("deposit_roads", C.c_uint64)]
+                ("candidates", C.c_uint64), ("arrivals", C.c_uint64), ("deposit_roads", C.c_uint64),
+                ("longest_walks", C.c_uint64)]
 
 
 _lib = None
@@ -216,7 +218,7 @@ def gmacop_stats_get(g: Graph, reset: bool = False, stream: Optional[int] = None
     return dict(launches={k: int(st.launches[i]) for i, k in enumerate(KERNELS)},
                 ms={k: float(st.ms[i]) for i, k in enumerate(KERNELS)},
                 selections=int(st.selections), candidates=int(st.candidates), arrivals=int(st.arrivals),
-                deposit_roads=int(st.deposit_roads))
+                deposit_roads=int(st.deposit_roads), longest_walks=int(st.longest_walks))
 
 
 def gmacop_release(g: Graph) -> None:

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_struct_layouts_match_header(tmp_path):
     """ctypes mirrors of the ABI structs have the C compiler's sizes and offsets."""
     structs = {"gmacop_graph_desc": gmacop._Desc, "gmacop_od": gmacop._OD, "gmacop_params": gmacop._Params,
-               "gmacop_result": gmacop._Result}
+               "gmacop_result": gmacop._Result, "gmacop_stats": gmacop._Stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gmacop.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -217,3 +217,33 @@ def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes):
     g = planar_graph(1500, rng)
     V = random_od(g.n, 12, rng)
     check(f"planar1500_{kernel}_L{lanes}", g, V, default_params(ants=24, iterations=5, max_steps=300, vmax_kmh=70))
+
+
+def test_hip_graph_replays_match_eager():
+    """The captured kernel sequence, replayed several times with eager calls
+    and host synchronisations in between, gives the eager (and oracle) result
+    every time; a changed argument recaptures."""
+    import torch
+    w = grid32(vehicles=32, ants=24, iterations=7)
+    announce("hip_graph")
+    want = oracle.route(w.graph, w.vehicles, w.params)
+    G = gmacop.gmacop_graph_create(w.graph)
+    stream = torch.cuda.Stream()
+    try:
+        b = gmacop.DeviceBatch(w.vehicles, w.params["max_steps"])
+        pg = dict(w.params, flags=gmacop.HIP_GRAPH)
+        for rep in range(4):
+            gmacop.gmacop_route_batch_device(G, b, pg, stream.cuda_stream)
+            stream.synchronize()
+            assert_same(b.result(), want, w.params["max_steps"], state=False)
+            tau, load = gmacop.gmacop_state_get(G)
+            assert np.array_equal(tau, want["tau"]) and np.array_equal(load, want["load"])
+            eager = gmacop.gmacop_route_batch(G, w.vehicles, w.params)       # eager work between replays
+            assert_same(eager, want, w.params["max_steps"], state=False)
+        p2 = dict(pg, seed=9)
+        want2 = oracle.route(w.graph, w.vehicles, dict(w.params, seed=9))
+        gmacop.gmacop_route_batch_device(G, b, p2, stream.cuda_stream)
+        stream.synchronize()
+        assert_same(b.result(), want2, w.params["max_steps"], state=False)
+    finally:
+        gmacop.gmacop_release(G)
