@@ -357,9 +357,9 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
         atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)cand);
         atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)arr);
         atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)dh);
+        atomicMax(a.iter_max, smax);
     }
 }
-
 
 // ---- lane-group primitives (groups of L aligned lanes inside a 16-lane DPP row) ----
 
