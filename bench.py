@@ -61,6 +61,48 @@ def cpu_baseline(w, iterations):
                       f"({r['steps_total']} selections in {dt:.1f} s, single thread)"}
 
 
+def measure_forms(gmacop, G, w, stream_obj, max_plain=None):
+    """Independent-mode routing of the workload's vehicles, two ways: the
+    plain per-query form (one gmacop_route_batch per vehicle, kernels
+    launched one by one) and the batched form (one call for all vehicles,
+    replayed as a HIP graph).  Per-vehicle results are identical; reports
+    edge-selections/s of both and their ratio."""
+    import numpy as np
+    V = w.vehicles
+    nv = len(V) if max_plain is None else min(len(V), max_plain)
+    p = dict(w.params, mode=gmacop.MODE_INDEPENDENT)
+    stream = stream_obj.cuda_stream
+    sub = type(V)(qid=V.qid[:nv], src=V.src[:nv], dst=V.dst[:nv])
+    batch = gmacop.DeviceBatch(sub, p["max_steps"])
+    pb = dict(p, flags=p["flags"] | gmacop.HIP_GRAPH)
+    gmacop.gmacop_route_batch_device(G, batch, pb, stream)       # warm-up + capture
+    stream_obj.synchronize()
+    t = time.perf_counter()
+    gmacop.gmacop_route_batch_device(G, batch, pb, stream)
+    stream_obj.synchronize()
+    t_batched = time.perf_counter() - t
+    rb = batch.result()
+    singles = [gmacop.DeviceBatch(type(V)(qid=V.qid[i:i + 1], src=V.src[i:i + 1], dst=V.dst[i:i + 1]), p["max_steps"])
+               for i in range(nv)]
+    gmacop.gmacop_route_batch_device(G, singles[0], p, stream)   # warm-up
+    stream_obj.synchronize()
+    t = time.perf_counter()
+    for b in singles:
+        gmacop.gmacop_route_batch_device(G, b, p, stream)
+    stream_obj.synchronize()
+    t_plain = time.perf_counter() - t
+    sel_plain = 0
+    for i, b in enumerate(singles):
+        r = b.result()
+        sel_plain += r["steps_total"]
+        assert r["cost_ms"][0] == rb["cost_ms"][i] and r["path_len"][0] == rb["path_len"][i], i
+    assert sel_plain == rb["steps_total"], (sel_plain, rb["steps_total"])
+    return {"mode": "independent", "vehicles": nv,
+            "plain_per_query": {"value": sel_plain / t_plain, "ms": t_plain * 1e3, "launch": "eager, one call per vehicle"},
+            "batched": {"value": rb["steps_total"] / t_batched, "ms": t_batched * 1e3, "launch": "hip_graph, one call"},
+            "batched_over_plain": t_plain / t_batched}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +114,8 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed pass (roofline becomes null)")
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the plain-per-query vs batched comparison (independent mode)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -161,6 +205,12 @@ def main():
         "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3},
         "roofline": roofline,
     }
+    if not args.no_forms:
+        print("[bench] plain per-query vs batched (independent mode)", file=sys.stderr, flush=True)
+        out["forms"] = measure_forms(gmacop, G, w, stream_obj)
+        f = out["forms"]
+        print(f"[bench] forms: plain {f['plain_per_query']['ms']:.1f} ms, batched {f['batched']['ms']:.1f} ms, "
+              f"ratio {f['batched_over_plain']:.1f}", file=sys.stderr, flush=True)
     gmacop.gmacop_release(G)
     if not args.no_cpu:
         print(f"[bench] timing the CPU oracle on {args.cpu_iterations} iterations", file=sys.stderr, flush=True)

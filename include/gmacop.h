@@ -125,7 +125,11 @@ int gmacop_graph_create(const gmacop_graph_desc *desc, gmacop_graph **out);
 /* Route nq vehicles (Alg. 1 step 3 and Alg. 2, iterated params->iterations
  * times).  Work is ordered on hip_stream (a hipStream_t; NULL = the null
  * stream).  Pheromone starts at tau0 and road loads at base_load on every
- * call.  Without GMACOP_DEVICE_PTRS, q and out are host memory and the call
+ * call.  GMACOP_MODE_SHARED: all vehicles deposit on one pheromone vector and
+ * the loads follow the vehicles' best routes.  GMACOP_MODE_INDEPENDENT: every
+ * vehicle has its own pheromone, loads stay at base_load, and a vehicle's
+ * result does not depend on the other vehicles of the batch (at most 4095
+ * iterations).  Without GMACOP_DEVICE_PTRS, q and out are host memory and the call
  * returns once the results are in them (Alg. 1 step 4).  With it, q and out
  * are device memory, the call only enqueues, and the caller synchronises the
  * stream before reading; q must stay valid until then.
@@ -142,6 +146,12 @@ int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const g
  * pheromone and road load of every road (host arrays of n_edges entries,
  * either may be NULL).  Synchronises hip_stream. */
 int gmacop_state_get(gmacop_graph *g, uint32_t *tau_q16, uint32_t *load, void *hip_stream);
+
+/* Independent mode: pheromone of the vehicle at batch position `vehicle` of
+ * the last gmacop_route_batch call on this graph, after its last iteration
+ * (host array of n_edges entries).  GMACOP_E_INVAL if the last call was not
+ * in independent mode or had no such vehicle.  Synchronises hip_stream. */
+int gmacop_vehicle_tau_get(gmacop_graph *g, uint32_t vehicle, uint32_t *tau_q16, void *hip_stream);
 
 /* Work counters and kernel times accumulated over gmacop_route_batch calls
  * since the last reset.  Kernel index: 0 = walk (tour construction and

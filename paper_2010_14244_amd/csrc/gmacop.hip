@@ -128,6 +128,82 @@ __device__ __forceinline__ uint64_t ipow_u64(uint64_t b, uint32_t e)
     return r;
 }
 
+// Evaporation without deposit, k times: x <- max(tau_min, floor(x (65536 - rho) / 65536)).
+__device__ __forceinline__ uint32_t evaporate_k(uint32_t tau, uint32_t k, uint32_t rho, uint32_t tau_min)
+{
+    for (uint32_t i = 0; i < k && tau > tau_min; ++i) {
+        const uint64_t t = ((uint64_t)tau * (65536u - rho)) >> 16;
+        tau = t < tau_min ? tau_min : (uint32_t)t;
+    }
+    return tau;
+}
+
+// Pheromone as the walkers read it.  Shared mode: one dense vector.
+// Independent mode: every vehicle slot keeps a lazy vector; the entry of a
+// road packs tau (bits 0-31), the iteration it holds for (bits 32-43) and
+// the call generation (bits 44-63).  An entry of another generation was
+// never deposited on in this call and holds the common sequence E^t(tau0);
+// a stored value evaporates forward on read.
+constexpr uint32_t kGenBits = 20;
+constexpr uint32_t kGenMask = (1u << kGenBits) - 1;
+constexpr uint32_t kLazyIterMax = 4095;
+
+struct PherView {
+    const uint32_t *dense;    // shared mode, [m]
+    const uint64_t *lazy;     // independent mode, [slots][m]
+    const uint32_t *gen;      // current call generation (device)
+    uint32_t m, tau0, rho, tau_min;
+};
+
+struct PherRead {
+    const uint32_t *dense;
+    const uint64_t *lazy;     // this slot's row
+    uint32_t gen, t, tau_def, rho, tau_min;
+
+    __device__ __forceinline__ uint32_t operator()(uint32_t e) const
+    {
+        if (dense) return dense[e];
+        const uint64_t x = lazy[e];
+        if ((uint32_t)(x >> 44) != gen) return tau_def;
+        const uint32_t ts = (uint32_t)(x >> 32) & 0xFFFu;
+        return evaporate_k((uint32_t)x, t - ts, rho, tau_min);
+    }
+};
+
+// View of slot v at iteration t (t counts from 0 within the call).
+__device__ __forceinline__ PherRead pher_at(const PherView &pv, uint32_t v, uint32_t t)
+{
+    PherRead r{pv.dense, nullptr, 0, t, 0, pv.rho, pv.tau_min};
+    if (!pv.dense) {
+        r.lazy = pv.lazy + (size_t)v * pv.m;
+        r.gen = *pv.gen & kGenMask;
+        r.tau_def = evaporate_k(pv.tau0, t, pv.rho, pv.tau_min);
+    }
+    return r;
+}
+
+// Deposit accumulators.  Shared mode: one vector.  Independent mode: one per
+// slot, with a list of the roads that received a deposit this iteration.
+struct DepView {
+    uint64_t *dep;            // [m] or [slots][m]
+    uint32_t *touched;        // [slots][cap] (independent mode)
+    uint32_t *touched_n;      // [slots]
+    uint32_t m, cap, indep;
+
+    __device__ __forceinline__ void add(uint32_t v, uint32_t e, uint64_t d) const
+    {
+        if (!indep) {
+            atomicAdd((unsigned long long *)&dep[e], (unsigned long long)d);
+            return;
+        }
+        const unsigned long long old = atomicAdd((unsigned long long *)&dep[(size_t)v * m + e], (unsigned long long)d);
+        if (old == 0) {
+            const uint32_t i = atomicAdd(&touched_n[v], 1u);
+            if (i < cap) touched[(size_t)v * cap + i] = e;
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -212,7 +288,10 @@ __global__ void k_cost(CostArgs a)
 }
 
 struct WalkArgs {
-    const uint32_t *row_ptr, *col, *cost, *tau;
+    const uint32_t *row_ptr, *col, *cost;
+    PherView pher;
+    DepView depv;
+    uint32_t t_local;
     const int32_t *x, *y;
     const gmacop_od *od;
     uint32_t n, nq, ants, max_steps, alpha, beta, kgoal, nwords;
@@ -222,7 +301,6 @@ struct WalkArgs {
     uint32_t *ant_len;     // [NA]
     uint32_t *ant_cost;    // [NA], kNoCost when the ant failed
     uint32_t *gbits;       // [NA][nwords] visited bits when not in LDS
-    uint64_t *dep;         // [m]
     uint64_t *iter_key;    // [nq]
     uint64_t *steps;       // [1] selections of this call
     uint64_t *counters;    // [4] cumulative: selections, candidates examined, arrivals, roads deposited on
@@ -259,6 +337,7 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
 
     uint32_t s = 0, ncand = 0, arrived = 0;
     if (valid) {
+        const PherRead tau = pher_at(a.pher, v, a.t_local);
         const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
         uint32_t u = q.src, cs = 0;
         bool ok = false;
@@ -286,7 +365,7 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
                         const uint32_t c = a.cost[e];
                         const int64_t h = goal_ms(a.x[x], a.y[x], dx, dy, a.kgoal);
                         const uint32_t eta = eta_of((int64_t)c + h - hu);
-                        w[j] = ipow_u64(a.tau[e], a.alpha) * ipow_u64(eta, a.beta);
+                        w[j] = ipow_u64(tau(e), a.alpha) * ipow_u64(eta, a.beta);
                         hx[j] = h;
                         cx[j] = c;
                     }
@@ -328,8 +407,7 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
             arrived = 1;
             const uint64_t dpos = a.q_deposit / cs;
             if (dpos)
-                for (uint32_t i = 0; i < s; ++i) atomicAdd((unsigned long long *)&a.dep[a.path[(size_t)i * NA + ant]],
-                                                           (unsigned long long)dpos);
+                for (uint32_t i = 0; i < s; ++i) a.depv.add(v, a.path[(size_t)i * NA + ant], dpos);
             atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
         }
         if (!LDS_BITS) {
@@ -424,7 +502,10 @@ __device__ __forceinline__ uint64_t grp_bcast(uint64_t v, uint32_t i)
 }
 
 struct LdsWalkArgs {
-    const uint32_t *row_ptr, *col, *cost, *tau;
+    const uint32_t *row_ptr, *col, *cost;
+    PherView pher;
+    DepView depv;
+    uint32_t t_local;
     const uint2 *rec;          // [m] static: head | head_out_degree << 24, head's first out-road
     const uint32_t *tail;      // [m] static: tail node of each road
     const int32_t *x, *y;
@@ -433,7 +514,7 @@ struct LdsWalkArgs {
     uint32_t seed_lo, seed_hi, iter;
     uint64_t q_deposit;
     uint32_t *path, *ant_len, *ant_cost;
-    uint64_t *dep, *iter_key, *steps, *counters;
+    uint64_t *iter_key, *steps, *counters;
     uint32_t *iter_max;    // longest walk of this iteration
 };
 
@@ -554,9 +635,10 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
     __syncthreads();
     if (valid) {
         const bool a1b2 = a.alpha == 1 && a.beta == 2;
+        const PherRead tau = pher_at(a.pher, v, a.t_local);
         for (uint32_t e = tid; e < a.m; e += nthr) {
             const uint2 r = a.rec[e];
-            const uint32_t c = a.cost[e], t = a.tau[e], tl = a.tail[e];
+            const uint32_t c = a.cost[e], t = tau(e), tl = a.tail[e];
             const uint32_t xh = r.x & 0xFFFFFFu;
             const uint32_t eta = eta_of((int64_t)c + (int64_t)s_aux[xh] - (int64_t)s_aux[tl]);
             s_w[e] = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
@@ -600,12 +682,12 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
                 for (; i + 3 * L < s; i += 4 * L) {
                     const uint32_t e0 = path[(size_t)i * NA], e1 = path[(size_t)(i + L) * NA];
                     const uint32_t e2 = path[(size_t)(i + 2 * L) * NA], e3 = path[(size_t)(i + 3 * L) * NA];
-                    atomicAdd((unsigned long long *)&a.dep[e0], (unsigned long long)dpos);
-                    atomicAdd((unsigned long long *)&a.dep[e1], (unsigned long long)dpos);
-                    atomicAdd((unsigned long long *)&a.dep[e2], (unsigned long long)dpos);
-                    atomicAdd((unsigned long long *)&a.dep[e3], (unsigned long long)dpos);
+                    a.depv.add(v, e0, dpos);
+                    a.depv.add(v, e1, dpos);
+                    a.depv.add(v, e2, dpos);
+                    a.depv.add(v, e3, dpos);
                 }
-                for (; i < s; i += L) atomicAdd((unsigned long long *)&a.dep[path[(size_t)i * NA]], (unsigned long long)dpos);
+                for (; i < s; i += L) a.depv.add(v, path[(size_t)i * NA], dpos);
             }
             if (j == 0)
                 atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
@@ -711,6 +793,64 @@ __global__ void k_edge(EdgeArgs a)
     }
 }
 
+struct ApplyArgs {
+    uint32_t m, cap, t_local, tau0, rho, tau_min, tau_max, theta;
+    const uint32_t *load;     // frozen loads
+    const uint32_t *gen;
+    uint64_t *lazy, *dep;
+    uint32_t *touched, *touched_n;
+};
+
+// Independent mode, one block per vehicle slot: for each road deposited on
+// in iteration t, tau(t+1) = clamp(floor(tau(t) (65536-rho)/65536) + D'),
+// D' = D or floor(D theta / load) -- the same update k_edge applies to a
+// dense vector; every other road only evaporates, which its lazy entry
+// already expresses.  Then the deposits and the list are cleared.
+__global__ __launch_bounds__(256) void k_apply_touched(ApplyArgs a)
+{
+    const uint32_t v = blockIdx.x;
+    const uint32_t n = min(a.touched_n[v], a.cap);
+    uint64_t *lazy = a.lazy + (size_t)v * a.m;
+    uint64_t *dep = a.dep + (size_t)v * a.m;
+    const uint32_t gen = *a.gen & kGenMask;
+    const uint32_t tau_def = evaporate_k(a.tau0, a.t_local, a.rho, a.tau_min);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t e = a.touched[(size_t)v * a.cap + i];
+        const uint64_t x = lazy[e];
+        const uint32_t tau = (uint32_t)(x >> 44) == gen
+                                 ? evaporate_k((uint32_t)x, a.t_local - ((uint32_t)(x >> 32) & 0xFFFu), a.rho, a.tau_min)
+                                 : tau_def;
+        const uint64_t D = dep[e];
+        const uint32_t L = a.load[e];
+        uint64_t dp = D;
+        if (L > a.theta) dp = (D / L) * a.theta + ((D % L) * a.theta) / L;
+        uint64_t t = (((uint64_t)tau * (65536u - a.rho)) >> 16) + dp;
+        t = t < a.tau_min ? a.tau_min : (t > a.tau_max ? a.tau_max : t);
+        lazy[e] = t | ((uint64_t)(a.t_local + 1) << 32) | ((uint64_t)gen << 44);
+        dep[e] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.touched_n[v] = 0;
+}
+
+// Dense pheromone of one independent slot after `t_end` iterations.
+__global__ void k_materialize(const uint64_t *lazy_row, const uint32_t *genp, uint32_t m, uint32_t t_end,
+                              uint32_t tau0, uint32_t rho, uint32_t tau_min, uint32_t *out)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint32_t gen = *genp & kGenMask;
+    const uint64_t x = lazy_row[e];
+    out[e] = (uint32_t)(x >> 44) == gen
+                 ? evaporate_k((uint32_t)x, t_end - ((uint32_t)(x >> 32) & 0xFFFu), rho, tau_min)
+                 : evaporate_k(tau0, t_end, rho, tau_min);
+}
+
+__global__ void k_next_generation(uint32_t *gen)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *gen = (*gen + 1) & kGenMask;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -780,6 +920,13 @@ struct gmacop_graph {
     struct Timed { hipEvent_t a, b; int kernel; };
     std::vector<Timed> pending;           // recorded, not yet summed
     std::vector<hipEvent_t> spare;
+    // independent mode: lazy pheromone and deposits per vehicle slot
+    size_t cap_lazy = 0, cap_depi = 0, cap_touch = 0, cap_touchn = 0;
+    uint64_t *lazy = nullptr, *dep_ind = nullptr;
+    uint32_t *touched = nullptr, *touched_n = nullptr, *dev_gen = nullptr;
+    uint32_t gen_count = 0;            // independent calls since the lazy array was cleared
+    uint32_t last_mode = 0, last_nq = 0, last_iters = 0;
+    gmacop_params last_p{};
     // captured kernel sequence of the last GMACOP_HIP_GRAPH call and the key of its arguments
     hipGraphExec_t gexec = nullptr;
     std::vector<uint64_t> gkey;
@@ -792,6 +939,7 @@ struct gmacop_graph {
         dfree(t0); dfree(wf); dfree(tau); dfree(load); dfree(cost); dfree(cnt); dfree(dep);
         dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_key); dfree(steps);
         dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters); dfree(iter_max);
+        dfree(lazy); dfree(dep_ind); dfree(touched); dfree(touched_n); dfree(dev_gen);
         for (auto &t : pending) {
             (void)hipEventDestroy(t.a);
             (void)hipEventDestroy(t.b);
@@ -821,7 +969,10 @@ int grow(T **p, size_t *cap, size_t need, bool zero)
     *cap = 0;
     int rc = dalloc(p, need);
     if (rc) return rc;
-    if (zero) HIP_TRY(hipMemset(*p, 0, need * sizeof(T)));
+    if (zero) {
+        HIP_TRY(hipMemset(*p, 0, need * sizeof(T)));
+        HIP_TRY(hipDeviceSynchronize());   // ordered before work on any stream
+    }
     *cap = need;
     return GMACOP_OK;
 }
@@ -1115,7 +1266,9 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     if (nq > 0 && !q) return fail(GMACOP_E_INVAL, "queries are NULL");
     int rc = validate_params(g, p, nq);
     if (rc) return rc;
-    if (p->mode != GMACOP_MODE_SHARED) return fail(GMACOP_E_UNSUPPORTED, "independent mode is not built yet");
+    const bool indep = p->mode == GMACOP_MODE_INDEPENDENT;
+    if (indep && p->iterations > kLazyIterMax)
+        return fail(GMACOP_E_UNSUPPORTED, "independent mode supports at most %u iterations", kLazyIterMax);
     const bool dev_ptrs = (p->flags & GMACOP_DEVICE_PTRS) != 0;
     if (!dev_ptrs) {
         for (uint32_t i = 0; i < nq; ++i) {
@@ -1127,11 +1280,11 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         }
     }
     HIP_TRY(hipSetDevice(g->device));
-    hipStream_t st = (hipStream_t)hip_stream;
     const uint32_t S = p->max_steps;
     const uint64_t NA = (uint64_t)nq * p->ants;
     const bool lds = g->n <= kLdsBitsetMaxNodes;
     const WalkPlan plan = plan_walk(g, p, g->max_lds);
+    hipStream_t st = (hipStream_t)hip_stream;
     const uint32_t nwords = (g->n + 31) / 32;
 
     // workspace
@@ -1153,6 +1306,29 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     }
     if ((rc = grow(&g->best_path, &g->cap_best, (size_t)nq * S, false))) return rc;
     if (!g->steps && (rc = dalloc(&g->steps, 1))) return rc;
+    const uint32_t tcap = (uint32_t)std::min<uint64_t>(g->m, (uint64_t)p->ants * S);
+    if (indep && nq) {
+        // zero-filled on allocation: deposits and list counts return to zero after every apply
+        const bool fresh_lazy = g->cap_lazy < (size_t)nq * g->m;
+        if ((rc = grow(&g->lazy, &g->cap_lazy, (size_t)nq * g->m, true)) ||
+            (rc = grow(&g->dep_ind, &g->cap_depi, (size_t)nq * g->m, true)) ||
+            (rc = grow(&g->touched, &g->cap_touch, (size_t)nq * tcap, false)) ||
+            (rc = grow(&g->touched_n, &g->cap_touchn, nq, true)))
+            return rc;
+        if (!g->dev_gen) {
+            if ((rc = dalloc(&g->dev_gen, 1))) return rc;
+            HIP_TRY(hipMemset(g->dev_gen, 0, sizeof(uint32_t)));
+            HIP_TRY(hipDeviceSynchronize());
+            g->gen_count = 0;
+        }
+        if (fresh_lazy || g->gen_count >= kGenMask) {
+            // generation numbers would repeat: start over from an all-zero lazy array
+            HIP_TRY(hipMemsetAsync(g->lazy, 0, sizeof(uint64_t) * g->cap_lazy, st));
+            HIP_TRY(hipMemsetAsync(g->dev_gen, 0, sizeof(uint32_t), st));
+            g->gen_count = 0;
+        }
+        g->gen_count++;
+    }
 
     const gmacop_od *od = q;
     uint32_t *best_path = g->best_path, *best_len = g->best_len, *best_cost = g->best_cost;
@@ -1171,26 +1347,37 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     EdgeInitArgs ia{g->m, p->tau0_q16, p->t_max_ms, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
                     g->t0, g->wf, g->tau, g->load, g->cnt, g->dep};
     CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost};
+    PherView pv{};
+    pv.dense = indep ? nullptr : g->tau;
+    pv.lazy = g->lazy;
+    pv.gen = g->dev_gen;
+    pv.m = g->m; pv.tau0 = p->tau0_q16; pv.rho = p->rho_q16; pv.tau_min = p->tau_min_q16;
+    DepView dv{};
+    dv.dep = indep ? g->dep_ind : g->dep;
+    dv.touched = g->touched; dv.touched_n = g->touched_n; dv.m = g->m; dv.cap = tcap; dv.indep = indep ? 1u : 0u;
     WalkArgs wa{};
-    wa.row_ptr = g->row_ptr; wa.col = g->col; wa.cost = g->cost; wa.tau = g->tau; wa.x = g->x; wa.y = g->y;
+    wa.row_ptr = g->row_ptr; wa.col = g->col; wa.cost = g->cost; wa.pher = pv; wa.depv = dv; wa.x = g->x; wa.y = g->y;
     wa.od = od; wa.n = g->n; wa.nq = nq; wa.ants = p->ants; wa.max_steps = S; wa.alpha = p->alpha; wa.beta = p->beta;
     wa.kgoal = p->vmax_kmh ? (uint32_t)((360ull << 16) / p->vmax_kmh) : 0;
     wa.nwords = nwords; wa.seed_lo = (uint32_t)p->seed; wa.seed_hi = (uint32_t)(p->seed >> 32);
     wa.q_deposit = p->q_deposit; wa.path = g->path; wa.ant_len = g->ant_len; wa.ant_cost = g->ant_cost;
-    wa.gbits = g->gbits; wa.dep = g->dep; wa.iter_key = g->iter_key; wa.steps = steps; wa.counters = g->counters;
+    wa.gbits = g->gbits; wa.iter_key = g->iter_key; wa.steps = steps; wa.counters = g->counters;
     wa.iter_max = g->iter_max;
     LdsWalkArgs la{};
-    la.row_ptr = g->row_ptr; la.col = g->col; la.cost = g->cost; la.tau = g->tau; la.x = g->x; la.y = g->y;
+    la.row_ptr = g->row_ptr; la.col = g->col; la.cost = g->cost; la.pher = pv; la.depv = dv; la.x = g->x; la.y = g->y;
     la.rec = g->rec; la.tail = g->tail;
     la.od = od; la.n = g->n; la.m = g->m; la.nq = nq; la.ants = p->ants; la.apb = plan.apb; la.bpv = plan.bpv;
     la.max_steps = S; la.alpha = p->alpha; la.beta = p->beta; la.kgoal = wa.kgoal; la.nwords = nwords;
     la.seed_lo = wa.seed_lo; la.seed_hi = wa.seed_hi; la.q_deposit = p->q_deposit; la.path = g->path;
-    la.ant_len = g->ant_len; la.ant_cost = g->ant_cost; la.dep = g->dep; la.iter_key = g->iter_key;
+    la.ant_len = g->ant_len; la.ant_cost = g->ant_cost; la.iter_key = g->iter_key;
     la.steps = steps; la.counters = g->counters; la.iter_max = g->iter_max;
-    BestArgs ba{nq, p->ants, S, load_update ? 1u : 0u, g->iter_max, g->counters, g->path, g->ant_len, g->iter_key,
+    const bool update_loads = load_update && !indep;
+    BestArgs ba{nq, p->ants, S, update_loads ? 1u : 0u, g->iter_max, g->counters, g->path, g->ant_len, g->iter_key,
                 best_path, best_len, best_cost, g->cnt};
-    EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, load_update ? 1u : 0u,
+    EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, update_loads ? 1u : 0u,
                 g->tau, g->load, g->cnt, g->base_load, g->dep};
+    ApplyArgs aa{g->m, tcap, 0, p->tau0_q16, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, g->load, g->dev_gen,
+                 g->lazy, g->dep_ind, g->touched, g->touched_n};
     if (plan.lds && (rc = launch_walk_lds_any(la, plan, st, true))) return rc;
 
     const bool timing = (p->flags & GMACOP_TIME_KERNELS) != 0;
@@ -1202,14 +1389,17 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         KernelTimer kt{g, st, timing};
         gmacop_graph::Timed tm{};
         hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ia);
+        if (indep && nq) hipLaunchKernelGGL(k_next_generation, dim3(1), dim3(64), 0, st, g->dev_gen);
         hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
                            best_len, best_cost, g->iter_key, steps);
         hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
         HIP_TRY(hipGetLastError());
         WalkArgs wt = wa;
         LdsWalkArgs lt = la;
+        ApplyArgs at = aa;
         for (uint32_t t = 0; t < p->iterations; ++t) {
             wt.iter = lt.iter = p->iter_offset + t;
+            wt.t_local = lt.t_local = at.t_local = t;
             const uint32_t md = g->max_deg;
             if (NA > 0) {
                 if ((erc = kt.start(0, &tm))) return erc;
@@ -1227,9 +1417,13 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
                 if ((erc = kt.stop(&tm))) return erc;
             }
             if ((erc = kt.start(2, &tm))) return erc;
-            hipLaunchKernelGGL(k_edge, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ea);
+            if (indep) {
+                if (nq) hipLaunchKernelGGL(k_apply_touched, dim3(nq), dim3(256), 0, st, at);
+            } else {
+                hipLaunchKernelGGL(k_edge, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ea);
+            }
             if ((erc = kt.stop(&tm))) return erc;
-            if (load_update) {
+            if (update_loads) {
                 if ((erc = kt.start(3, &tm))) return erc;
                 hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
                 if ((erc = kt.stop(&tm))) return erc;
@@ -1248,7 +1442,9 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
             (uint64_t)(uintptr_t)g->iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
             p->rho_q16, p->tau0_q16, p->tau_min_q16, p->tau_max_q16, p->q_deposit, p->theta, p->th_max,
             p->t_max_ms, p->vmax_kmh, p->mode, p->flags & GMACOP_NO_LOAD_UPDATE, p->seed, p->iter_offset,
-            plan.lds, plan.lanes, plan.apb, plan.bpv, plan.maxd, (uint64_t)plan.lds_bytes, (uint64_t)lds};
+            plan.lds, plan.lanes, plan.apb, plan.bpv, plan.maxd, (uint64_t)plan.lds_bytes, (uint64_t)lds,
+            (uint64_t)(uintptr_t)g->lazy, (uint64_t)(uintptr_t)g->dep_ind, (uint64_t)(uintptr_t)g->touched,
+            (uint64_t)(uintptr_t)g->touched_n, (uint64_t)(uintptr_t)g->dev_gen, tcap};
         if (!g->gexec || key != g->gkey) {
             if (g->gexec) {
                 (void)hipGraphExecDestroy(g->gexec);
@@ -1280,7 +1476,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
             g->launches[1] += p->iterations;
         }
         g->launches[2] += p->iterations;
-        if (load_update) g->launches[3] += p->iterations;
+        if (update_loads) g->launches[3] += p->iterations;
         HIP_TRY(hipGraphLaunch(g->gexec, st));
     } else if ((rc = enqueue())) {
         return rc;
@@ -1296,6 +1492,31 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         HIP_TRY(hipMemcpyAsync(out->steps_total, steps, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
+    g->last_mode = p->mode;
+    g->last_nq = nq;
+    g->last_iters = p->iterations;
+    g->last_p = *p;
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_vehicle_tau_get(gmacop_graph *g, uint32_t vehicle, uint32_t *tau_q16, void *hip_stream)
+{
+    if (!g || !tau_q16) return fail(GMACOP_E_INVAL, "graph or output is NULL");
+    if (g->last_mode != GMACOP_MODE_INDEPENDENT || vehicle >= g->last_nq)
+        return fail(GMACOP_E_INVAL, "no independent-mode vehicle %u in the last call", vehicle);
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint32_t *tmp = nullptr;
+    int rc = dalloc(&tmp, g->m);
+    if (rc) return rc;
+    const gmacop_params &p = g->last_p;
+    hipLaunchKernelGGL(k_materialize, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, g->lazy + (size_t)vehicle * g->m,
+                       (const uint32_t *)g->dev_gen, g->m, g->last_iters, p.tau0_q16, p.rho_q16, p.tau_min_q16, tmp);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(tau_q16, tmp, sizeof(uint32_t) * g->m, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(GMACOP_E_DEVICE, "vehicle_tau_get: %s", hipGetErrorString(e));
     return GMACOP_OK;
 }
 

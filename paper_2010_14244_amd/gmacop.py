@@ -31,8 +31,8 @@ DEVICE_PTRS = 2
 TIME_KERNELS = 4
 HIP_GRAPH = 8
 
-EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_state_get", "gmacop_stats_get",
-            "gmacop_release", "gmacop_last_error")
+EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_state_get", "gmacop_vehicle_tau_get",
+            "gmacop_stats_get", "gmacop_release", "gmacop_last_error")
 KERNELS = ("walk", "best", "edge", "cost")
 
 
@@ -94,6 +94,8 @@ def lib():
         L.gmacop_route_batch.restype = C.c_int
         L.gmacop_state_get.argtypes = [vp, vp, vp, vp]
         L.gmacop_state_get.restype = C.c_int
+        L.gmacop_vehicle_tau_get.argtypes = [vp, C.c_uint32, vp, vp]
+        L.gmacop_vehicle_tau_get.restype = C.c_int
         L.gmacop_stats_get.argtypes = [vp, C.POINTER(_Stats), C.c_int, vp]
         L.gmacop_stats_get.restype = C.c_int
         L.gmacop_release.argtypes = [vp]
@@ -209,6 +211,14 @@ def gmacop_state_get(g: Graph, stream: Optional[int] = None):
     load = np.zeros(g.m, np.uint32)
     _check(lib().gmacop_state_get(g.handle, tau.ctypes.data, load.ctypes.data, stream))
     return tau, load
+
+
+def gmacop_vehicle_tau_get(g: Graph, vehicle: int, stream: Optional[int] = None) -> np.ndarray:
+    """Independent mode: pheromone [m] of the vehicle at batch position
+    ``vehicle`` after the last call's final iteration."""
+    tau = np.zeros(g.m, np.uint32)
+    _check(lib().gmacop_vehicle_tau_get(g.handle, int(vehicle), tau.ctypes.data, stream))
+    return tau
 
 
 def gmacop_stats_get(g: Graph, reset: bool = False, stream: Optional[int] = None) -> dict:

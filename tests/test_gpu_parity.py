@@ -247,3 +247,55 @@ def test_hip_graph_replays_match_eager():
         assert_same(b.result(), want2, w.params["max_steps"], state=False)
     finally:
         gmacop.gmacop_release(G)
+
+
+def check_independent(name, g, veh, p):
+    announce(name)
+    want = oracle.route(g, veh, p)
+    G = gmacop.gmacop_graph_create(g)
+    try:
+        got = gmacop.gmacop_route_batch(G, veh, p)
+        assert_same(got, want, p["max_steps"], state=False)
+        for v in range(len(veh)):
+            assert np.array_equal(gmacop.gmacop_vehicle_tau_get(G, v), want["tau"][v]), v
+    finally:
+        gmacop.gmacop_release(G)
+    return got, want
+
+
+@pytest.mark.parametrize("kernel,lanes", [("lds", 4), ("lds", 1), ("global", 1)])
+def test_independent_mode(monkeypatch, kernel, lanes):
+    """Private pheromone per vehicle with frozen loads, both walkers, final
+    pheromone of every vehicle included."""
+    monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
+    monkeypatch.setenv("GMACOP_WALK_LANES", str(lanes))
+    w = grid32(vehicles=20, ants=24, iterations=9)
+    check_independent(f"{w.name}_indep_{kernel}_L{lanes}", w.graph, w.vehicles,
+                      dict(w.params, mode=gmacop.MODE_INDEPENDENT))
+    rng = np.random.default_rng(31)
+    g = planar_graph(5000, rng)
+    V = random_od(g.n, 10, rng)
+    check_independent(f"planar5000_indep_{kernel}_L{lanes}", g, V,
+                      default_params(ants=16, iterations=6, max_steps=400, vmax_kmh=70, mode=gmacop.MODE_INDEPENDENT,
+                                     rho_q16=0x3000))
+
+
+def test_independent_alone_equals_in_mix():
+    """A vehicle's independent-mode result is the same alone and in a batch,
+    and over repeated calls on one handle (generations of lazy pheromone)."""
+    w = grid32(vehicles=12, ants=16, iterations=6)
+    p = dict(w.params, mode=gmacop.MODE_INDEPENDENT)
+    announce("indep_alone_vs_mix")
+    G = gmacop.gmacop_graph_create(w.graph)
+    try:
+        mix = gmacop.gmacop_route_batch(G, w.vehicles, p)
+        for v in (0, 5, 11):
+            one = Vehicles(qid=w.vehicles.qid[v:v + 1], src=w.vehicles.src[v:v + 1], dst=w.vehicles.dst[v:v + 1])
+            alone = gmacop.gmacop_route_batch(G, one, p)
+            L = int(mix["path_len"][v])
+            assert alone["cost_ms"][0] == mix["cost_ms"][v] and alone["path_len"][0] == L
+            assert alone["path_edges"][0, :L].tolist() == mix["path_edges"][v, :L].tolist()
+        again = gmacop.gmacop_route_batch(G, w.vehicles, p)
+        assert_same(again, mix, p["max_steps"], state=False)
+    finally:
+        gmacop.gmacop_release(G)
