@@ -503,6 +503,9 @@ __device__ __forceinline__ uint64_t grp_bcast(uint64_t v, uint32_t i)
 
 struct LdsWalkArgs {
     const uint32_t *row_ptr, *col, *cost;
+    const uint32_t *node_inst, *inst_off, *inst_eoff;   // city of each node; node / road ranges of cities
+    const uint8_t *vclass;     // walker serving each vehicle
+    uint32_t cls;              // the LDS size class this launch serves
     PherView pher;
     DepView depv;
     uint32_t t_local;
@@ -524,8 +527,8 @@ struct LdsWalkArgs {
 template <int L, int CH, int SL>
 __device__ __forceinline__ bool lds_step(const uint2 *s_rec, const uint64_t *s_w, const uint32_t *s_cost,
                                          uint32_t *bits, uint32_t j, uint32_t m_last, uint64_t myr, uint32_t dst,
-                                         uint32_t &u, uint32_t &rs, uint32_t &d, uint32_t &s, uint32_t &ncand,
-                                         uint64_t &cs, bool &ok, uint32_t *path_s)
+                                         uint32_t e_lo, uint32_t &u, uint32_t &rs, uint32_t &d, uint32_t &s,
+                                         uint32_t &ncand, uint64_t &cs, bool &ok, uint32_t *path_s)
 {
     ncand += d;
     uint64_t w[CH], incl[CH];
@@ -568,7 +571,7 @@ __device__ __forceinline__ bool lds_step(const uint2 *s_rec, const uint64_t *s_w
     const uint32_t xsel = sel_x & 0xFFFFFFu;
     const uint32_t esel = rs + sel_c - 1;
     if (j == 0) {
-        *path_s = esel;
+        *path_s = e_lo + esel;
         atomicOr(&bits[xsel >> 5], 1u << (xsel & 31));
     }
     cs += s_cost[esel];
@@ -587,15 +590,16 @@ __device__ __forceinline__ bool lds_step(const uint2 *s_rec, const uint64_t *s_w
 template <int L, int CH, int SL>
 __device__ __forceinline__ bool lds_steps(const uint2 *s_rec, const uint64_t *s_w, const uint32_t *s_cost,
                                           uint32_t *bits, uint32_t j, uint32_t m_last, uint64_t myr, uint32_t dst,
-                                          uint32_t max_steps, uint32_t NA, uint32_t &u, uint32_t &rs, uint32_t &d,
-                                          uint32_t &s, uint32_t &ncand, uint64_t &cs, bool &ok, uint32_t *path)
+                                          uint32_t max_steps, uint32_t NA, uint32_t e_lo, uint32_t &u, uint32_t &rs,
+                                          uint32_t &d, uint32_t &s, uint32_t &ncand, uint64_t &cs, bool &ok,
+                                          uint32_t *path)
 {
-    if (s >= max_steps || !lds_step<L, CH, SL>(s_rec, s_w, s_cost, bits, j, m_last, myr, dst, u, rs, d, s, ncand,
-                                               cs, ok, path + (size_t)s * NA))
+    if (s >= max_steps || !lds_step<L, CH, SL>(s_rec, s_w, s_cost, bits, j, m_last, myr, dst, e_lo, u, rs, d, s,
+                                               ncand, cs, ok, path + (size_t)s * NA))
         return false;
     if constexpr (SL + 1 < L)
-        return lds_steps<L, CH, SL + 1>(s_rec, s_w, s_cost, bits, j, m_last, myr, dst, max_steps, NA, u, rs, d, s,
-                                        ncand, cs, ok, path);
+        return lds_steps<L, CH, SL + 1>(s_rec, s_w, s_cost, bits, j, m_last, myr, dst, max_steps, NA, e_lo, u, rs, d,
+                                        s, ncand, cs, ok, path);
     return true;
 }
 
@@ -617,33 +621,39 @@ template <int L, int CH>
 __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
 {
     extern __shared__ uint64_t s_mem[];
-    uint2 *s_rec = (uint2 *)s_mem;                   // [m] (head | head_deg << 24, head_row_start)
-    uint64_t *s_w = s_mem + a.m;                     // [m] choice weight
-    uint32_t *s_cost = (uint32_t *)(s_mem + 2 * (size_t)a.m);  // [m] road cost
-    uint32_t *s_aux = s_cost + ((a.m + 1) & ~1u);    // goal terms, then visited bits
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const uint32_t v = blockIdx.x / a.bpv, part = blockIdx.x % a.bpv;
+    if (a.vclass[v] != a.cls) return;                // whole block: another walker serves this vehicle
     const gmacop_od q = a.od[v];
-    const bool valid = q.src < a.n && q.dst < a.n && q.src != q.dst;
-    const uint32_t nws = a.nwords | 1u;              // visited words per ant (odd stride spreads banks)
+    // the vehicle's city, in city-local node and road ids
+    const uint32_t city = a.node_inst[q.src];
+    const uint32_t n_lo = a.inst_off[city], n_cnt = a.inst_off[city + 1] - n_lo;
+    const uint32_t e_lo = a.inst_eoff[city], e_cnt = a.inst_eoff[city + 1] - e_lo;
+    uint2 *s_rec = (uint2 *)s_mem;                   // [e_cnt] (head | head_deg << 24, head_row_start)
+    uint64_t *s_w = s_mem + e_cnt;                   // [e_cnt] choice weight
+    uint32_t *s_cost = (uint32_t *)(s_mem + 2 * (size_t)e_cnt);   // [e_cnt] road cost
+    uint32_t *s_aux = s_cost + ((e_cnt + 1) & ~1u);  // goal terms, then visited bits
+    const uint32_t nws = ((n_cnt + 31) / 32) | 1u;   // visited words per ant (odd stride spreads banks)
 
     // ---- prologue: choice table of this vehicle, one coalesced pass per road ----
-    if (valid) {
+    {
         const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
-        for (uint32_t i = tid; i < a.n; i += nthr) s_aux[i] = (uint32_t)goal_ms(a.x[i], a.y[i], dx, dy, a.kgoal);
+        for (uint32_t i = tid; i < n_cnt; i += nthr)
+            s_aux[i] = (uint32_t)goal_ms(a.x[n_lo + i], a.y[n_lo + i], dx, dy, a.kgoal);
     }
     __syncthreads();
-    if (valid) {
+    {
         const bool a1b2 = a.alpha == 1 && a.beta == 2;
         const PherRead tau = pher_at(a.pher, v, a.t_local);
-        for (uint32_t e = tid; e < a.m; e += nthr) {
+        for (uint32_t le = tid; le < e_cnt; le += nthr) {
+            const uint32_t e = e_lo + le;
             const uint2 r = a.rec[e];
-            const uint32_t c = a.cost[e], t = tau(e), tl = a.tail[e];
-            const uint32_t xh = r.x & 0xFFFFFFu;
-            const uint32_t eta = eta_of((int64_t)c + (int64_t)s_aux[xh] - (int64_t)s_aux[tl]);
-            s_w[e] = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
-            s_rec[e] = r;
-            s_cost[e] = c;
+            const uint32_t c = a.cost[e], t = tau(e), tl = a.tail[e] - n_lo;
+            const uint32_t xl = (r.x & 0xFFFFFFu) - n_lo;
+            const uint32_t eta = eta_of((int64_t)c + (int64_t)s_aux[xl] - (int64_t)s_aux[tl]);
+            s_w[le] = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
+            s_rec[le] = make_uint2(xl | (r.x & 0xFF000000u), r.y - e_lo);
+            s_cost[le] = c;
         }
     }
     __syncthreads();
@@ -653,23 +663,23 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
     // ---- walk ----
     const uint32_t grp = tid / L, j = tid % L;
     const uint32_t k = part * a.apb + grp;
-    const bool active = valid && grp < a.apb && k < a.ants;
+    const bool active = grp < a.apb && k < a.ants;
     const uint32_t NA = a.nq * a.ants;
     const uint32_t ant = v * a.ants + k;
     uint32_t s = 0, ncand = 0, arrived = 0;
     if (active) {
         uint32_t *bits = s_aux + grp * nws;
-        uint32_t u = q.src;
-        uint32_t rs = a.row_ptr[u], d = a.row_ptr[u + 1] - rs;
+        uint32_t u = q.src - n_lo;
+        uint32_t rs = a.row_ptr[q.src] - e_lo, d = a.row_ptr[q.src + 1] - a.row_ptr[q.src];
         if (j == 0) atomicOr(&bits[u >> 5], 1u << (u & 31));
         bool ok = false;
         uint64_t cs64 = 0;
-        const uint32_t m_last = a.m - 1;
+        const uint32_t m_last = e_cnt - 1;
         uint32_t *path = a.path + ant;
         for (;;) {
             const uint64_t myr = philox_u64(q.qid, k, a.iter, s + j, a.seed_lo, a.seed_hi);
-            if (!lds_steps<L, CH, 0>(s_rec, s_w, s_cost, bits, j, m_last, myr, q.dst, a.max_steps, NA, u, rs, d, s,
-                                     ncand, cs64, ok, path))
+            if (!lds_steps<L, CH, 0>(s_rec, s_w, s_cost, bits, j, m_last, myr, q.dst - n_lo, a.max_steps, NA, e_lo,
+                                     u, rs, d, s, ncand, cs64, ok, path))
                 break;
         }
         const uint32_t cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
@@ -696,11 +706,255 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
             a.ant_len[ant] = s;
             a.ant_cost[ant] = ok ? cs : kNoCost;
         }
-    } else if (grp < a.apb && k < a.ants && j == 0) {
+    }
+    // counters: only the first lane of each group contributes
+    uint64_t cnt = j == 0 ? s : 0, cand = j == 0 ? ncand : 0, arr = j == 0 ? arrived : 0,
+             dh = (j == 0 && arrived) ? s : 0;
+    uint32_t smax = s;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off);
+        cand += __shfl_xor(cand, off);
+        arr += __shfl_xor(arr, off);
+        dh += __shfl_xor(dh, off);
+        smax = max(smax, (uint32_t)__shfl_xor((int)smax, off));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0 && cnt) {
+        atomicAdd((unsigned long long *)a.steps, (unsigned long long)cnt);
+        atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)cnt);
+        atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)cand);
+        atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)arr);
+        atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)dh);
+        atomicMax(a.iter_max, smax);
+    }
+}
+
+struct GlbWalkArgs {
+    const uint4 *rec16;        // [m] static: head | head_deg << 24, head's first out-road, head x, head y
+    const uint32_t *row_ptr, *cost;
+    const int32_t *x, *y;
+    const uint32_t *node_lo;   // [n] first node of the node's city
+    const uint8_t *vclass;     // [nq] walker serving each vehicle (kWalkerGlobal here)
+    PherView pher;
+    DepView depv;
+    const gmacop_od *od;
+    uint32_t n, m, nq, ants, apb, max_steps, alpha, beta, kgoal;
+    uint32_t nwords;           // visited-bit words per ant (largest city)
+    uint32_t bloom_log2;       // Bloom filter of 2^bloom_log2 bits per ant in LDS
+    uint32_t seed_lo, seed_hi, iter, t_local;
+    uint64_t q_deposit;
+    uint32_t *path, *ant_len, *ant_cost, *gbits;
+    uint64_t *iter_key, *steps, *counters;
+    uint32_t *iter_max;
+};
+
+constexpr uint8_t kWalkerNone = 0, kWalkerGlobal = 8;   // 1..3: LDS walker size classes
+
+__device__ __forceinline__ uint32_t bloom_h1(uint32_t x, uint32_t lg) { return (x * 0x9E3779B1u) >> (32 - lg); }
+__device__ __forceinline__ uint32_t bloom_h2(uint32_t x, uint32_t lg)
+{
+    return ((x ^ 0x5BD1E995u) * 0x85EBCA77u + 0x165667B1u) >> (32 - lg);
+}
+
+// One step of an ant whose roads are read from global memory (k_walk_glb).
+template <int L, int CH, int SL>
+__device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, const PherRead &tau, uint32_t *bloom, uint32_t *gb,
+                                         uint32_t n_lo, int32_t dx, int32_t dy, uint32_t j, uint64_t myr,
+                                         uint32_t dst, uint32_t &u, uint32_t &rs, uint32_t &d, int64_t &hu,
+                                         uint32_t (&hist)[4], uint32_t &s, uint32_t &ncand, uint64_t &cs, bool &ok,
+                                         uint32_t *path_s)
+{
+    ncand += d;
+    const uint32_t lg = a.bloom_log2;
+    uint64_t w[CH], incl[CH];
+    uint4 rec[CH];
+    uint32_t cst[CH];
+    int64_t hx[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const uint32_t idx = min(rs + (uint32_t)(c * L) + j, a.m - 1);   // always a valid address
+        rec[c] = a.rec16[idx];
+        cst[c] = a.cost[idx];
+        w[c] = tau(idx);
+    }
+    uint64_t base = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const uint32_t xh = rec[c].x & 0xFFFFFFu;
+        bool live = (uint32_t)(c * L) + j < d;
+        live = live && xh != hist[0] && xh != hist[1] && xh != hist[2] && xh != hist[3];
+        if (live) {
+            const uint32_t xl = xh - n_lo;
+            const uint32_t b1 = bloom_h1(xl, lg), b2 = bloom_h2(xl, lg);
+            if (((bloom[b1 >> 5] >> (b1 & 31)) & (bloom[b2 >> 5] >> (b2 & 31)) & 1u) != 0) {
+                // Bloom filter says "maybe": the exact bitset decides (read at the device-coherent level)
+                const uint32_t word = __hip_atomic_load(&gb[xl >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                live = ((word >> (xl & 31)) & 1u) == 0;
+            }
+        }
+        hx[c] = 0;
+        if (live) {
+            hx[c] = goal_ms((int32_t)rec[c].z, (int32_t)rec[c].w, dx, dy, a.kgoal);
+            const uint32_t eta = eta_of((int64_t)cst[c] + hx[c] - hu);
+            const uint32_t t = (uint32_t)w[c];
+            w[c] = (a.alpha == 1 && a.beta == 2) ? (uint64_t)t * (eta * eta)
+                                                 : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
+        } else {
+            w[c] = 0;
+        }
+        incl[c] = grp_prefix<L>(w[c], j) + base;
+        base += grp_sum<L>(w[c]);
+    }
+    const uint64_t T = base;
+    if (T == 0) return false;   // dead end
+    uint64_t r = myr;
+    if (L == 2) r = SL == 0 ? dpp64<kDppQuad(0, 0, 2, 2)>(myr) : dpp64<kDppQuad(1, 1, 3, 3)>(myr);
+    if (L == 4) r = dpp64<kDppQuad(SL, SL, SL, SL)>(myr);
+    if (L >= 8) r = __shfl(myr, SL, L);
+    const uint64_t target = __umul64hi(r, T);
+    uint32_t sel_x = 0, sel_y = 0, sel_c = 0, sel_cost = 0, sel_hlo = 0, sel_hhi = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const bool hit = w[c] != 0 && incl[c] - w[c] <= target && target < incl[c];
+        sel_x |= hit ? rec[c].x : 0u;
+        sel_y |= hit ? rec[c].y : 0u;
+        sel_c |= hit ? (uint32_t)(c * L) + j + 1 : 0u;
+        sel_cost |= hit ? cst[c] : 0u;
+        sel_hlo |= hit ? (uint32_t)(uint64_t)hx[c] : 0u;
+        sel_hhi |= hit ? (uint32_t)((uint64_t)hx[c] >> 32) : 0u;
+    }
+    sel_x = grp_or<L>(sel_x);
+    sel_y = grp_or<L>(sel_y);
+    sel_c = grp_or<L>(sel_c);
+    sel_cost = grp_or<L>(sel_cost);
+    sel_hlo = grp_or<L>(sel_hlo);
+    sel_hhi = grp_or<L>(sel_hhi);
+    if (sel_c == 0) return false;   // unreachable when T > 0; keeps every index in range
+    const uint32_t xsel = sel_x & 0xFFFFFFu;
+    if (j == 0) {
+        *path_s = rs + sel_c - 1;
+        const uint32_t xl = xsel - n_lo;
+        const uint32_t b1 = bloom_h1(xl, lg), b2 = bloom_h2(xl, lg);
+        atomicOr(&bloom[b1 >> 5], 1u << (b1 & 31));
+        atomicOr(&bloom[b2 >> 5], 1u << (b2 & 31));
+        atomicOr(&gb[xl >> 5], 1u << (xl & 31));
+    }
+    hist[3] = hist[2];
+    hist[2] = hist[1];
+    hist[1] = hist[0];
+    hist[0] = xsel;
+    cs += sel_cost;
+    hu = (int64_t)(((uint64_t)sel_hhi << 32) | sel_hlo);
+    ++s;
+    u = xsel;
+    rs = sel_y;
+    d = sel_x >> 24;
+    if (u == dst) {
+        ok = true;
+        return false;
+    }
+    return true;
+}
+
+template <int L, int CH, int SL>
+__device__ __forceinline__ bool glb_steps(const GlbWalkArgs &a, const PherRead &tau, uint32_t *bloom, uint32_t *gb,
+                                          uint32_t n_lo, int32_t dx, int32_t dy, uint32_t j, uint64_t myr,
+                                          uint32_t dst, uint32_t NA, uint32_t &u, uint32_t &rs, uint32_t &d,
+                                          int64_t &hu, uint32_t (&hist)[4], uint32_t &s, uint32_t &ncand,
+                                          uint64_t &cs, bool &ok, uint32_t *path)
+{
+    if (s >= a.max_steps || !glb_step<L, CH, SL>(a, tau, bloom, gb, n_lo, dx, dy, j, myr, dst, u, rs, d, hu, hist, s,
+                                                 ncand, cs, ok, path + (size_t)s * NA))
+        return false;
+    if constexpr (SL + 1 < L)
+        return glb_steps<L, CH, SL + 1>(a, tau, bloom, gb, n_lo, dx, dy, j, myr, dst, NA, u, rs, d, hu, hist, s,
+                                        ncand, cs, ok, path);
+    return true;
+}
+
+// Walk for graphs too large for LDS.  L lanes per ant (as in k_walk_lds);
+// each candidate road is one 16-byte record gather (head, head's out-road
+// range, head coordinates) plus its cost and pheromone.  The visited test is
+// exact but rarely touches memory: the last four nodes are kept in
+// registers; then a per-ant Bloom filter in LDS (two hash bits); only when
+// it reports "maybe" is the per-ant bitset in global memory read.  Inserts
+// into both are fire-and-forget atomics; the bitset words are cleared from
+// the path when the walk ends.
+template <int L, int CH>
+__global__ __launch_bounds__(256) void k_walk_glb(GlbWalkArgs a)
+{
+    extern __shared__ uint32_t s_bloom[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t grp = tid / L, j = tid % L;
+    const uint32_t NA = a.nq * a.ants;
+    const uint32_t ant = blockIdx.x * a.apb + grp;
+    const bool in_range = grp < a.apb && ant < NA;
+    const uint32_t v = in_range ? ant / a.ants : 0, k = in_range ? ant % a.ants : 0;
+    gmacop_od q = {0, 0, 0};
+    if (in_range) q = a.od[v];
+    const bool active = in_range && a.vclass[v] == kWalkerGlobal;
+    const uint32_t bws = (1u << (a.bloom_log2 - 5)) | 1u;   // odd stride spreads banks
+    uint32_t *bloom = s_bloom + grp * bws;
+    if (grp < a.apb)
+        for (uint32_t i = j; i < bws; i += L) bloom[i] = 0;
+    uint32_t s = 0, ncand = 0, arrived = 0;
+    if (active) {
+        const PherRead tau = pher_at(a.pher, v, a.t_local);
+        const uint32_t n_lo = a.node_lo[q.src];
+        uint32_t *gb = a.gbits + (size_t)ant * a.nwords;
+        const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
+        uint32_t u = q.src;
+        uint32_t rs = a.row_ptr[u], d = a.row_ptr[u + 1] - rs;
+        int64_t hu = goal_ms(a.x[u], a.y[u], dx, dy, a.kgoal);
+        uint32_t hist[4] = {u, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+        if (j == 0) {
+            const uint32_t ul = u - n_lo;
+            atomicOr(&bloom[bloom_h1(ul, a.bloom_log2) >> 5], 1u << (bloom_h1(ul, a.bloom_log2) & 31));
+            atomicOr(&bloom[bloom_h2(ul, a.bloom_log2) >> 5], 1u << (bloom_h2(ul, a.bloom_log2) & 31));
+            atomicOr(&gb[ul >> 5], 1u << (ul & 31));
+        }
+        bool ok = false;
+        uint64_t cs64 = 0;
+        uint32_t *path = a.path + ant;
+        for (;;) {
+            const uint64_t myr = philox_u64(q.qid, k, a.iter, s + j, a.seed_lo, a.seed_hi);
+            if (!glb_steps<L, CH, 0>(a, tau, bloom, gb, n_lo, dx, dy, j, myr, q.dst, NA, u, rs, d, hu, hist, s, ncand,
+                                     cs64, ok, path))
+                break;
+        }
+        const uint32_t cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
+        if (ok) {
+            arrived = 1;
+            const uint64_t dpos = a.q_deposit / cs;
+            if (dpos) {
+                uint32_t i = j;
+                for (; i + 3 * L < s; i += 4 * L) {
+                    const uint32_t e0 = path[(size_t)i * NA], e1 = path[(size_t)(i + L) * NA];
+                    const uint32_t e2 = path[(size_t)(i + 2 * L) * NA], e3 = path[(size_t)(i + 3 * L) * NA];
+                    a.depv.add(v, e0, dpos);
+                    a.depv.add(v, e1, dpos);
+                    a.depv.add(v, e2, dpos);
+                    a.depv.add(v, e3, dpos);
+                }
+                for (; i < s; i += L) a.depv.add(v, path[(size_t)i * NA], dpos);
+            }
+            if (j == 0)
+                atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
+        }
+        if (j == 0) {
+            a.ant_len[ant] = s;
+            a.ant_cost[ant] = ok ? cs : kNoCost;
+        }
+        // clear this ant's visited words for the next walk
+        if (j == 0) gb[(q.src - n_lo) >> 5] = 0;
+        for (uint32_t i = j; i < s; i += L) {
+            const uint32_t xl = (a.rec16[path[(size_t)i * NA]].x & 0xFFFFFFu) - n_lo;
+            gb[xl >> 5] = 0;
+        }
+    } else if (in_range && j == 0 && a.vclass[v] == kWalkerNone) {
         a.ant_len[ant] = 0;
         a.ant_cost[ant] = kNoCost;
     }
-    // counters: only the first lane of each group contributes
     uint64_t cnt = j == 0 ? s : 0, cand = j == 0 ? ncand : 0, arr = j == 0 ? arrived : 0,
              dh = (j == 0 && arrived) ? s : 0;
     uint32_t smax = s;
@@ -851,6 +1105,23 @@ __global__ void k_next_generation(uint32_t *gen)
     if (threadIdx.x == 0 && blockIdx.x == 0) *gen = (*gen + 1) & kGenMask;
 }
 
+// Which walker serves each vehicle: none for an invalid query (node out of
+// range, src == dst), else the LDS walker when its city's roads fit the LDS
+// budget, else the global-memory walker.
+__global__ void k_classify(const gmacop_od *od, uint32_t nq, uint32_t n, const uint32_t *node_inst,
+                           const uint8_t *inst_fits_lds, uint8_t *vclass)
+{
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nq) return;
+    const gmacop_od q = od[v];
+    uint8_t c = kWalkerNone;
+    if (q.src < n && q.dst < n && q.src != q.dst) {
+        const uint8_t ic = inst_fits_lds[node_inst[q.src]];
+        c = ic ? ic : kWalkerGlobal;
+    }
+    vclass[v] = c;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -901,6 +1172,15 @@ struct gmacop_graph {
     uint32_t *row_ptr = nullptr, *col = nullptr, *len_dm = nullptr, *cycle = nullptr, *base_load = nullptr;
     uint32_t *rev_ptr = nullptr, *rev_edge = nullptr, *tail = nullptr;
     uint2 *rec = nullptr;              // head | head_out_degree << 24, head's first out-road (n < 2^24)
+    uint4 *rec16 = nullptr;            // rec plus head coordinates
+    uint32_t *node_lo = nullptr, *node_inst = nullptr;   // first node / index of each node's city
+    uint32_t *inst_off_dev = nullptr, *inst_eoff_dev = nullptr;   // node / road range of each city
+    uint8_t *inst_fits = nullptr;      // per city: served by the LDS walker in the current plan
+    uint8_t *vclass = nullptr;         // per vehicle: walker of the current call
+    size_t cap_vclass = 0;
+    uint32_t max_city_nodes = 0;
+    std::vector<uint8_t> city_class_dev;   // host copy of inst_fits
+    std::vector<uint32_t> inst_eoff;   // host: first road of each city
     uint16_t *speed = nullptr, *green = nullptr;
     int32_t *x = nullptr, *y = nullptr;
     // per-call state (device)
@@ -935,7 +1215,8 @@ struct gmacop_graph {
     {
         (void)hipSetDevice(device);
         dfree(row_ptr); dfree(col); dfree(len_dm); dfree(cycle); dfree(base_load);
-        dfree(rev_ptr); dfree(rev_edge); dfree(tail); dfree(rec); dfree(speed); dfree(green); dfree(x); dfree(y);
+        dfree(rev_ptr); dfree(rev_edge); dfree(tail); dfree(rec); dfree(rec16); dfree(node_lo); dfree(node_inst);
+        dfree(inst_fits); dfree(vclass); dfree(inst_off_dev); dfree(inst_eoff_dev); dfree(speed); dfree(green); dfree(x); dfree(y);
         dfree(t0); dfree(wf); dfree(tau); dfree(load); dfree(cost); dfree(cnt); dfree(dep);
         dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_key); dfree(steps);
         dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters); dfree(iter_max);
@@ -1098,12 +1379,14 @@ int launch_walk(const WalkArgs &wa, bool lds, hipStream_t st)
 }
 
 struct WalkPlan {
-    bool lds = false;        // roads staged in LDS (k_walk_lds), else k_walk
-    uint32_t lanes = 1;      // lanes per ant (k_walk_lds)
-    uint32_t apb = 0;        // ants per block (k_walk_lds)
-    uint32_t bpv = 0;        // blocks per vehicle (k_walk_lds)
-    size_t lds_bytes = 0;
-    uint32_t maxd = 4;       // candidate bound the kernel is built for
+    uint32_t maxd = 4;             // candidate bound the kernels are built for
+    bool legacy = false;           // k_walk for every vehicle (graphs with 2^24 nodes or more)
+    uint32_t lds_lanes = 4, lds_apb = 0, lds_bpv = 0;
+    size_t lds_bytes[4] = {0, 0, 0, 0};   // [1..3]: dynamic LDS of each LDS size-class launch, 0 = none
+    bool glb = false;              // some city is served by k_walk_glb
+    uint32_t glb_lanes = 4, glb_apb = 0, bloom_log2 = 11, glb_nwords = 0;
+    size_t glb_lds_bytes = 0;
+    std::vector<uint8_t> city_class;      // per city: LDS class 1..3, or 0 = global walker
 };
 
 template <int L, int MAXD>
@@ -1111,14 +1394,14 @@ int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, b
 {
     constexpr int CH = (MAXD + L - 1) / L;
     auto kern = k_walk_lds<L, CH>;
-    if (setup) {   // before any launch: allow the block's dynamic LDS
-        if (pl.lds_bytes > 65536)
-            HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)pl.lds_bytes));
+    if (setup) {   // before any launch: allow the largest dynamic LDS of the plan
+        const size_t mx = std::max(pl.lds_bytes[1], std::max(pl.lds_bytes[2], pl.lds_bytes[3]));
+        if (mx > 65536)
+            HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mx));
         return GMACOP_OK;
     }
-    const unsigned grid = wa.nq * pl.bpv;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(pl.apb * L), pl.lds_bytes, st, wa);
+    const unsigned grid = wa.nq * pl.lds_bpv;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(pl.lds_apb * L), pl.lds_bytes[wa.cls], st, wa);
     HIP_TRY(hipGetLastError());
     return GMACOP_OK;
 }
@@ -1136,11 +1419,43 @@ int launch_walk_lds_d(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st,
 
 int launch_walk_lds_any(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup = false)
 {
-    switch (pl.lanes) {
+    switch (pl.lds_lanes) {
     case 1: return launch_walk_lds_d<1>(wa, pl, st, setup);
     case 2: return launch_walk_lds_d<2>(wa, pl, st, setup);
     case 4: return launch_walk_lds_d<4>(wa, pl, st, setup);
     default: return launch_walk_lds_d<8>(wa, pl, st, setup);
+    }
+}
+
+template <int L, int MAXD>
+int launch_walk_glb(const GlbWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+{
+    constexpr int CH = (MAXD + L - 1) / L;
+    const uint64_t NA = (uint64_t)wa.nq * wa.ants;
+    hipLaunchKernelGGL((k_walk_glb<L, CH>), dim3(blocks_for(NA, pl.glb_apb)), dim3(pl.glb_apb * L), pl.glb_lds_bytes,
+                       st, wa);
+    HIP_TRY(hipGetLastError());
+    return GMACOP_OK;
+}
+
+template <int L>
+int launch_walk_glb_d(const GlbWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+{
+    switch (pl.maxd) {
+    case 4: return launch_walk_glb<L, 4>(wa, pl, st);
+    case 8: return launch_walk_glb<L, 8>(wa, pl, st);
+    case 16: return launch_walk_glb<L, 16>(wa, pl, st);
+    default: return launch_walk_glb<L, 32>(wa, pl, st);
+    }
+}
+
+int launch_walk_glb_any(const GlbWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
+{
+    switch (pl.glb_lanes) {
+    case 1: return launch_walk_glb_d<1>(wa, pl, st);
+    case 2: return launch_walk_glb_d<2>(wa, pl, st);
+    case 4: return launch_walk_glb_d<4>(wa, pl, st);
+    default: return launch_walk_glb_d<8>(wa, pl, st);
     }
 }
 
@@ -1150,36 +1465,48 @@ uint32_t env_u32(const char *name, uint32_t dflt)
     return (v && *v) ? (uint32_t)strtoul(v, nullptr, 10) : dflt;
 }
 
-// Choose the walk kernel and its shape.  k_walk_lds when the roads, the goal
-// terms and the visited bits of a block fit the device's LDS per block;
-// otherwise the global-memory walker.  GMACOP_WALK_LANES (1, 2, 4, 8) and
-// GMACOP_WALK_KERNEL (lds | global) override the choice for tuning; results
-// do not depend on it.
+uint32_t lanes_or(uint32_t L, uint32_t dflt) { return (L == 1 || L == 2 || L == 4 || L == 8) ? L : dflt; }
+
+// The per-size schedule.  Every city whose roads, goal terms and visited
+// bits fit in LDS goes to k_walk_lds, in one of three size classes (up to a
+// quarter, a half, or all of the LDS a block may use), so small cities are
+// not charged the largest city's LDS; larger cities go to k_walk_glb.
+// GMACOP_WALK_KERNEL (lds | global | legacy), GMACOP_WALK_LANES,
+// GMACOP_GLB_LANES (1, 2, 4, 8) and GMACOP_BLOOM_LOG2 (8..16) override the
+// choices for tuning; results do not depend on them.
 WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
 {
     WalkPlan pl;
     pl.maxd = g->max_deg <= 4 ? 4 : g->max_deg <= 8 ? 8 : g->max_deg <= 16 ? 16 : 32;
     const char *kind = getenv("GMACOP_WALK_KERNEL");
-    const bool want_global = kind && strcmp(kind, "global") == 0;
-    uint32_t L = env_u32("GMACOP_WALK_LANES", g->max_deg <= 4 ? 4 : 8);
-    if (L != 1 && L != 2 && L != 4 && L != 8) L = 4;
-    const uint32_t nwords = (g->n + 31) / 32;
-    if (!want_global && g->n < (1u << 24)) {
-        uint32_t apb = std::min<uint32_t>(p->ants, 512 / L);
-        while (apb >= 1) {
-            const size_t aux = std::max<size_t>(g->n, (size_t)(nwords | 1u) * apb) * 4;
-            const size_t bytes = (size_t)g->m * 16 + (size_t)((g->m + 1) & ~1u) * 4 + aux;
-            if (bytes <= (size_t)max_lds) {
-                pl.lds = true;
-                pl.lanes = L;
-                pl.apb = apb;
-                pl.bpv = (p->ants + apb - 1) / apb;
-                pl.lds_bytes = bytes;
-                break;
-            }
-            apb /= 2;
-        }
+    const bool force_global = kind && strcmp(kind, "global") == 0;
+    pl.legacy = (kind && strcmp(kind, "legacy") == 0) || g->n >= (1u << 24);
+    pl.city_class.assign(g->n_inst, 0);
+    if (pl.legacy) return pl;
+    pl.lds_lanes = lanes_or(env_u32("GMACOP_WALK_LANES", 4), 4);
+    pl.lds_apb = std::max<uint32_t>(1, std::min<uint32_t>(p->ants, 512 / pl.lds_lanes));
+    pl.lds_bpv = (p->ants + pl.lds_apb - 1) / pl.lds_apb;
+    const size_t t3 = (size_t)max_lds, t2 = t3 / 2, t1 = t3 / 4;
+    uint32_t glb_nodes = 0;
+    for (uint32_t i = 0; i < g->n_inst; ++i) {
+        const uint32_t nc = g->inst_off[i + 1] - g->inst_off[i];
+        const uint32_t ec = g->inst_eoff[i + 1] - g->inst_eoff[i];
+        const size_t need = (size_t)ec * 16 + (size_t)((ec + 1) & ~1u) * 4 +
+                            std::max<size_t>(nc, (size_t)(((nc + 31) / 32) | 1u) * pl.lds_apb) * 4;
+        uint8_t c = 0;
+        if (!force_global && ec > 0) c = need <= t1 ? 1 : need <= t2 ? 2 : need <= t3 ? 3 : 0;
+        pl.city_class[i] = c;
+        if (c)
+            pl.lds_bytes[c] = std::max(pl.lds_bytes[c], need);
+        else
+            glb_nodes = std::max(glb_nodes, nc);
     }
+    pl.glb = glb_nodes > 0;
+    pl.glb_lanes = lanes_or(env_u32("GMACOP_GLB_LANES", 4), 4);
+    pl.glb_apb = 256 / pl.glb_lanes;
+    pl.bloom_log2 = std::min<uint32_t>(16, std::max<uint32_t>(8, env_u32("GMACOP_BLOOM_LOG2", 11)));
+    pl.glb_lds_bytes = (size_t)pl.glb_apb * ((1u << (pl.bloom_log2 - 5)) | 1u) * 4;
+    pl.glb_nwords = (glb_nodes + 31) / 32;
     return pl;
 }
 
@@ -1229,7 +1556,27 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
             const uint32_t deg = d->row_ptr[x + 1] - d->row_ptr[x];
             rec[e] = make_uint2((x & 0xFFFFFFu) | (std::min(deg, 255u) << 24), d->row_ptr[x]);
         }
-    if ((rc = upload(&g->tail, tail.data(), m)) || (rc = upload(&g->rec, rec.data(), m))) {
+    std::vector<uint4> rec16(m);
+    for (uint32_t e = 0; e < m; ++e) {
+        const uint32_t x = d->col[e];
+        rec16[e] = make_uint4(rec[e].x, rec[e].y, (uint32_t)d->x_dm[x], (uint32_t)d->y_dm[x]);
+    }
+    std::vector<uint32_t> node_lo(n), node_inst(n);
+    g->inst_eoff.resize(g->n_inst + 1);
+    for (uint32_t i = 0; i < g->n_inst; ++i) {
+        g->inst_eoff[i] = d->row_ptr[g->inst_off[i]];
+        g->max_city_nodes = std::max(g->max_city_nodes, g->inst_off[i + 1] - g->inst_off[i]);
+        for (uint32_t u = g->inst_off[i]; u < g->inst_off[i + 1]; ++u) {
+            node_lo[u] = g->inst_off[i];
+            node_inst[u] = i;
+        }
+    }
+    g->inst_eoff[g->n_inst] = m;
+    if ((rc = upload(&g->tail, tail.data(), m)) || (rc = upload(&g->rec, rec.data(), m)) ||
+        (rc = upload(&g->rec16, rec16.data(), m)) || (rc = upload(&g->node_lo, node_lo.data(), n)) ||
+        (rc = upload(&g->node_inst, node_inst.data(), n)) || (rc = dalloc(&g->inst_fits, g->n_inst)) ||
+        (rc = upload(&g->inst_off_dev, g->inst_off.data(), g->n_inst + 1)) ||
+        (rc = upload(&g->inst_eoff_dev, g->inst_eoff.data(), g->n_inst + 1))) {
         std::string keep = t_err;
         delete g;
         t_err = keep;
@@ -1296,7 +1643,14 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         if ((rc = grow(&g->ant_cost, &c2, NA, false))) return rc;
         g->cap_ants = std::min(c1, c2);
     }
-    if (!plan.lds && !lds && (rc = grow(&g->gbits, &g->cap_bits, (size_t)NA * nwords, true))) return rc;
+    if (plan.legacy && !lds && (rc = grow(&g->gbits, &g->cap_bits, (size_t)NA * nwords, true))) return rc;
+    if (!plan.legacy && plan.glb && (rc = grow(&g->gbits, &g->cap_bits, (size_t)NA * plan.glb_nwords, true)))
+        return rc;
+    if ((rc = grow(&g->vclass, &g->cap_vclass, std::max<size_t>(nq, 1), false))) return rc;
+    if (plan.city_class != g->city_class_dev) {   // per-city walker choice, uploaded when it changes
+        HIP_TRY(hipMemcpy(g->inst_fits, plan.city_class.data(), g->n_inst, hipMemcpyHostToDevice));
+        g->city_class_dev = plan.city_class;
+    }
     {
         size_t c1 = g->cap_veh, c2 = g->cap_veh, c3 = g->cap_veh, c4 = g->cap_veh;
         if ((rc = grow(&g->iter_key, &c1, nq, false)) || (rc = grow(&g->best_len, &c2, nq, false)) ||
@@ -1366,7 +1720,8 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     LdsWalkArgs la{};
     la.row_ptr = g->row_ptr; la.col = g->col; la.cost = g->cost; la.pher = pv; la.depv = dv; la.x = g->x; la.y = g->y;
     la.rec = g->rec; la.tail = g->tail;
-    la.od = od; la.n = g->n; la.m = g->m; la.nq = nq; la.ants = p->ants; la.apb = plan.apb; la.bpv = plan.bpv;
+    la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev; la.inst_eoff = g->inst_eoff_dev; la.vclass = g->vclass;
+    la.od = od; la.n = g->n; la.m = g->m; la.nq = nq; la.ants = p->ants; la.apb = plan.lds_apb; la.bpv = plan.lds_bpv;
     la.max_steps = S; la.alpha = p->alpha; la.beta = p->beta; la.kgoal = wa.kgoal; la.nwords = nwords;
     la.seed_lo = wa.seed_lo; la.seed_hi = wa.seed_hi; la.q_deposit = p->q_deposit; la.path = g->path;
     la.ant_len = g->ant_len; la.ant_cost = g->ant_cost; la.iter_key = g->iter_key;
@@ -1378,7 +1733,16 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
                 g->tau, g->load, g->cnt, g->base_load, g->dep};
     ApplyArgs aa{g->m, tcap, 0, p->tau0_q16, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, g->load, g->dev_gen,
                  g->lazy, g->dep_ind, g->touched, g->touched_n};
-    if (plan.lds && (rc = launch_walk_lds_any(la, plan, st, true))) return rc;
+    GlbWalkArgs ga{};
+    ga.rec16 = g->rec16; ga.row_ptr = g->row_ptr; ga.cost = g->cost; ga.x = g->x; ga.y = g->y; ga.node_lo = g->node_lo;
+    ga.vclass = g->vclass; ga.pher = pv; ga.depv = dv; ga.od = od; ga.n = g->n; ga.m = g->m; ga.nq = nq;
+    ga.ants = p->ants; ga.apb = plan.glb_apb; ga.max_steps = S; ga.alpha = p->alpha; ga.beta = p->beta;
+    ga.kgoal = wa.kgoal; ga.nwords = plan.glb_nwords; ga.bloom_log2 = plan.bloom_log2; ga.seed_lo = wa.seed_lo;
+    ga.seed_hi = wa.seed_hi; ga.q_deposit = p->q_deposit; ga.path = g->path; ga.ant_len = g->ant_len;
+    ga.ant_cost = g->ant_cost; ga.gbits = g->gbits; ga.iter_key = g->iter_key; ga.steps = steps;
+    ga.counters = g->counters; ga.iter_max = g->iter_max;
+    const bool any_lds = !plan.legacy && (plan.lds_bytes[1] || plan.lds_bytes[2] || plan.lds_bytes[3]);
+    if (any_lds && (rc = launch_walk_lds_any(la, plan, st, true))) return rc;
 
     const bool timing = (p->flags & GMACOP_TIME_KERNELS) != 0;
     const bool use_graph = (p->flags & GMACOP_HIP_GRAPH) && !timing && st != nullptr;
@@ -1393,23 +1757,32 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
                            best_len, best_cost, g->iter_key, steps);
         hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
+        if (nq && !plan.legacy)
+            hipLaunchKernelGGL(k_classify, dim3(blocks_for(nq, 256)), dim3(256), 0, st, od, nq, g->n,
+                               (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, g->vclass);
         HIP_TRY(hipGetLastError());
         WalkArgs wt = wa;
         LdsWalkArgs lt = la;
+        GlbWalkArgs gt = ga;
         ApplyArgs at = aa;
         for (uint32_t t = 0; t < p->iterations; ++t) {
-            wt.iter = lt.iter = p->iter_offset + t;
-            wt.t_local = lt.t_local = at.t_local = t;
+            wt.iter = lt.iter = gt.iter = p->iter_offset + t;
+            wt.t_local = lt.t_local = gt.t_local = at.t_local = t;
             const uint32_t md = g->max_deg;
             if (NA > 0) {
                 if ((erc = kt.start(0, &tm))) return erc;
-                if (plan.lds) {
-                    erc = launch_walk_lds_any(lt, plan, st);
-                } else {
+                if (plan.legacy) {
                     erc = md <= 4 ? launch_walk<4>(wt, lds, st)
                           : md <= 8 ? launch_walk<8>(wt, lds, st)
                           : md <= 16 ? launch_walk<16>(wt, lds, st)
                                      : launch_walk<32>(wt, lds, st);
+                } else {
+                    for (uint32_t c = 1; c <= 3 && !erc; ++c)
+                        if (plan.lds_bytes[c]) {
+                            lt.cls = c;
+                            erc = launch_walk_lds_any(lt, plan, st);
+                        }
+                    if (!erc && plan.glb) erc = launch_walk_glb_any(gt, plan, st);
                 }
                 if (erc || (erc = kt.stop(&tm))) return erc;
                 if ((erc = kt.start(1, &tm))) return erc;
@@ -1442,7 +1815,9 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
             (uint64_t)(uintptr_t)g->iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
             p->rho_q16, p->tau0_q16, p->tau_min_q16, p->tau_max_q16, p->q_deposit, p->theta, p->th_max,
             p->t_max_ms, p->vmax_kmh, p->mode, p->flags & GMACOP_NO_LOAD_UPDATE, p->seed, p->iter_offset,
-            plan.lds, plan.lanes, plan.apb, plan.bpv, plan.maxd, (uint64_t)plan.lds_bytes, (uint64_t)lds,
+            plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, (uint64_t)plan.lds_bytes[1],
+            (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3], plan.glb, plan.glb_lanes, plan.glb_apb,
+            plan.bloom_log2, plan.glb_nwords, (uint64_t)lds, (uint64_t)(uintptr_t)g->vclass,
             (uint64_t)(uintptr_t)g->lazy, (uint64_t)(uintptr_t)g->dep_ind, (uint64_t)(uintptr_t)g->touched,
             (uint64_t)(uintptr_t)g->touched_n, (uint64_t)(uintptr_t)g->dev_gen, tcap};
         if (!g->gexec || key != g->gkey) {

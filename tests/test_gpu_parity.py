@@ -205,18 +205,40 @@ def test_grid32_full_against_stored_oracle_results():
     assert hashlib.sha256(got["load"].tobytes()).hexdigest() == want["load_sha256"]
 
 
-@pytest.mark.parametrize("kernel,lanes", [("global", 1), ("lds", 1), ("lds", 2), ("lds", 4), ("lds", 8)])
-def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes):
-    """Every walker shape (global-memory or LDS-staged roads, 1-8 lanes per
-    ant) reproduces the oracle exactly."""
+@pytest.mark.parametrize("kernel,lanes,bloom", [("legacy", 1, 11), ("global", 1, 11), ("global", 2, 11),
+                                                ("global", 4, 11), ("global", 8, 11), ("global", 4, 8),
+                                                ("lds", 1, 11), ("lds", 2, 11), ("lds", 4, 11), ("lds", 8, 11)])
+def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes, bloom):
+    """Every walker shape (first global-memory walker, global walker with
+    1-8 lanes per ant and a small Bloom filter that sends most visited tests
+    to the exact bitset, LDS-staged roads with 1-8 lanes) reproduces the
+    oracle exactly."""
     monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
     monkeypatch.setenv("GMACOP_WALK_LANES", str(lanes))
+    monkeypatch.setenv("GMACOP_GLB_LANES", str(lanes))
+    monkeypatch.setenv("GMACOP_BLOOM_LOG2", str(bloom))
     w = grid32(vehicles=24, ants=40, iterations=6)
-    check(f"{w.name}_{kernel}_L{lanes}", w.graph, w.vehicles, w.params)
+    check(f"{w.name}_{kernel}_L{lanes}_b{bloom}", w.graph, w.vehicles, w.params)
     rng = np.random.default_rng(23)
     g = planar_graph(1500, rng)
     V = random_od(g.n, 12, rng)
-    check(f"planar1500_{kernel}_L{lanes}", g, V, default_params(ants=24, iterations=5, max_steps=300, vmax_kmh=70))
+    check(f"planar1500_{kernel}_L{lanes}_b{bloom}", g, V,
+          default_params(ants=24, iterations=5, max_steps=300, vmax_kmh=70))
+
+
+def test_mixed_walkers_in_one_iteration():
+    """Packed cities where small ones are served from LDS and a large one by
+    the global walker, all depositing on one shared pheromone vector."""
+    rng = np.random.default_rng(41)
+    gs = [grid_graph(4, 6, rng), planar_graph(12000, rng), planar_graph(900, rng), grid_graph(9, 9, rng)]
+    packed = pack_graphs(gs)
+    off = packed.inst_node_off.astype(np.int64)
+    vs = [random_od(gi.n, 5, rng, node_lo=int(off[i]), qid0=5 * i) for i, gi in enumerate(gs)]
+    V = Vehicles(qid=np.concatenate([v.qid for v in vs]), src=np.concatenate([v.src for v in vs]),
+                 dst=np.concatenate([v.dst for v in vs]))
+    p = default_params(ants=16, iterations=5, max_steps=500, vmax_kmh=70)
+    check("mixed_cities", packed, V, p)
+    check("mixed_cities_indep", packed, V, dict(p, mode=gmacop.MODE_INDEPENDENT), state=False)
 
 
 def test_hip_graph_replays_match_eager():
@@ -263,12 +285,13 @@ def check_independent(name, g, veh, p):
     return got, want
 
 
-@pytest.mark.parametrize("kernel,lanes", [("lds", 4), ("lds", 1), ("global", 1)])
+@pytest.mark.parametrize("kernel,lanes", [("lds", 4), ("lds", 1), ("global", 4), ("global", 1), ("legacy", 1)])
 def test_independent_mode(monkeypatch, kernel, lanes):
     """Private pheromone per vehicle with frozen loads, both walkers, final
     pheromone of every vehicle included."""
     monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
     monkeypatch.setenv("GMACOP_WALK_LANES", str(lanes))
+    monkeypatch.setenv("GMACOP_GLB_LANES", str(lanes))
     w = grid32(vehicles=20, ants=24, iterations=9)
     check_independent(f"{w.name}_indep_{kernel}_L{lanes}", w.graph, w.vehicles,
                       dict(w.params, mode=gmacop.MODE_INDEPENDENT))
