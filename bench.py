@@ -103,12 +103,68 @@ def measure_forms(gmacop, G, w, stream_obj, max_plain=None):
             "batched_over_plain": t_plain / t_batched}
 
 
+def bench_serve(args):
+    """Continuous-batching router on the 1M-node city: Poisson arrivals at
+    each rate in --rates, 32 ants x 20 iterations per query."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2010_14244_amd import gmacop, serve
+
+    torch.cuda.set_device(0)
+    print("[bench] generating the serving city", file=sys.stderr, flush=True)
+    w = workloads.serving_city(n=args.serve_nodes)
+    g, p = w.graph, dict(w.params)
+    G = gmacop.gmacop_graph_create(g)
+    srv = gmacop.Server(G, p, max_slots=args.serve_slots)
+    stream_obj = torch.cuda.Stream()
+    stream = stream_obj.cuda_stream
+    print(f"[bench] {w.name}: n={g.n} m={g.m} slots={srv.slots} ({srv.bytes_per_slot / 2**20:.1f} MiB each)",
+          file=sys.stderr, flush=True)
+    rng = np.random.default_rng(7)
+    rates, qid0 = [float(r) for r in args.rates.split(",")], 0
+    runs = []
+    for rate in rates:
+        n = max(int(rate * args.serve_seconds), args.serve_warmup + 10)
+        od = workloads.query_stream(g, n, rng, qid0=qid0)
+        qid0 += n
+        arr = serve.poisson_arrivals(n, rate, rng)
+        gmacop.gmacop_stats_get(G, reset=True)
+        r = serve.serve(srv, od, arr, warmup=args.serve_warmup, stream=stream,
+                        log=lambda m: print(m, file=sys.stderr, flush=True))
+        st = gmacop.gmacop_stats_get(G)
+        run = {"offered_qps": rate, "queries": n, "sustained_qps": r["sustained_qps"], "p50_ms": r["p50_ms"],
+               "p99_ms": r["p99_ms"], "steps": r["steps"], "selections": st["selections"],
+               "edge_selections_per_s": st["selections"] / r["wall_s"],
+               "longest_walk_per_step": st["longest_walks"] / max(1, r["steps"])}
+        runs.append(run)
+        print(f"[bench] rate {rate:.0f}/s: sustained {r['sustained_qps']:.0f}/s p50 {r['p50_ms']:.1f} ms "
+              f"p99 {r['p99_ms']:.1f} ms, {r['steps']} steps", file=sys.stderr, flush=True)
+    best = max(runs, key=lambda x: x["sustained_qps"])
+    out = {"metric": "route queries/sec (continuous batching)", "value": best["sustained_qps"], "unit": "queries/s",
+           "n_gpus": 1, "steps": sum(x["steps"] for x in runs), "warmup": args.serve_warmup,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+           "data": "synthetic",
+           "config": {"workload": w.name, "nodes": g.n, "roads": g.m, "ants": p["ants"],
+                      "iterations": p["iterations"], "max_steps": p["max_steps"], "slots": srv.slots,
+                      "mode": "independent"},
+           "latency_ms": {"p50": best["p50_ms"], "p99": best["p99_ms"]}, "serving": runs}
+    srv.release()
+    gmacop.gmacop_release(G)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="grid32", choices=["grid8", "grid32", "planar100k", "multicity"])
+    ap.add_argument("--workload", default="grid32", choices=["grid8", "grid32", "planar100k", "multicity", "serve"])
+    ap.add_argument("--rates", default="2000,5000,10000,20000", help="serve: offered query rates")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="serve: seconds of arrivals per rate")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="serve: queries excluded from latency stats")
+    ap.add_argument("--serve-slots", type=int, default=4096, help="serve: slot limit (memory may allow fewer)")
+    ap.add_argument("--serve-nodes", type=int, default=1_000_000, help="serve: city size")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iterations", type=int, default=10)
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -122,6 +178,8 @@ def main():
               "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serve":
+        return bench_serve(args)
     import torch
     from paper_2010_14244_amd import gmacop
 

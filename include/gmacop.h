@@ -172,6 +172,46 @@ typedef struct {
  * is non-zero. */
 int gmacop_stats_get(gmacop_graph *g, gmacop_stats *s, int reset, void *hip_stream);
 
+/* ---- continuous batching ----
+ * A router serves a stream of route queries on a resident graph: every query
+ * is an independent-mode run of params->iterations iterations (Section 4.2,
+ * Alg. 2 per vehicle), and queries are admitted while others are in flight.
+ * Each in-flight query owns a slot (its pheromone, deposits, ant paths and
+ * best route on the device); a step admits new queries into free slots,
+ * advances every in-flight query by one iteration in one batch of kernels,
+ * and returns the queries that completed.  A query's result depends only on
+ * the query (its qid keys its random stream): it is identical whatever else
+ * is in flight, and identical to gmacop_route_batch in independent mode. */
+typedef struct gmacop_server gmacop_server;
+
+/* Create a router on g (which must outlive it).  The number of slots is
+ * max_slots, or fewer if the per-slot device memory times the slots would
+ * exceed mem_budget_bytes (0: half of the device memory free now); the graph
+ * must have fewer than 2^24 nodes.  Loads are frozen at the sensed loads.
+ * Errors: GMACOP_E_INVAL / E_RANGE as gmacop_route_batch, GMACOP_E_NOMEM when
+ * not even one slot fits, GMACOP_E_UNSUPPORTED for 0 or more than 4095
+ * iterations. */
+int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uint32_t max_slots, uint64_t mem_budget_bytes,
+                         gmacop_server **out);
+
+/* Slots, slots in use, device bytes per slot (any pointer may be NULL). */
+int gmacop_server_info(const gmacop_server *s, uint32_t *slots, uint32_t *active, uint64_t *bytes_per_slot);
+
+/* One step.  On entry *n_admit is the number of queries in admit (host);
+ * the first min(*n_admit, free slots) are admitted and *n_admit returns how
+ * many.  Every in-flight query then runs one iteration.  Queries that ran
+ * their last iteration are returned in order of slot: done_qid[i],
+ * done_len[i] (0 = no route), done_cost[i] (0xFFFFFFFF = none) and the route
+ * in done_paths[i * max_steps ...] (host buffers of done_cap entries; done_cap
+ * must cover every query finishing in the step, at most the slot count);
+ * *n_done returns their number.  Synchronous on hip_stream. */
+int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint32_t *n_admit, uint32_t *done_qid,
+                       uint32_t *done_len, uint32_t *done_cost, uint32_t *done_paths, uint32_t done_cap,
+                       uint32_t *n_done, void *hip_stream);
+
+/* Free the router's device memory (not the graph).  NULL-safe. */
+void gmacop_server_release(gmacop_server *s);
+
 /* Free the graph and all of its device memory (Alg. 1 step 5).  NULL-safe. */
 void gmacop_release(gmacop_graph *g);
 

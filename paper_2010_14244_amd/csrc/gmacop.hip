@@ -152,8 +152,15 @@ struct PherView {
     const uint32_t *dense;    // shared mode, [m]
     const uint64_t *lazy;     // independent mode, [slots][m]
     const uint32_t *gen;      // current call generation (device)
+    const uint32_t *slot_t;   // serving: iteration of each slot (else NULL: one iteration for all)
+    const uint32_t *slot_gen; // serving: generation of each slot (else NULL: *gen)
     uint32_t m, tau0, rho, tau_min;
 };
+
+__device__ __forceinline__ uint32_t slot_iter(const PherView &pv, uint32_t v, uint32_t t)
+{
+    return pv.slot_t ? pv.slot_t[v] : t;
+}
 
 struct PherRead {
     const uint32_t *dense;
@@ -173,10 +180,11 @@ struct PherRead {
 // View of slot v at iteration t (t counts from 0 within the call).
 __device__ __forceinline__ PherRead pher_at(const PherView &pv, uint32_t v, uint32_t t)
 {
+    t = slot_iter(pv, v, t);
     PherRead r{pv.dense, nullptr, 0, t, 0, pv.rho, pv.tau_min};
     if (!pv.dense) {
         r.lazy = pv.lazy + (size_t)v * pv.m;
-        r.gen = *pv.gen & kGenMask;
+        r.gen = (pv.slot_gen ? pv.slot_gen[v] : *pv.gen) & kGenMask;
         r.tau_def = evaporate_k(pv.tau0, t, pv.rho, pv.tau_min);
     }
     return r;
@@ -373,7 +381,7 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
                 T += w[j];
             }
             if (T == 0) break;   // dead end
-            const uint64_t r = philox_u64(q.qid, k, a.iter, s, a.seed_lo, a.seed_hi);
+            const uint64_t r = philox_u64(q.qid, k, a.iter + slot_iter(a.pher, v, 0), s, a.seed_lo, a.seed_hi);
             const uint64_t target = __umul64hi(r, T);
             uint64_t prefix = 0;
             uint32_t jsel = 0, xsel = 0, csel = 0;
@@ -676,8 +684,9 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
         uint64_t cs64 = 0;
         const uint32_t m_last = e_cnt - 1;
         uint32_t *path = a.path + ant;
+        const uint32_t it = a.iter + slot_iter(a.pher, v, 0);
         for (;;) {
-            const uint64_t myr = philox_u64(q.qid, k, a.iter, s + j, a.seed_lo, a.seed_hi);
+            const uint64_t myr = philox_u64(q.qid, k, it, s + j, a.seed_lo, a.seed_hi);
             if (!lds_steps<L, CH, 0>(s_rec, s_w, s_cost, bits, j, m_last, myr, q.dst - n_lo, a.max_steps, NA, e_lo,
                                      u, rs, d, s, ncand, cs64, ok, path))
                 break;
@@ -916,8 +925,9 @@ __global__ __launch_bounds__(256) void k_walk_glb(GlbWalkArgs a)
         bool ok = false;
         uint64_t cs64 = 0;
         uint32_t *path = a.path + ant;
+        const uint32_t it = a.iter + slot_iter(a.pher, v, 0);
         for (;;) {
-            const uint64_t myr = philox_u64(q.qid, k, a.iter, s + j, a.seed_lo, a.seed_hi);
+            const uint64_t myr = philox_u64(q.qid, k, it, s + j, a.seed_lo, a.seed_hi);
             if (!glb_steps<L, CH, 0>(a, tau, bloom, gb, n_lo, dx, dy, j, myr, q.dst, NA, u, rs, d, hu, hist, s, ncand,
                                      cs64, ok, path))
                 break;
@@ -1051,6 +1061,7 @@ struct ApplyArgs {
     uint32_t m, cap, t_local, tau0, rho, tau_min, tau_max, theta;
     const uint32_t *load;     // frozen loads
     const uint32_t *gen;
+    const uint32_t *slot_t, *slot_gen;   // serving: per-slot iteration and generation (else NULL)
     uint64_t *lazy, *dep;
     uint32_t *touched, *touched_n;
 };
@@ -1066,13 +1077,14 @@ __global__ __launch_bounds__(256) void k_apply_touched(ApplyArgs a)
     const uint32_t n = min(a.touched_n[v], a.cap);
     uint64_t *lazy = a.lazy + (size_t)v * a.m;
     uint64_t *dep = a.dep + (size_t)v * a.m;
-    const uint32_t gen = *a.gen & kGenMask;
-    const uint32_t tau_def = evaporate_k(a.tau0, a.t_local, a.rho, a.tau_min);
+    const uint32_t gen = (a.slot_gen ? a.slot_gen[v] : *a.gen) & kGenMask;
+    const uint32_t t_local = a.slot_t ? a.slot_t[v] : a.t_local;
+    const uint32_t tau_def = evaporate_k(a.tau0, t_local, a.rho, a.tau_min);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
         const uint32_t e = a.touched[(size_t)v * a.cap + i];
         const uint64_t x = lazy[e];
         const uint32_t tau = (uint32_t)(x >> 44) == gen
-                                 ? evaporate_k((uint32_t)x, a.t_local - ((uint32_t)(x >> 32) & 0xFFFu), a.rho, a.tau_min)
+                                 ? evaporate_k((uint32_t)x, t_local - ((uint32_t)(x >> 32) & 0xFFFu), a.rho, a.tau_min)
                                  : tau_def;
         const uint64_t D = dep[e];
         const uint32_t L = a.load[e];
@@ -1080,7 +1092,7 @@ __global__ __launch_bounds__(256) void k_apply_touched(ApplyArgs a)
         if (L > a.theta) dp = (D / L) * a.theta + ((D % L) * a.theta) / L;
         uint64_t t = (((uint64_t)tau * (65536u - a.rho)) >> 16) + dp;
         t = t < a.tau_min ? a.tau_min : (t > a.tau_max ? a.tau_max : t);
-        lazy[e] = t | ((uint64_t)(a.t_local + 1) << 32) | ((uint64_t)gen << 44);
+        lazy[e] = t | ((uint64_t)(t_local + 1) << 32) | ((uint64_t)gen << 44);
         dep[e] = 0;
     }
     __syncthreads();
@@ -1120,6 +1132,54 @@ __global__ void k_classify(const gmacop_od *od, uint32_t nq, uint32_t n, const u
         c = ic ? ic : kWalkerGlobal;
     }
     vclass[v] = c;
+}
+
+// ---- serving: slot admission, advance, result gather ----
+
+// Queries enter free slots: the slot's route starts empty at iteration 0
+// with a fresh pheromone generation.
+__global__ void k_admit(const uint32_t *slots, const gmacop_od *ods, const uint32_t *gens, uint32_t n,
+                        gmacop_od *slot_od, uint32_t *slot_t, uint32_t *slot_gen, uint32_t *best_len,
+                        uint32_t *best_cost, uint64_t *iter_key)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t sl = slots[i];
+    slot_od[sl] = ods[i];
+    slot_t[sl] = 0;
+    slot_gen[sl] = gens[i];
+    best_len[sl] = 0;
+    best_cost[sl] = kNoCost;
+    iter_key[sl] = kNoKey;
+}
+
+// After an iteration: every active slot moves to the next iteration; a slot
+// that has run all iterations is retired (its query marked invalid, so the
+// walkers skip it until a new query is admitted).
+__global__ void k_advance(uint32_t nslots, uint32_t n, uint32_t iterations, gmacop_od *slot_od, uint32_t *slot_t)
+{
+    const uint32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nslots) return;
+    const gmacop_od q = slot_od[sl];
+    if (q.src >= n || q.dst >= n || q.src == q.dst) return;
+    const uint32_t t = slot_t[sl] + 1;
+    slot_t[sl] = t;
+    if (t >= iterations) slot_od[sl] = gmacop_od{q.qid, 0xFFFFFFFFu, 0xFFFFFFFFu};
+}
+
+// Results of finished slots into contiguous buffers (one block per slot).
+__global__ void k_gather_done(const uint32_t *slots, uint32_t max_steps, const uint32_t *best_path,
+                              const uint32_t *best_len, const uint32_t *best_cost, uint32_t *out_path,
+                              uint32_t *out_len, uint32_t *out_cost)
+{
+    const uint32_t i = blockIdx.x, sl = slots[i];
+    const uint32_t len = best_len[sl];
+    for (uint32_t s = threadIdx.x; s < len; s += blockDim.x)
+        out_path[(size_t)i * max_steps + s] = best_path[(size_t)sl * max_steps + s];
+    if (threadIdx.x == 0) {
+        out_len[i] = len;
+        out_cost[i] = best_cost[sl];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1732,7 +1792,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, update_loads ? 1u : 0u,
                 g->tau, g->load, g->cnt, g->base_load, g->dep};
     ApplyArgs aa{g->m, tcap, 0, p->tau0_q16, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, g->load, g->dev_gen,
-                 g->lazy, g->dep_ind, g->touched, g->touched_n};
+                 nullptr, nullptr, g->lazy, g->dep_ind, g->touched, g->touched_n};
     GlbWalkArgs ga{};
     ga.rec16 = g->rec16; ga.row_ptr = g->row_ptr; ga.cost = g->cost; ga.x = g->x; ga.y = g->y; ga.node_lo = g->node_lo;
     ga.vclass = g->vclass; ga.pher = pv; ga.depv = dv; ga.od = od; ga.n = g->n; ga.m = g->m; ga.nq = nq;
@@ -1951,4 +2011,306 @@ extern "C" void gmacop_release(gmacop_graph *g)
 extern "C" const char *gmacop_last_error(void)
 {
     return t_err.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// continuous-batching router
+// ---------------------------------------------------------------------------
+
+struct gmacop_server {
+    gmacop_graph *g = nullptr;
+    gmacop_params p{};
+    uint32_t slots = 0, tcap = 0, nwords_legacy = 0;
+    size_t per_slot = 0;
+    WalkPlan plan;
+    // device, per slot
+    gmacop_od *slot_od = nullptr;
+    uint32_t *slot_t = nullptr, *slot_gen = nullptr, *best_path = nullptr, *best_len = nullptr, *best_cost = nullptr;
+    uint64_t *iter_key = nullptr, *lazy = nullptr, *dep = nullptr, *steps = nullptr, *counters = nullptr;
+    uint32_t *touched = nullptr, *touched_n = nullptr, *path = nullptr, *ant_len = nullptr, *ant_cost = nullptr;
+    uint32_t *gbits = nullptr, *iter_max = nullptr;
+    uint8_t *vclass = nullptr;
+    // device, per road: this router's frozen-load cost table
+    uint32_t *t0 = nullptr, *wf = nullptr, *load = nullptr, *cost = nullptr, *cnt = nullptr, *tau = nullptr;
+    uint64_t *dep_shared = nullptr;
+    // device staging for admissions and results
+    uint32_t *adm_slots = nullptr, *adm_gen = nullptr, *done_slots = nullptr, *done_path = nullptr,
+             *done_len = nullptr, *done_cost = nullptr;
+    gmacop_od *adm_od = nullptr;
+    // host mirror
+    std::vector<uint32_t> free_list, t_host, qid_host, gen_host;
+    std::vector<uint8_t> active;
+    uint64_t ticks = 0, admitted = 0, completed = 0;
+
+    ~gmacop_server()
+    {
+        (void)hipSetDevice(g ? g->device : 0);
+        dfree(slot_od); dfree(slot_t); dfree(slot_gen); dfree(best_path); dfree(best_len); dfree(best_cost);
+        dfree(iter_key); dfree(lazy); dfree(dep); dfree(steps); dfree(counters); dfree(touched); dfree(touched_n);
+        dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_max); dfree(vclass);
+        dfree(t0); dfree(wf); dfree(load); dfree(cost); dfree(cnt); dfree(tau); dfree(dep_shared);
+        dfree(adm_slots); dfree(adm_gen); dfree(done_slots); dfree(done_path); dfree(done_len); dfree(done_cost);
+        dfree(adm_od);
+    }
+};
+
+namespace {
+
+template <typename T>
+int dalloc_zero(T **p, size_t count)
+{
+    int rc = dalloc(p, count);
+    if (rc) return rc;
+    HIP_TRY(hipMemset(*p, 0, std::max<size_t>(count, 1) * sizeof(T)));
+    return GMACOP_OK;
+}
+
+}  // namespace
+
+extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uint32_t max_slots,
+                                    uint64_t mem_budget_bytes, gmacop_server **out)
+{
+    if (!out) return fail(GMACOP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!g || !p) return fail(GMACOP_E_INVAL, "graph or params is NULL");
+    gmacop_params pp = *p;
+    pp.mode = GMACOP_MODE_INDEPENDENT;
+    pp.flags &= GMACOP_TIME_KERNELS;
+    int rc = validate_params(g, &pp, 1);
+    if (rc) return rc;
+    if (pp.iterations == 0 || pp.iterations > kLazyIterMax)
+        return fail(GMACOP_E_UNSUPPORTED, "router needs 1..%u iterations", kLazyIterMax);
+    HIP_TRY(hipSetDevice(g->device));
+    gmacop_server *s = new gmacop_server();
+    s->g = g;
+    s->p = pp;
+    s->plan = plan_walk(g, &pp, g->max_lds);
+    if (s->plan.legacy) {
+        delete s;
+        return fail(GMACOP_E_UNSUPPORTED, "router needs a graph under 2^24 nodes");
+    }
+    const uint32_t A = pp.ants, S = pp.max_steps, m = g->m;
+    s->tcap = (uint32_t)std::min<uint64_t>(m, (uint64_t)A * S);
+    s->nwords_legacy = (g->n + 31) / 32;
+    const uint64_t words = s->plan.legacy ? (g->n <= kLdsBitsetMaxNodes ? 0 : s->nwords_legacy) : s->plan.glb_nwords;
+    s->per_slot = (size_t)m * 16 + (size_t)s->tcap * 4 + (size_t)A * S * 4 + (size_t)A * 8 + (size_t)A * words * 4 +
+                  (size_t)S * 8 + 64;
+    size_t budget = mem_budget_bytes;
+    if (!budget) {
+        size_t fr = 0, tot = 0;
+        HIP_TRY(hipMemGetInfo(&fr, &tot));
+        budget = fr / 2;
+    }
+    uint64_t cap_slots = budget / std::max<size_t>(s->per_slot, 1);
+    if (max_slots) cap_slots = std::min<uint64_t>(cap_slots, max_slots);
+    cap_slots = std::min<uint64_t>(cap_slots, 0xFFFFFFFFull / std::max<uint32_t>(A, 1));
+    if (cap_slots == 0) {
+        delete s;
+        return fail(GMACOP_E_NOMEM, "memory budget below one query slot (%zu bytes)", s->per_slot);
+    }
+    const uint32_t NS = (uint32_t)cap_slots;
+    s->slots = NS;
+    const uint64_t NA = (uint64_t)NS * A;
+    std::vector<gmacop_od> idle(NS, gmacop_od{0, 0xFFFFFFFFu, 0xFFFFFFFFu});
+    if ((rc = upload(&s->slot_od, idle.data(), NS)) || (rc = dalloc_zero(&s->slot_t, NS)) ||
+        (rc = dalloc_zero(&s->slot_gen, NS)) || (rc = dalloc(&s->best_path, (size_t)NS * S)) ||
+        (rc = dalloc_zero(&s->best_len, NS)) || (rc = dalloc(&s->best_cost, NS)) || (rc = dalloc(&s->iter_key, NS)) ||
+        (rc = dalloc_zero(&s->lazy, (size_t)NS * m)) || (rc = dalloc_zero(&s->dep, (size_t)NS * m)) ||
+        (rc = dalloc_zero(&s->touched_n, NS)) || (rc = dalloc(&s->touched, (size_t)NS * s->tcap)) ||
+        (rc = dalloc(&s->path, (size_t)S * NA)) || (rc = dalloc(&s->ant_len, NA)) || (rc = dalloc(&s->ant_cost, NA)) ||
+        (rc = dalloc_zero(&s->gbits, (size_t)NA * words)) || (rc = dalloc_zero(&s->steps, 1)) ||
+        (rc = dalloc_zero(&s->counters, 5)) || (rc = dalloc_zero(&s->iter_max, 1)) || (rc = dalloc(&s->vclass, NS)) ||
+        (rc = dalloc(&s->t0, m)) || (rc = dalloc(&s->wf, m)) || (rc = dalloc(&s->load, m)) ||
+        (rc = dalloc(&s->cost, m)) || (rc = dalloc(&s->cnt, m)) || (rc = dalloc(&s->tau, m)) ||
+        (rc = dalloc(&s->dep_shared, m)) || (rc = dalloc(&s->adm_slots, NS)) || (rc = dalloc(&s->adm_gen, NS)) ||
+        (rc = dalloc(&s->adm_od, NS)) || (rc = dalloc(&s->done_slots, NS)) ||
+        (rc = dalloc(&s->done_path, (size_t)NS * S)) || (rc = dalloc(&s->done_len, NS)) ||
+        (rc = dalloc(&s->done_cost, NS))) {
+        std::string keep = t_err;
+        delete s;
+        t_err = keep;
+        return rc;
+    }
+    // this router's cost table: loads frozen at the sensed loads
+    EdgeInitArgs ia{m, pp.tau0_q16, pp.t_max_ms, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
+                    s->t0, s->wf, s->tau, s->load, s->cnt, s->dep_shared};
+    hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(m, 256)), dim3(256), 0, 0, ia);
+    CostArgs ca{g->n, pp.theta, pp.th_max, g->rev_ptr, g->rev_edge, g->cycle, s->load, s->t0, s->wf, s->cost};
+    hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, 0, ca);
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete s;
+        return fail(GMACOP_E_DEVICE, "router set-up: %s", hipGetErrorString(e));
+    }
+    s->free_list.resize(NS);
+    for (uint32_t i = 0; i < NS; ++i) s->free_list[i] = NS - 1 - i;   // pop_back hands out slot 0 first
+    s->t_host.assign(NS, 0);
+    s->qid_host.assign(NS, 0);
+    s->gen_host.assign(NS, 0);
+    s->active.assign(NS, 0);
+    *out = s;
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_server_info(const gmacop_server *s, uint32_t *slots, uint32_t *active, uint64_t *bytes_per_slot)
+{
+    if (!s) return fail(GMACOP_E_INVAL, "server is NULL");
+    if (slots) *slots = s->slots;
+    if (active) *active = s->slots - (uint32_t)s->free_list.size();
+    if (bytes_per_slot) *bytes_per_slot = s->per_slot;
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint32_t *n_admit, uint32_t *done_qid,
+                                  uint32_t *done_len, uint32_t *done_cost, uint32_t *done_paths, uint32_t done_cap,
+                                  uint32_t *n_done, void *hip_stream)
+{
+    if (!s || !n_admit || !n_done) return fail(GMACOP_E_INVAL, "server or counts are NULL");
+    if (*n_admit && !admit) return fail(GMACOP_E_INVAL, "admissions are NULL");
+    gmacop_graph *g = s->g;
+    const gmacop_params &p = s->p;
+    const uint32_t A = p.ants, S = p.max_steps, NS = s->slots;
+    // queries finishing in this step: those admitted iterations-1 steps ago, plus the new ones if iterations == 1
+    uint32_t finishing = 0;
+    for (uint32_t i = 0; i < NS; ++i) finishing += s->active[i] && s->t_host[i] + 1 == p.iterations;
+    const uint32_t take = std::min<uint32_t>(*n_admit, (uint32_t)s->free_list.size());
+    if (finishing + (p.iterations == 1 ? take : 0) > done_cap)
+        return fail(GMACOP_E_INVAL, "done_cap %u below the %u queries finishing in this step", done_cap,
+                    finishing + (p.iterations == 1 ? take : 0));
+    if ((finishing || (p.iterations == 1 && take)) && (!done_qid || !done_len || !done_cost || !done_paths))
+        return fail(GMACOP_E_INVAL, "result buffers are NULL");
+    for (uint32_t i = 0; i < take; ++i) {
+        if (admit[i].qid == 0xFFFFFFFFu) return fail(GMACOP_E_INVAL, "admission %u uses the reserved qid", i);
+        if (admit[i].src >= g->n || admit[i].dst >= g->n || admit[i].src == admit[i].dst)
+            return fail(GMACOP_E_INVAL, "admission %u: invalid nodes", i);
+        if (instance_of(g, admit[i].src) != instance_of(g, admit[i].dst))
+            return fail(GMACOP_E_INVAL, "admission %u: src and dst in different cities", i);
+    }
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    int rc;
+    if (s->plan.city_class != g->city_class_dev) {
+        HIP_TRY(hipMemcpy(g->inst_fits, s->plan.city_class.data(), g->n_inst, hipMemcpyHostToDevice));
+        g->city_class_dev = s->plan.city_class;
+    }
+
+    // 1. admissions
+    if (take) {
+        std::vector<uint32_t> sl(take), gens(take);
+        for (uint32_t i = 0; i < take; ++i) {
+            const uint32_t x = s->free_list.back();
+            s->free_list.pop_back();
+            sl[i] = x;
+            uint32_t gnew = s->gen_host[x] + 1;
+            if (gnew > kGenMask) {   // generation numbers would repeat: clear the slot's pheromone row
+                HIP_TRY(hipMemsetAsync(s->lazy + (size_t)x * g->m, 0, sizeof(uint64_t) * g->m, st));
+                gnew = 1;
+            }
+            s->gen_host[x] = gnew;
+            gens[i] = gnew;
+            s->t_host[x] = 0;
+            s->qid_host[x] = admit[i].qid;
+            s->active[x] = 1;
+        }
+        HIP_TRY(hipMemcpyAsync(s->adm_slots, sl.data(), 4 * take, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(s->adm_gen, gens.data(), 4 * take, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(s->adm_od, admit, sizeof(gmacop_od) * take, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_admit, dim3(blocks_for(take, 256)), dim3(256), 0, st, (const uint32_t *)s->adm_slots,
+                           (const gmacop_od *)s->adm_od, (const uint32_t *)s->adm_gen, take, s->slot_od, s->slot_t,
+                           s->slot_gen, s->best_len, s->best_cost, s->iter_key);
+        s->admitted += take;
+    }
+    *n_admit = take;
+
+    // 2. one iteration for every active slot
+    const WalkPlan &plan = s->plan;
+    const bool timing = (p.flags & GMACOP_TIME_KERNELS) != 0;
+    KernelTimer kt{g, st, timing};
+    gmacop_graph::Timed tm{};
+    PherView pv{};
+    pv.lazy = s->lazy; pv.gen = nullptr; pv.slot_t = s->slot_t; pv.slot_gen = s->slot_gen;
+    pv.m = g->m; pv.tau0 = p.tau0_q16; pv.rho = p.rho_q16; pv.tau_min = p.tau_min_q16;
+    DepView dv{s->dep, s->touched, s->touched_n, g->m, s->tcap, 1u};
+    const uint32_t kgoal = p.vmax_kmh ? (uint32_t)((360ull << 16) / p.vmax_kmh) : 0;
+    const uint32_t NAll = NS * A;
+    hipLaunchKernelGGL(k_classify, dim3(blocks_for(NS, 256)), dim3(256), 0, st, (const gmacop_od *)s->slot_od, NS,
+                       g->n, (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, s->vclass);
+    if ((rc = kt.start(0, &tm))) return rc;
+    {
+        LdsWalkArgs la{};
+        la.row_ptr = g->row_ptr; la.col = g->col; la.cost = s->cost; la.pher = pv; la.depv = dv; la.x = g->x;
+        la.y = g->y; la.rec = g->rec; la.tail = g->tail; la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev;
+        la.inst_eoff = g->inst_eoff_dev; la.vclass = s->vclass; la.od = s->slot_od; la.n = g->n; la.m = g->m;
+        la.nq = NS; la.ants = A; la.apb = plan.lds_apb; la.bpv = plan.lds_bpv; la.max_steps = S; la.alpha = p.alpha;
+        la.beta = p.beta; la.kgoal = kgoal; la.nwords = 0; la.seed_lo = (uint32_t)p.seed;
+        la.seed_hi = (uint32_t)(p.seed >> 32); la.iter = p.iter_offset; la.t_local = 0; la.q_deposit = p.q_deposit;
+        la.path = s->path; la.ant_len = s->ant_len; la.ant_cost = s->ant_cost; la.iter_key = s->iter_key;
+        la.steps = s->steps; la.counters = g->counters; la.iter_max = g->iter_max;
+        const bool any_lds = plan.lds_bytes[1] || plan.lds_bytes[2] || plan.lds_bytes[3];
+        if (any_lds && (rc = launch_walk_lds_any(la, plan, st, true))) return rc;
+        for (uint32_t c = 1; c <= 3; ++c)
+            if (plan.lds_bytes[c]) {
+                la.cls = c;
+                if ((rc = launch_walk_lds_any(la, plan, st))) return rc;
+            }
+        if (plan.glb) {
+            GlbWalkArgs ga{};
+            ga.rec16 = g->rec16; ga.row_ptr = g->row_ptr; ga.cost = s->cost; ga.x = g->x; ga.y = g->y;
+            ga.node_lo = g->node_lo; ga.vclass = s->vclass; ga.pher = pv; ga.depv = dv; ga.od = s->slot_od;
+            ga.n = g->n; ga.m = g->m; ga.nq = NS; ga.ants = A; ga.apb = plan.glb_apb; ga.max_steps = S;
+            ga.alpha = p.alpha; ga.beta = p.beta; ga.kgoal = kgoal; ga.nwords = plan.glb_nwords;
+            ga.bloom_log2 = plan.bloom_log2; ga.seed_lo = la.seed_lo; ga.seed_hi = la.seed_hi; ga.iter = p.iter_offset;
+            ga.t_local = 0; ga.q_deposit = p.q_deposit; ga.path = s->path; ga.ant_len = s->ant_len;
+            ga.ant_cost = s->ant_cost; ga.gbits = s->gbits; ga.iter_key = s->iter_key; ga.steps = s->steps;
+            ga.counters = g->counters; ga.iter_max = g->iter_max;
+            if ((rc = launch_walk_glb_any(ga, plan, st))) return rc;
+        }
+    }
+    if ((rc = kt.stop(&tm)) || (rc = kt.start(1, &tm))) return rc;
+    BestArgs ba{NS, A, S, 0u, g->iter_max, g->counters, s->path, s->ant_len, s->iter_key, s->best_path, s->best_len,
+                s->best_cost, s->cnt};
+    hipLaunchKernelGGL(k_best, dim3(NS), dim3(kWave), 0, st, ba);
+    if ((rc = kt.stop(&tm)) || (rc = kt.start(2, &tm))) return rc;
+    ApplyArgs aa{g->m, s->tcap, 0, p.tau0_q16, p.rho_q16, p.tau_min_q16, p.tau_max_q16, p.theta, s->load, nullptr,
+                 s->slot_t, s->slot_gen, s->lazy, s->dep, s->touched, s->touched_n};
+    hipLaunchKernelGGL(k_apply_touched, dim3(NS), dim3(256), 0, st, aa);
+    if ((rc = kt.stop(&tm))) return rc;
+    hipLaunchKernelGGL(k_advance, dim3(blocks_for(NS, 256)), dim3(256), 0, st, NS, g->n, p.iterations, s->slot_od,
+                       s->slot_t);
+    HIP_TRY(hipGetLastError());
+    (void)NAll;
+
+    // 3. finished queries
+    std::vector<uint32_t> fin;
+    for (uint32_t i = 0; i < NS; ++i)
+        if (s->active[i]) {
+            s->t_host[i] += 1;
+            if (s->t_host[i] >= p.iterations) fin.push_back(i);
+        }
+    const uint32_t nf = (uint32_t)fin.size();
+    if (nf) {
+        HIP_TRY(hipMemcpyAsync(s->done_slots, fin.data(), 4 * nf, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_gather_done, dim3(nf), dim3(64), 0, st, (const uint32_t *)s->done_slots, S,
+                           (const uint32_t *)s->best_path, (const uint32_t *)s->best_len,
+                           (const uint32_t *)s->best_cost, s->done_path, s->done_len, s->done_cost);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(done_len, s->done_len, 4 * nf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(done_cost, s->done_cost, 4 * nf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(done_paths, s->done_path, sizeof(uint32_t) * (size_t)nf * S, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (uint32_t i = 0; i < nf; ++i) {
+        done_qid[i] = s->qid_host[fin[i]];
+        s->active[fin[i]] = 0;
+        s->free_list.push_back(fin[i]);
+    }
+    *n_done = nf;
+    s->completed += nf;
+    s->ticks++;
+    return GMACOP_OK;
+}
+
+extern "C" void gmacop_server_release(gmacop_server *s)
+{
+    delete s;
 }

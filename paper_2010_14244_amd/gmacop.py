@@ -32,7 +32,8 @@ TIME_KERNELS = 4
 HIP_GRAPH = 8
 
 EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_state_get", "gmacop_vehicle_tau_get",
-            "gmacop_stats_get", "gmacop_release", "gmacop_last_error")
+            "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
+            "gmacop_server_release", "gmacop_release", "gmacop_last_error")
 KERNELS = ("walk", "best", "edge", "cost")
 
 
@@ -98,6 +99,15 @@ def lib():
         L.gmacop_vehicle_tau_get.restype = C.c_int
         L.gmacop_stats_get.argtypes = [vp, C.POINTER(_Stats), C.c_int, vp]
         L.gmacop_stats_get.restype = C.c_int
+        u32p = C.POINTER(C.c_uint32)
+        L.gmacop_server_create.argtypes = [vp, C.POINTER(_Params), C.c_uint32, C.c_uint64, C.POINTER(vp)]
+        L.gmacop_server_create.restype = C.c_int
+        L.gmacop_server_info.argtypes = [vp, u32p, u32p, C.POINTER(C.c_uint64)]
+        L.gmacop_server_info.restype = C.c_int
+        L.gmacop_server_step.argtypes = [vp, vp, u32p, vp, vp, vp, vp, C.c_uint32, u32p, vp]
+        L.gmacop_server_step.restype = C.c_int
+        L.gmacop_server_release.argtypes = [vp]
+        L.gmacop_server_release.restype = None
         L.gmacop_release.argtypes = [vp]
         L.gmacop_release.restype = None
         L.gmacop_last_error.argtypes = []
@@ -235,3 +245,52 @@ def gmacop_release(g: Graph) -> None:
     if g is not None and g.handle:
         lib().gmacop_release(g.handle)
         g.handle = None
+
+
+class Server:
+    """Continuous-batching router (gmacop_server_*): independent-mode queries
+    admitted while others are in flight, one iteration per step."""
+
+    def __init__(self, g: Graph, p: dict, max_slots: int = 0, mem_budget_bytes: int = 0):
+        h = C.c_void_p()
+        pp = _params(dict(p, mode=MODE_INDEPENDENT))
+        _check(lib().gmacop_server_create(g.handle, C.byref(pp), int(max_slots), int(mem_budget_bytes), C.byref(h)))
+        self.handle = h.value
+        self.graph = g                      # keeps the graph alive
+        self.max_steps = int(p["max_steps"])
+        self.iterations = int(p["iterations"])
+        sl, act, bps = C.c_uint32(), C.c_uint32(), C.c_uint64()
+        _check(lib().gmacop_server_info(self.handle, C.byref(sl), C.byref(act), C.byref(bps)))
+        self.slots, self.bytes_per_slot = int(sl.value), int(bps.value)
+        self._qid = np.zeros(self.slots, np.uint32)
+        self._len = np.zeros(self.slots, np.uint32)
+        self._cost = np.zeros(self.slots, np.uint32)
+        self._paths = np.zeros((self.slots, max(self.max_steps, 1)), np.uint32)
+
+    def active(self) -> int:
+        act = C.c_uint32()
+        _check(lib().gmacop_server_info(self.handle, None, C.byref(act), None))
+        return int(act.value)
+
+    def step(self, od: np.ndarray, stream: Optional[int] = None):
+        """od: uint32 [k, 3] (qid, src, dst) to admit.  Returns (admitted count,
+        list of (qid, path edges, cost)) for the queries that completed."""
+        od = np.ascontiguousarray(od, np.uint32).reshape(-1, 3)
+        na, nd = C.c_uint32(od.shape[0]), C.c_uint32(0)
+        _check(lib().gmacop_server_step(self.handle, od.ctypes.data if od.shape[0] else None, C.byref(na),
+                                        self._qid.ctypes.data, self._len.ctypes.data, self._cost.ctypes.data,
+                                        self._paths.ctypes.data, self.slots, C.byref(nd), stream))
+        done = [(int(self._qid[i]), self._paths[i, :int(self._len[i])].copy(), int(self._cost[i]))
+                for i in range(nd.value)]
+        return int(na.value), done
+
+    def release(self):
+        if self.handle:
+            lib().gmacop_server_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

@@ -322,3 +322,72 @@ def test_independent_alone_equals_in_mix():
         assert_same(again, mix, p["max_steps"], state=False)
     finally:
         gmacop.gmacop_release(G)
+
+
+def test_router_results_equal_standalone_runs():
+    """Queries served by the continuous-batching router, admitted over
+    several steps while others are in flight and slots are reused, give the
+    same routes as each query run alone (independent mode) and as the oracle."""
+    from workloads import query_stream
+    w = grid32(iterations=5)
+    p = dict(w.params, ants=16, iterations=5, mode=gmacop.MODE_INDEPENDENT)
+    rng = np.random.default_rng(5)
+    od = query_stream(w.graph, 23, rng, qid0=100)
+    announce("router")
+    G = gmacop.gmacop_graph_create(w.graph)
+    srv = gmacop.Server(G, p, max_slots=6)
+    try:
+        assert srv.slots == 6
+        results, nxt, step = {}, 0, 0
+        plan = [3, 0, 1, 4, 0, 2, 5, 0, 0, 3]          # arrivals per step, then drain
+        while len(results) < od.shape[0]:
+            k = plan[step] if step < len(plan) else od.shape[0]
+            batch = od[nxt:nxt + k]
+            adm, done = srv.step(batch)
+            assert adm <= k
+            nxt += adm
+            for qid, path, cost in done:
+                results[qid] = (path, cost)
+            step += 1
+            assert step < 200
+        alone = {}
+        for i in range(od.shape[0]):
+            veh = Vehicles(qid=od[i:i + 1, 0], src=od[i:i + 1, 1], dst=od[i:i + 1, 2])
+            r = gmacop.gmacop_route_batch(G, veh, p)
+            L = int(r["path_len"][0])
+            qid = int(od[i, 0])
+            assert results[qid][1] == int(r["cost_ms"][0]), qid
+            assert results[qid][0].tolist() == r["path_edges"][0, :L].tolist(), qid
+            alone[qid] = r
+        veh = Vehicles(qid=od[:6, 0], src=od[:6, 1], dst=od[:6, 2])
+        want = oracle.route(w.graph, veh, p)
+        for i in range(6):
+            assert results[int(od[i, 0])][1] == int(want["cost_ms"][i])
+    finally:
+        srv.release()
+        gmacop.gmacop_release(G)
+
+
+def test_router_admission_limits():
+    w = grid8()
+    p = dict(w.params, ants=4, iterations=3)
+    G = gmacop.gmacop_graph_create(w.graph)
+    try:
+        with pytest.raises(gmacop.GmacopError) as ei:
+            gmacop.Server(G, p, max_slots=4, mem_budget_bytes=16)      # below one slot
+        assert ei.value.code == gmacop.E_NOMEM
+        srv = gmacop.Server(G, p, max_slots=2)
+        od = np.array([[1, 0, 63], [2, 5, 60], [3, 9, 17]], np.uint32)
+        adm, done = srv.step(od)
+        assert adm == 2 and not done and srv.active() == 2
+        adm, done = srv.step(od[2:])
+        assert adm == 0
+        adm, done = srv.step(od[2:])
+        assert adm == 0 and len(done) == 2 and srv.active() == 0
+        adm, done = srv.step(od[2:])
+        assert adm == 1
+        with pytest.raises(gmacop.GmacopError):
+            srv.step(np.array([[4, 3, 3]], np.uint32))                 # src == dst
+        srv.release()
+    finally:
+        gmacop.gmacop_release(G)

@@ -446,3 +446,20 @@ def from_edges(n: int, tails, heads, *, len_dm=1000, speed_kmh=50, green_pm=500,
 
     return _to_csr(n, tails, heads, bc(len_dm, m), bc(speed_kmh, m), bc(base_load, m),
                    bc(cycle_ms, n), x, y, green_fn)
+
+
+def serving_city(seed: int = 1, *, n: int = 1_000_000, ants: int = 32, iterations: int = 20,
+                 max_steps: int = 4096) -> Workload:
+    """Planar road network of ~1M nodes / ~2.5M roads for routing queries
+    (independent per-query pheromone, 32 ants x 20 iterations)."""
+    rng = np.random.default_rng(seed)
+    g = planar_graph(n, rng)
+    return Workload(f"planar{n // 1000}k_serving_{ants}ants_{iterations}it", g,
+                    random_od(g.n, 1, rng),
+                    default_params(ants=ants, iterations=iterations, max_steps=max_steps, vmax_kmh=70, mode=1))
+
+
+def query_stream(g: RoadGraph, count: int, rng: np.random.Generator, qid0: int = 0) -> np.ndarray:
+    """count uniform random OD queries as uint32 [count, 3] (qid, src, dst)."""
+    v = random_od(g.n, count, rng, qid0=qid0)
+    return np.stack([v.qid, v.src, v.dst], axis=1).astype(np.uint32)
