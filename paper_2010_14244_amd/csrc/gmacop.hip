@@ -611,6 +611,85 @@ __device__ __forceinline__ bool lds_steps(const uint2 *s_rec, const uint64_t *s_
     return true;
 }
 
+// Replicated-lane step: every lane of the group reads all candidates of the
+// current node (the same LDS addresses, served as broadcasts) and computes the
+// prefix sums, target and winner locally, so no value crosses lanes except
+// this step's Philox word (drawn by group lane SL).  s_rw holds per road
+// (head | head_deg << 24, head's first road, weight lo, weight hi).
+template <int L, int MAXD, int SL>
+__device__ __forceinline__ bool lds_step_repl(const uint4 *s_rw, const uint32_t *s_cost, uint32_t *bits, uint32_t j,
+                                              uint32_t m_last, uint64_t myr, uint32_t dst, uint32_t e_lo,
+                                              uint32_t &u, uint32_t &rs, uint32_t &d, uint32_t &s, uint32_t &ncand,
+                                              uint64_t &cs, bool &ok, uint32_t *path_s)
+{
+    ncand += d;
+    uint4 rec[MAXD];
+    uint64_t w[MAXD];
+#pragma unroll
+    for (int c = 0; c < MAXD; ++c) rec[c] = s_rw[min(rs + (uint32_t)c, m_last)];
+    uint64_t T = 0;
+#pragma unroll
+    for (int c = 0; c < MAXD; ++c) {
+        const uint32_t xh = rec[c].x & 0xFFFFFFu;
+        const bool live = (uint32_t)c < d && !((bits[xh >> 5] >> (xh & 31)) & 1u);
+        w[c] = live ? (((uint64_t)rec[c].w << 32) | rec[c].z) : 0;
+        T += w[c];
+    }
+    if (T == 0) return false;   // dead end
+    uint64_t r = myr;
+    if (L == 2) r = SL == 0 ? dpp64<kDppQuad(0, 0, 2, 2)>(myr) : dpp64<kDppQuad(1, 1, 3, 3)>(myr);
+    if (L == 4) r = dpp64<kDppQuad(SL, SL, SL, SL)>(myr);
+    if (L >= 8) r = __shfl(myr, SL, L);
+    const uint64_t target = __umul64hi(r, T);
+    // first candidate whose inclusive prefix exceeds the target
+    // exactly one candidate c has prefix_{c-1} <= target < prefix_c with w_c > 0
+    uint64_t prefix = 0;
+    uint32_t sel1 = 0, sx = 0, sy = 0;
+#pragma unroll
+    for (int c = 0; c < MAXD; ++c) {
+        const uint64_t before = prefix;
+        prefix += w[c];
+        const bool take = before <= target && target < prefix;
+        sel1 |= take ? (uint32_t)c + 1 : 0u;
+        sx |= take ? rec[c].x : 0u;
+        sy |= take ? rec[c].y : 0u;
+    }
+    if (sel1 == 0) return false;   // unreachable when T > 0
+    const uint4 rs4 = make_uint4(sx, sy, 0, 0);
+    const uint32_t xsel = rs4.x & 0xFFFFFFu;
+    const uint32_t esel = rs + sel1 - 1;
+    if (j == 0) {
+        *path_s = e_lo + esel;
+        atomicOr(&bits[xsel >> 5], 1u << (xsel & 31));
+    }
+    cs += s_cost[esel];
+    ++s;
+    u = xsel;
+    rs = rs4.y;
+    d = rs4.x >> 24;
+    if (u == dst) {
+        ok = true;
+        return false;
+    }
+    return true;
+}
+
+template <int L, int MAXD, int SL>
+__device__ __forceinline__ bool lds_steps_repl(const uint4 *s_rw, const uint32_t *s_cost, uint32_t *bits,
+                                               uint32_t j, uint32_t m_last, uint64_t myr, uint32_t dst,
+                                               uint32_t max_steps, uint32_t NA, uint32_t e_lo, uint32_t &u,
+                                               uint32_t &rs, uint32_t &d, uint32_t &s, uint32_t &ncand, uint64_t &cs,
+                                               bool &ok, uint32_t *path)
+{
+    if (s >= max_steps || !lds_step_repl<L, MAXD, SL>(s_rw, s_cost, bits, j, m_last, myr, dst, e_lo, u, rs, d, s,
+                                                      ncand, cs, ok, path + (size_t)s * NA))
+        return false;
+    if constexpr (SL + 1 < L)
+        return lds_steps_repl<L, MAXD, SL + 1>(s_rw, s_cost, bits, j, m_last, myr, dst, max_steps, NA, e_lo, u, rs,
+                                               d, s, ncand, cs, ok, path);
+    return true;
+}
+
 // Walk for graphs whose roads fit in LDS.  One block serves `apb` ants of one
 // vehicle (blocks_per_vehicle = bpv).  Prologue: the block derives the
 // vehicle's goal term for every node and stages, per road, the head node,
@@ -625,7 +704,7 @@ __device__ __forceinline__ bool lds_steps(const uint2 *s_rec, const uint64_t *s_
 // fixed DPP pattern.  A step is two dependent LDS reads (road record,
 // visited word).  The path cost is summed after the walk, only for ants that
 // arrive.
-template <int L, int CH>
+template <int L, int CH, bool REPL>
 __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
 {
     extern __shared__ uint64_t s_mem[];
@@ -659,8 +738,14 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
             const uint32_t c = a.cost[e], t = tau(e), tl = a.tail[e] - n_lo;
             const uint32_t xl = (r.x & 0xFFFFFFu) - n_lo;
             const uint32_t eta = eta_of((int64_t)c + (int64_t)s_aux[xl] - (int64_t)s_aux[tl]);
-            s_w[le] = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
-            s_rec[le] = make_uint2(xl | (r.x & 0xFF000000u), r.y - e_lo);
+            const uint64_t wgt = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
+            if (REPL) {
+                ((uint4 *)s_mem)[le] = make_uint4(xl | (r.x & 0xFF000000u), r.y - e_lo, (uint32_t)wgt,
+                                                  (uint32_t)(wgt >> 32));
+            } else {
+                s_w[le] = wgt;
+                s_rec[le] = make_uint2(xl | (r.x & 0xFF000000u), r.y - e_lo);
+            }
             s_cost[le] = c;
         }
     }
@@ -687,9 +772,14 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
         const uint32_t it = a.iter + slot_iter(a.pher, v, 0);
         for (;;) {
             const uint64_t myr = philox_u64(q.qid, k, it, s + j, a.seed_lo, a.seed_hi);
-            if (!lds_steps<L, CH, 0>(s_rec, s_w, s_cost, bits, j, m_last, myr, q.dst - n_lo, a.max_steps, NA, e_lo,
-                                     u, rs, d, s, ncand, cs64, ok, path))
+            if (REPL) {
+                if (!lds_steps_repl<L, CH, 0>((const uint4 *)s_mem, s_cost, bits, j, m_last, myr, q.dst - n_lo,
+                                              a.max_steps, NA, e_lo, u, rs, d, s, ncand, cs64, ok, path))
+                    break;
+            } else if (!lds_steps<L, CH, 0>(s_rec, s_w, s_cost, bits, j, m_last, myr, q.dst - n_lo, a.max_steps, NA,
+                                            e_lo, u, rs, d, s, ncand, cs64, ok, path)) {
                 break;
+            }
         }
         const uint32_t cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
         if (ok) {
@@ -1442,6 +1532,7 @@ struct WalkPlan {
     uint32_t maxd = 4;             // candidate bound the kernels are built for
     bool legacy = false;           // k_walk for every vehicle (graphs with 2^24 nodes or more)
     uint32_t lds_lanes = 4, lds_apb = 0, lds_bpv = 0;
+    bool lds_repl = false;                // replicated-lane steps (k_walk_lds<..., true>)
     size_t lds_bytes[4] = {0, 0, 0, 0};   // [1..3]: dynamic LDS of each LDS size-class launch, 0 = none
     bool glb = false;              // some city is served by k_walk_glb
     uint32_t glb_lanes = 4, glb_apb = 0, bloom_log2 = 11, glb_nwords = 0;
@@ -1453,7 +1544,7 @@ template <int L, int MAXD>
 int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup)
 {
     constexpr int CH = (MAXD + L - 1) / L;
-    auto kern = k_walk_lds<L, CH>;
+    auto kern = pl.lds_repl ? k_walk_lds<L, MAXD, true> : k_walk_lds<L, CH, false>;
     if (setup) {   // before any launch: allow the largest dynamic LDS of the plan
         const size_t mx = std::max(pl.lds_bytes[1], std::max(pl.lds_bytes[2], pl.lds_bytes[3]));
         if (mx > 65536)
@@ -1544,6 +1635,10 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     pl.city_class.assign(g->n_inst, 0);
     if (pl.legacy) return pl;
     pl.lds_lanes = lanes_or(env_u32("GMACOP_WALK_LANES", 4), 4);
+    {
+        const char *var = getenv("GMACOP_LDS_VARIANT");
+        pl.lds_repl = var && strcmp(var, "repl") == 0 && pl.maxd <= 8;
+    }
     pl.lds_apb = std::max<uint32_t>(1, std::min<uint32_t>(p->ants, 512 / pl.lds_lanes));
     pl.lds_bpv = (p->ants + pl.lds_apb - 1) / pl.lds_apb;
     const size_t t3 = (size_t)max_lds, t2 = t3 / 2, t1 = t3 / 4;
@@ -1875,7 +1970,8 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
             (uint64_t)(uintptr_t)g->iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
             p->rho_q16, p->tau0_q16, p->tau_min_q16, p->tau_max_q16, p->q_deposit, p->theta, p->th_max,
             p->t_max_ms, p->vmax_kmh, p->mode, p->flags & GMACOP_NO_LOAD_UPDATE, p->seed, p->iter_offset,
-            plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, (uint64_t)plan.lds_bytes[1],
+            plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.lds_repl,
+            (uint64_t)plan.lds_bytes[1],
             (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3], plan.glb, plan.glb_lanes, plan.glb_apb,
             plan.bloom_log2, plan.glb_nwords, (uint64_t)lds, (uint64_t)(uintptr_t)g->vclass,
             (uint64_t)(uintptr_t)g->lazy, (uint64_t)(uintptr_t)g->dep_ind, (uint64_t)(uintptr_t)g->touched,

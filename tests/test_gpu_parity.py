@@ -205,10 +205,12 @@ def test_grid32_full_against_stored_oracle_results():
     assert hashlib.sha256(got["load"].tobytes()).hexdigest() == want["load_sha256"]
 
 
-@pytest.mark.parametrize("kernel,lanes,bloom", [("legacy", 1, 11), ("global", 1, 11), ("global", 2, 11),
-                                                ("global", 4, 11), ("global", 8, 11), ("global", 4, 8),
-                                                ("lds", 1, 11), ("lds", 2, 11), ("lds", 4, 11), ("lds", 8, 11)])
-def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes, bloom):
+@pytest.mark.parametrize("kernel,lanes,bloom,variant", [
+    ("legacy", 1, 11, ""), ("global", 1, 11, ""), ("global", 2, 11, ""), ("global", 4, 11, ""),
+    ("global", 8, 11, ""), ("global", 4, 8, ""), ("lds", 1, 11, ""), ("lds", 2, 11, ""), ("lds", 4, 11, ""),
+    ("lds", 8, 11, ""), ("lds", 1, 11, "repl"), ("lds", 2, 11, "repl"), ("lds", 4, 11, "repl"),
+    ("lds", 8, 11, "repl")])
+def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes, bloom, variant):
     """Every walker shape (first global-memory walker, global walker with
     1-8 lanes per ant and a small Bloom filter that sends most visited tests
     to the exact bitset, LDS-staged roads with 1-8 lanes) reproduces the
@@ -217,8 +219,9 @@ def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes, bloom)
     monkeypatch.setenv("GMACOP_WALK_LANES", str(lanes))
     monkeypatch.setenv("GMACOP_GLB_LANES", str(lanes))
     monkeypatch.setenv("GMACOP_BLOOM_LOG2", str(bloom))
+    monkeypatch.setenv("GMACOP_LDS_VARIANT", variant)
     w = grid32(vehicles=24, ants=40, iterations=6)
-    check(f"{w.name}_{kernel}_L{lanes}_b{bloom}", w.graph, w.vehicles, w.params)
+    check(f"{w.name}_{kernel}_L{lanes}_b{bloom}{variant}", w.graph, w.vehicles, w.params)
     rng = np.random.default_rng(23)
     g = planar_graph(1500, rng)
     V = random_od(g.n, 12, rng)
