@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed pass (roofline becomes null)")
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the timed steps, run 4 device-to-device copies of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the plain-per-query vs batched comparison (independent mode)")
     args = ap.parse_args()
@@ -195,6 +198,13 @@ def main():
     p_run = dict(p, flags=p["flags"] | (0 if args.eager else gmacop.HIP_GRAPH))
 
     print(f"[bench] {w.name}: n={g.n} m={g.m} vehicles={len(V)} warmup={args.warmup}", file=sys.stderr, flush=True)
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib << 18, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         gmacop.gmacop_route_batch_device(G, b, p_run, stream)
     stream_obj.synchronize()

@@ -38,6 +38,8 @@ def digest(a) -> str:
 
 WORKLOADS = {
     "grid32": lambda: workloads.grid32(),
+    "planar100k": lambda: workloads.planar100k(),
+    "multicity": lambda: workloads.multi_city(),
 }
 
 

@@ -187,13 +187,16 @@ def _digest_routes(path_edges, path_len):
     return h.hexdigest()
 
 
-def test_grid32_full_against_stored_oracle_results():
-    """Full 32x32 workload (256 vehicles x 128 ants x 100 iterations): the
-    oracle's results were stored by tests/golden/make_expected.py."""
-    path = os.path.join(HERE, "golden", "grid32_expected.json")
+@pytest.mark.parametrize("name", ["grid32", "planar100k", "multicity"])
+def test_full_workload_against_stored_oracle_results(name):
+    """Full-size workloads (32x32 grid: 256 vehicles x 128 ants x 100 it;
+    100k-node planar city: 4096 x 64 x 50; 64 packed cities: 10466 x 32 x 30)
+    against the oracle's results stored by tests/golden/make_expected.py."""
+    from workloads import multi_city, planar100k
+    path = os.path.join(HERE, "golden", f"{name}_expected.json")
     with open(path) as f:
         want = json.load(f)
-    w = grid32()
+    w = {"grid32": grid32, "planar100k": planar100k, "multicity": multi_city}[name]()
     assert w.name == want["workload"] and w.params == want["params"]
     announce(w.name)
     got = run_gpu(w.graph, w.vehicles, w.params)
@@ -203,7 +206,6 @@ def test_grid32_full_against_stored_oracle_results():
     assert _digest_routes(got["path_edges"], got["path_len"]) == want["routes_sha256"]
     assert hashlib.sha256(got["tau"].tobytes()).hexdigest() == want["tau_sha256"]
     assert hashlib.sha256(got["load"].tobytes()).hexdigest() == want["load_sha256"]
-
 
 @pytest.mark.parametrize("kernel,lanes,bloom,variant", [
     ("legacy", 1, 11, ""), ("global", 1, 11, ""), ("global", 2, 11, ""), ("global", 4, 11, ""),

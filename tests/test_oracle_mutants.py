@@ -1,0 +1,54 @@
+"""The oracle's pins catch plausible mistakes: each mutant below plants one
+error in a copy of the oracle's C source (a wrong constant, sign, comparison,
+tie-break, clamp or dropped term), is built on the CPU, and must fail at
+least one test of test_oracle_pins.py."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "gmacop_oracle.c")
+
+MUTANTS = {
+    "philox_multiplier": ("0xD2511F53u * c[0]", "0xD2511F55u * c[0]"),
+    "isqrt_bound": ("if (mid * mid <= x) lo = mid;", "if (mid * mid < x) lo = mid;"),
+    "free_flow_units": ("g->len_dm[e] * 360u / g->speed_kmh[e]", "g->len_dm[e] * 36u / g->speed_kmh[e]"),
+    "red_wait_formula": ("red * red / (2 * C)", "red * red / C"),
+    "preempt_tie_break": ("load[e] > load[best_edge[v]]", "load[e] >= load[best_edge[v]]"),
+    "th_max_comparison": ("load[e] > p->th_max", "load[e] >= p->th_max"),
+    "congestion_divisor": ("(uint64_t)t0[e] * load[e] / p->theta", "(uint64_t)t0[e] * load[e] / (p->theta + 1)"),
+    "goal_sign": ("(int64_t)g->x_dm[node] - g->x_dm[dst]", "(int64_t)g->x_dm[node] + g->x_dm[dst]"),
+    "eta_scale": ("((uint64_t)1 << 26) / d", "((uint64_t)1 << 25) / d"),
+    "roulette_strict": ("if (prefix > target) return j;", "if (prefix >= target) return j;"),
+    "visited_ignored": ("if (visited[x]) { wbuf[j] = 0; continue; }", "if (0) { wbuf[j] = 0; continue; }"),
+    "deposit_amount": ("const uint64_t d = p->q_deposit / cs;", "const uint64_t d = p->q_deposit / (cs + 1);"),
+    "evaporation_factor": ("(uint64_t)tau * (65536u - p->rho_q16) / 65536u",
+                           "(uint64_t)tau * (65535u - p->rho_q16) / 65536u"),
+    "best_tie": ("(uint32_t)(iter_key >> 32) < *best_cost", "(uint32_t)(iter_key >> 32) <= *best_cost"),
+    "load_increment": ("load[path_edges[(size_t)v * S + i]] += 1;", "load[path_edges[(size_t)v * S + i]] += 2;"),
+}
+
+
+@pytest.fixture(scope="module")
+def source():
+    with open(SRC) as f:
+        return f.read()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, source, name):
+    old, new = MUTANTS[name]
+    assert source.count(old) == 1, f"mutation site for {name} not found exactly once"
+    mut = tmp_path / "gmacop_oracle.c"
+    mut.write_text(source.replace(old, new))
+    (tmp_path / "gmacop_oracle.h").write_text(open(os.path.join(ROOT, "oracle", "gmacop_oracle.h")).read())
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", str(lib), str(mut)])
+    env = dict(os.environ, GMACOP_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(HERE, "test_oracle_pins.py")], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"

@@ -554,3 +554,42 @@ def test_parameter_checks(orc):
     assert orc.route_rc(g, V, dict(p, beta=2, alpha=1, tau_max_q16=2 ** 30 - 1)) == 0       # 30+32+2 = 64
     assert orc.route_rc(g, V, dict(p, beta=3, alpha=1, tau_max_q16=2 ** 24)) == orc.E_RANGE  # 25+48+2 = 75
     assert orc.route_rc(g, V, dict(p, q_deposit=2 ** 62)) == orc.E_RANGE
+
+
+def test_deposit_closed_form_on_a_chain(orc):
+    """Chain 0 -> 1 -> 2 (with the reverse roads): every ant takes the only
+    route, cost C = 2 * 7200 ms.  With 3 ants each deposits floor(q / C) =
+    455111 per road, so after iteration 1: tau = 65536/2 + 3*455111 =
+    1398101; after iteration 2: floor(1398101/2) + 1365333 = 2064383.  The
+    reverse roads only evaporate: 65536 >> 2 = 16384."""
+    g = from_edges(3, [0, 1, 1, 2], [1, 0, 2, 1], len_dm=1000)
+    V = veh([0], [2], qid=[4])
+    p = default_params(ants=3, iterations=2, max_steps=2, vmax_kmh=0, rho_q16=0x8000, q_deposit=65536 * 100000)
+    res = orc.route(g, V, p)
+    assert res["cost_ms"][0] == 14400 and res["path_len"][0] == 2
+    fwd = [0, 2]          # CSR order: (0,1), (1,0), (1,2), (2,1)
+    back = [1, 3]
+    assert [int(res["tau"][e]) for e in fwd] == [2064383, 2064383]
+    assert [int(res["tau"][e]) for e in back] == [16384, 16384]
+    assert res["load"].tolist() == [1, 0, 1, 0]
+
+
+def _draw_top_bit(orc, seed, qid, ant, it, step):
+    x = orc.philox4x32_10([qid, ant, it, step], [seed & 0xFFFFFFFF, seed >> 32])
+    return int(x[1]) >> 31            # r = x1 * 2^32 + x0; r >= 2^63 iff top bit of x1
+
+
+def test_equal_cost_route_found_later_does_not_replace_best(orc):
+    """Diamond 0 -> {1, 2} -> 3, both routes cost the same, pheromone frozen
+    (rho = 0, q = 0).  Every ant arrives with the same cost, so each
+    iteration's best ant is ant 0, which takes road 0->1 iff its first draw
+    is below 2^63.  The vehicle's best route must stay the one found in
+    iteration 0 even when iteration 1's best ant takes the other branch."""
+    g = from_edges(4, [0, 0, 1, 2], [1, 2, 3, 3], len_dm=1000)
+    p = default_params(ants=2, iterations=2, max_steps=3, vmax_kmh=0, rho_q16=0, q_deposit=0)
+    qid = next(q for q in range(1000) if _draw_top_bit(orc, p["seed"], q, 0, 0, 0) !=
+               _draw_top_bit(orc, p["seed"], q, 0, 1, 0))
+    res = orc.route(g, veh([0], [3], qid=[qid]), p)
+    first_edge = 0 if _draw_top_bit(orc, p["seed"], qid, 0, 0, 0) == 0 else 1
+    assert res["path_edges"][0, :2].tolist() == [first_edge, 2 + first_edge]
+    assert res["cost_ms"][0] == 14400
