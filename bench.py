@@ -32,6 +32,32 @@ BYTES_PER_CANDIDATE = 20
 BYTES_PER_DEPOSIT_ROAD = 12
 
 
+PMC_PROFILE = os.path.join(ROOT, "profiles", "k_walk_lds_grid32x32_256veh_128ants_100it.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_14244_amd", "csrc", "gmacop.hip")
+
+
+def measured_walk_traffic():
+    """HBM bytes per walk launch from the committed PMC profile (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the copy-kernel calibration), or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        vals = {}
+        with open(PMC_PROFILE) as f:
+            for line in f:
+                if ":" in line and line.split(":")[0].strip().startswith(("pmc_", "source_sha256")):
+                    k, v = line.split(":", 1)
+                    vals[k.strip()] = v.strip()
+        with open(KERNEL_SOURCE, "rb") as f:
+            cur = hashlib.sha256(f.read()).hexdigest()[:16]
+        if vals.get("source_sha256_prefix") != cur:
+            return None
+        return (float(vals["pmc_walk_fetch_kib"]) * float(vals["pmc_fetch_scale"]) +
+                float(vals["pmc_walk_write_kib"]) * float(vals["pmc_write_scale"])) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -241,8 +267,10 @@ def main():
         bytes_per_launch = (BYTES_PER_SELECTION * ksel + BYTES_PER_CANDIDATE * kt["candidates"] +
                             BYTES_PER_DEPOSIT_ROAD * kt["deposit_roads"]) / nl
         achieved = bytes_per_launch / (walk_ms * 1e-3) / 1e9
+        traffic = measured_walk_traffic() if args.workload == "grid32" else None
         roofline = {"bound": "hbm", "kernel": "k_walk", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                    "traffic": None if traffic is None else round(traffic),
                     "avg_launch_ms": round(walk_ms, 5), "launches_timed": nl,
                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
                     "selections_per_launch": ksel / nl, "mean_candidates_per_selection": kt["candidates"] / ksel,
