@@ -66,6 +66,9 @@ constexpr uint32_t kRoadCostCap = 1u << 31;
 constexpr uint64_t kNoKey = ~0ull;
 constexpr int kWave = 64;
 constexpr uint32_t kMaxDegree = 32;
+constexpr size_t kStaticLds = 256;   // static LDS of the walker kernels (block aggregates), kept out of the dynamic budget
+constexpr int kLdsClasses = 6;       // LDS walker classes: 1..3 k_walk_ldsr, 4..6 k_walk_lds (three size tiers each)
+constexpr bool is_road_class(uint32_t c) { return c >= 1 && c <= 3; }
 constexpr uint32_t kLdsBitsetMaxNodes = 4096;   // 512 B of visited bits per ant in LDS
 
 // ---------------------------------------------------------------------------
@@ -93,11 +96,37 @@ __device__ __forceinline__ uint64_t philox_u64(uint32_t c0, uint32_t c1, uint32_
     return ((uint64_t)c1 << 32) | c0;
 }
 
-// floor(sqrt(x)) for x < 2^63: double-precision estimate, then exact
+// The same generator advanced a few rounds at a time (rounds R0..R1-1 of the
+// ten; key words k0, k1 as given to round 0), so that a walker can spread one
+// draw over several steps.  The empty asm keeps the rounds where they are
+// written instead of letting the compiler move them next to their first use.
+struct PhiloxState {
+    uint32_t c0, c1, c2, c3;
+};
+
+template <int R0, int R1>
+__device__ __forceinline__ void philox_rounds(PhiloxState &x, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = R0; r < R1; ++r) {
+        const uint32_t kr0 = k0 + (uint32_t)r * 0x9E3779B9u, kr1 = k1 + (uint32_t)r * 0xBB67AE85u;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x.c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x.c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x.c1 ^ kr0, n2 = (uint32_t)(p0 >> 32) ^ x.c3 ^ kr1;
+        x.c0 = n0;
+        x.c1 = (uint32_t)p1;
+        x.c2 = n2;
+        x.c3 = (uint32_t)p0;
+    }
+    if (R1 > R0) asm volatile("" : "+v"(x.c0), "+v"(x.c1), "+v"(x.c2), "+v"(x.c3));
+}
+
+// floor(sqrt(x)) for x < 2^63: a floating-point estimate (single precision
+// below 2^48, where it is within a few units), then exact integer
 // correction so that s*s <= x < (s+1)*(s+1).
 __device__ __forceinline__ uint64_t isqrt_u64(uint64_t x)
 {
-    uint64_t s = (uint64_t)sqrt((double)x);
+    uint64_t s = x < (1ull << 48) ? (uint64_t)__fsqrt_rn((float)x) : (uint64_t)sqrt((double)x);
     while (s * s > x) --s;
     while ((s + 1) * (s + 1) <= x) ++s;
     return s;
@@ -519,6 +548,7 @@ struct LdsWalkArgs {
     uint32_t t_local;
     const uint2 *rec;          // [m] static: head | head_out_degree << 24, head's first out-road
     const uint32_t *tail;      // [m] static: tail node of each road
+    const uint32_t *rev_ptr, *rev_edge;   // roads into each node (k_walk_ldsr)
     const int32_t *x, *y;
     const gmacop_od *od;
     uint32_t n, m, nq, ants, apb, bpv, max_steps, alpha, beta, kgoal, nwords;
@@ -528,6 +558,79 @@ struct LdsWalkArgs {
     uint64_t *iter_key, *steps, *counters;
     uint32_t *iter_max;    // longest walk of this iteration
 };
+
+// End of an LDS walker block: every ant of the block has walked, so the
+// staged road records are no longer read and their space becomes one u64
+// deposit accumulator per city road.  Arriving ants add floor(q / cost) to
+// the roads of their path with LDS atomics (exact integer sums, so the order
+// does not matter); then the block adds each non-zero sum to the global
+// deposit once, and its best (cost, ant) key and step counters once, instead
+// of one global atomic per road of every path -- those contend on the roads
+// that many ants share.
+template <int L>
+__device__ __forceinline__ void lds_block_finish(const LdsWalkArgs &a, uint64_t *s_mem, uint32_t e_lo,
+                                                 uint32_t e_cnt, uint32_t v, uint32_t k, bool active, bool ok,
+                                                 uint32_t s, uint32_t cs, uint32_t ncand, uint32_t j,
+                                                 const uint32_t *path, uint32_t NA)
+{
+    __shared__ uint64_t s_blk[6];   // best key, steps, candidates, arrivals, deposited roads, longest walk
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    uint64_t *acc = s_mem;          // [e_cnt]
+    const bool arrived = active && ok;
+    const uint64_t dpos = arrived ? a.q_deposit / cs : 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < e_cnt; i += nthr) acc[i] = 0;
+    if (tid < 6) s_blk[tid] = tid == 0 ? ~0ull : 0;
+    __syncthreads();
+    if (dpos) {
+        // lane j takes path entries j, j+L, ...; eight loads in flight before the LDS adds
+        uint32_t i = j;
+        for (; i + 7 * L < s; i += 8 * L) {
+            uint32_t e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e[u] = path[(size_t)(i + u * L) * NA];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) atomicAdd((unsigned long long *)&acc[e[u] - e_lo], (unsigned long long)dpos);
+        }
+        for (; i < s; i += L) atomicAdd((unsigned long long *)&acc[path[(size_t)i * NA] - e_lo], (unsigned long long)dpos);
+    }
+    if (arrived && j == 0) atomicMin((unsigned long long *)&s_blk[0], (unsigned long long)(((uint64_t)cs << 32) | k));
+    // counters: one contribution per ant (its first lane), summed over the wave, then over the block
+    uint64_t cnt = (active && j == 0) ? s : 0, cand = (active && j == 0) ? ncand : 0;
+    uint64_t arr = (arrived && j == 0) ? 1 : 0, dh = (arrived && j == 0) ? s : 0;
+    uint32_t smax = active ? s : 0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off);
+        cand += __shfl_xor(cand, off);
+        arr += __shfl_xor(arr, off);
+        dh += __shfl_xor(dh, off);
+        smax = max(smax, (uint32_t)__shfl_xor((int)smax, off));
+    }
+    if ((tid & (kWave - 1)) == 0 && cnt) {
+        atomicAdd((unsigned long long *)&s_blk[1], (unsigned long long)cnt);
+        atomicAdd((unsigned long long *)&s_blk[2], (unsigned long long)cand);
+        atomicAdd((unsigned long long *)&s_blk[3], (unsigned long long)arr);
+        atomicAdd((unsigned long long *)&s_blk[4], (unsigned long long)dh);
+        atomicMax((unsigned long long *)&s_blk[5], (unsigned long long)smax);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < e_cnt; i += nthr) {
+        const uint64_t x = acc[i];
+        if (x) a.depv.add(v, e_lo + i, x);
+    }
+    if (tid == 0) {
+        if (s_blk[0] != ~0ull) atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)s_blk[0]);
+        if (s_blk[1]) {
+            atomicAdd((unsigned long long *)a.steps, (unsigned long long)s_blk[1]);
+            atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)s_blk[1]);
+            atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)s_blk[2]);
+            atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)s_blk[3]);
+            atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)s_blk[4]);
+            atomicMax(a.iter_max, (uint32_t)s_blk[5]);
+        }
+    }
+}
 
 // One step of an ant on LDS-staged roads (see k_walk_lds).  SL = step index
 // modulo L: the group lane that drew this step's Philox word.  Returns false
@@ -701,9 +804,9 @@ __device__ __forceinline__ bool lds_steps_repl(const uint4 *s_rw, const uint32_t
 // it) is taken.  The L lanes draw Philox words for L consecutive steps at
 // once (the counter does not depend on the path), so one draw serves L
 // steps; the step loop is unrolled by L so each step reads its word with a
-// fixed DPP pattern.  A step is two dependent LDS reads (road record,
-// visited word).  The path cost is summed after the walk, only for ants that
-// arrive.
+// fixed DPP pattern.  A step is three dependent LDS reads (road record,
+// visited word, chosen road's cost).  Deposits are gathered per block
+// (lds_block_finish).
 template <int L, int CH, bool REPL>
 __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
 {
@@ -759,16 +862,16 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
     const bool active = grp < a.apb && k < a.ants;
     const uint32_t NA = a.nq * a.ants;
     const uint32_t ant = v * a.ants + k;
-    uint32_t s = 0, ncand = 0, arrived = 0;
+    uint32_t s = 0, ncand = 0, cs = 0;
+    bool ok = false;
+    uint32_t *path = a.path + ant;
     if (active) {
         uint32_t *bits = s_aux + grp * nws;
         uint32_t u = q.src - n_lo;
         uint32_t rs = a.row_ptr[q.src] - e_lo, d = a.row_ptr[q.src + 1] - a.row_ptr[q.src];
         if (j == 0) atomicOr(&bits[u >> 5], 1u << (u & 31));
-        bool ok = false;
         uint64_t cs64 = 0;
         const uint32_t m_last = e_cnt - 1;
-        uint32_t *path = a.path + ant;
         const uint32_t it = a.iter + slot_iter(a.pher, v, 0);
         for (;;) {
             const uint64_t myr = philox_u64(q.qid, k, it, s + j, a.seed_lo, a.seed_hi);
@@ -781,51 +884,199 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
                 break;
             }
         }
-        const uint32_t cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
-        if (ok) {
-            arrived = 1;
-            const uint64_t dpos = a.q_deposit / cs;
-            if (dpos) {
-                // lane j deposits on roads j, j+L, ...; path entries loaded ahead of the atomics
-                uint32_t i = j;
-                for (; i + 3 * L < s; i += 4 * L) {
-                    const uint32_t e0 = path[(size_t)i * NA], e1 = path[(size_t)(i + L) * NA];
-                    const uint32_t e2 = path[(size_t)(i + 2 * L) * NA], e3 = path[(size_t)(i + 3 * L) * NA];
-                    a.depv.add(v, e0, dpos);
-                    a.depv.add(v, e1, dpos);
-                    a.depv.add(v, e2, dpos);
-                    a.depv.add(v, e3, dpos);
-                }
-                for (; i < s; i += L) a.depv.add(v, path[(size_t)i * NA], dpos);
-            }
-            if (j == 0)
-                atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
-        }
+        cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
         if (j == 0) {
             a.ant_len[ant] = s;
             a.ant_cost[ant] = ok ? cs : kNoCost;
         }
     }
-    // counters: only the first lane of each group contributes
-    uint64_t cnt = j == 0 ? s : 0, cand = j == 0 ? ncand : 0, arr = j == 0 ? arrived : 0,
-             dh = (j == 0 && arrived) ? s : 0;
-    uint32_t smax = s;
+    lds_block_finish<L>(a, s_mem, e_lo, e_cnt, v, k, active, ok, s, cs, ncand, j, path, NA);
+}
+
+// Value of the last lane of the group (the group total of an inclusive prefix).
+template <int L>
+__device__ __forceinline__ uint64_t grp_last(uint64_t v)
+{
+    if (L == 1) return v;
+    if (L == 2) return dpp64<kDppQuad(1, 1, 3, 3)>(v);
+    if (L == 4) return dpp64<kDppQuad(3, 3, 3, 3)>(v);
+    return __shfl(v, L - 1, L);
+}
+
+// One step of the road-visited walker (k_walk_ldsr).  Every read of the step
+// depends only on the current node (its first out-road rs and first in-road
+// rv), so the road records, costs, visited words and the node's in-roads come
+// back in one LDS round trip.  The current node's in-roads are then marked
+// visited; none of them is a candidate of this step (no self-loops).  The
+// lane holding the chosen road writes the path entry and adds the road's cost
+// to its own partial sum; only the chosen record crosses lanes.
+template <int L, int CH, int SL>
+__device__ __forceinline__ bool rv_step(const uint4 *s_R, const uint32_t *s_cost, const uint32_t *s_rev,
+                                        uint32_t *bits, uint32_t j, uint32_t m_last, uint64_t myr, uint32_t e_lo,
+                                        PhiloxState &nx, uint32_t k0, uint32_t k1, uint32_t &rs, uint32_t &d,
+                                        uint32_t &rv, uint32_t &ind, uint32_t &s, uint32_t &ncand, uint64_t &cs,
+                                        bool &ok, uint32_t *path_s)
+{
+    uint4 R[CH];
+    uint32_t cst[CH], vw[CH], inr[CH], idx[CH];
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        cnt += __shfl_xor(cnt, off);
-        cand += __shfl_xor(cand, off);
-        arr += __shfl_xor(arr, off);
-        dh += __shfl_xor(dh, off);
-        smax = max(smax, (uint32_t)__shfl_xor((int)smax, off));
+    for (int c = 0; c < CH; ++c) {
+        idx[c] = min(rs + (uint32_t)(c * L) + j, m_last);   // always a valid address
+        inr[c] = s_rev[min(rv + (uint32_t)(c * L) + j, m_last)];
+        R[c] = s_R[idx[c]];
+        cst[c] = s_cost[idx[c]];
+        vw[c] = bits[idx[c] >> 5];
     }
-    if ((threadIdx.x & (kWave - 1)) == 0 && cnt) {
-        atomicAdd((unsigned long long *)a.steps, (unsigned long long)cnt);
-        atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)cnt);
-        atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)cand);
-        atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)arr);
-        atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)dh);
-        atomicMax(a.iter_max, smax);
+    __builtin_amdgcn_sched_barrier(0);   // every read above is in flight before the first wait
+    philox_rounds<SL * 10 / L, (SL + 1) * 10 / L>(nx, k0, k1);   // next block's draw, in the read latency
+    // (no branch: lanes past the in-degree OR zero into an in-range word, so
+    // nothing below waits for these writes)
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+        atomicOr(&bits[inr[c] >> 5], (uint32_t)(c * L) + j < ind ? 1u << (inr[c] & 31) : 0u);
+    ncand += d;
+    uint64_t w[CH], incl[CH];
+    uint64_t base = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const bool live = (uint32_t)(c * L) + j < d && !((vw[c] >> (idx[c] & 31)) & 1u);
+        w[c] = live ? (((uint64_t)R[c].w << 32) | R[c].z) : 0;
+        incl[c] = grp_prefix<L>(w[c], j) + base;
+        base = grp_last<L>(incl[c]);
     }
+    const uint64_t T = base;
+    uint64_t r = myr;
+    if (L == 2) r = SL == 0 ? dpp64<kDppQuad(0, 0, 2, 2)>(myr) : dpp64<kDppQuad(1, 1, 3, 3)>(myr);
+    if (L == 4) r = dpp64<kDppQuad(SL, SL, SL, SL)>(myr);
+    if (L >= 8) r = __shfl(myr, SL, L);
+    const uint64_t target = __umul64hi(r, T);
+    // the candidate whose prefix interval [incl - w, incl) holds the target (none when T == 0)
+    uint32_t sx = 0, sy = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const bool hit = incl[c] - w[c] <= target && target < incl[c];
+        sx |= hit ? R[c].x : 0u;
+        sy |= hit ? R[c].y : 0u;
+        cs += hit ? cst[c] : 0u;
+        if (hit) *path_s = e_lo + idx[c];
+    }
+    sx = grp_or<L>(sx);
+    sy = grp_or<L>(sy);
+    const bool moved = T != 0;
+    s += moved ? 1u : 0u;
+    ok = moved && (sx >> 31) != 0;
+    rs = sx & 0xFFFFu;
+    d = (sx >> 16) & 0x7FFFu;
+    rv = sy & 0xFFFFu;
+    ind = sy >> 16;
+    return moved && !ok;
+}
+
+// (ps: this ant's path entry of the current step; it advances by NA per step)
+template <int L, int CH, int SL>
+__device__ __forceinline__ bool rv_steps(const uint4 *s_R, const uint32_t *s_cost, const uint32_t *s_rev,
+                                         uint32_t *bits, uint32_t j, uint32_t m_last, uint64_t myr, uint32_t e_lo,
+                                         PhiloxState &nx, uint32_t k0, uint32_t k1, uint32_t max_steps, uint32_t NA,
+                                         uint32_t &rs, uint32_t &d, uint32_t &rv, uint32_t &ind, uint32_t &s,
+                                         uint32_t &ncand, uint64_t &cs, bool &ok, uint32_t *&ps)
+{
+    if (s >= max_steps || !rv_step<L, CH, SL>(s_R, s_cost, s_rev, bits, j, m_last, myr, e_lo, nx, k0, k1, rs, d, rv,
+                                              ind, s, ncand, cs, ok, ps))
+        return false;
+    ps += NA;
+    if constexpr (SL + 1 < L)
+        return rv_steps<L, CH, SL + 1>(s_R, s_cost, s_rev, bits, j, m_last, myr, e_lo, nx, k0, k1, max_steps, NA, rs,
+                                       d, rv, ind, s, ncand, cs, ok, ps);
+    return true;
+}
+
+// Walk for cities whose roads fit in LDS, with visited state kept per road:
+// entering a node marks every road into it, so a candidate road is live
+// when its own bit is clear -- the bit's address is known from the current
+// node alone, and a step needs a single LDS round trip.  Same block layout,
+// Philox schedule, choice table and results as k_walk_lds.  LDS per block:
+// per road a 16-byte record (head's first out-road | head out-degree << 16 |
+// head-is-destination << 31; head's first in-road | head in-degree << 16;
+// choice weight), its cost and its entry of the city's in-road list, then
+// the goal terms (prologue) overlaid by the visited road bits of each ant.
+// City-local road ids must stay below 2^16.
+template <int L, int CH>
+__global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
+{
+    extern __shared__ uint64_t s_mem[];
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    const uint32_t v = blockIdx.x / a.bpv, part = blockIdx.x % a.bpv;
+    if (a.vclass[v] != a.cls) return;                // whole block: another walker serves this vehicle
+    const gmacop_od q = a.od[v];
+    const uint32_t city = a.node_inst[q.src];
+    const uint32_t n_lo = a.inst_off[city], n_cnt = a.inst_off[city + 1] - n_lo;
+    const uint32_t e_lo = a.inst_eoff[city], e_cnt = a.inst_eoff[city + 1] - e_lo;
+    uint4 *s_R = (uint4 *)s_mem;                                  // [e_cnt]
+    uint32_t *s_cost = (uint32_t *)(s_R + e_cnt);                 // [e_cnt]
+    uint32_t *s_rev = s_cost + e_cnt;                             // [e_cnt] city-local roads, grouped by head
+    uint32_t *s_aux = s_rev + e_cnt;                              // goal terms, then visited road bits
+    const uint32_t nws = ((e_cnt + 31) / 32) | 1u;                // visited words per ant (odd stride)
+
+    {
+        const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
+        for (uint32_t i = tid; i < n_cnt; i += nthr)
+            s_aux[i] = (uint32_t)goal_ms(a.x[n_lo + i], a.y[n_lo + i], dx, dy, a.kgoal);
+    }
+    __syncthreads();
+    {
+        const bool a1b2 = a.alpha == 1 && a.beta == 2;
+        const PherRead tau = pher_at(a.pher, v, a.t_local);
+        for (uint32_t le = tid; le < e_cnt; le += nthr) {
+            const uint32_t e = e_lo + le;
+            const uint2 r = a.rec[e];
+            const uint32_t c = a.cost[e], t = tau(e), tl = a.tail[e] - n_lo;
+            const uint32_t h = r.x & 0xFFFFFFu, xl = h - n_lo;
+            const uint32_t eta = eta_of((int64_t)c + (int64_t)s_aux[xl] - (int64_t)s_aux[tl]);
+            const uint64_t wgt = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
+            const uint32_t ri = a.rev_ptr[h], rn = a.rev_ptr[h + 1] - ri;
+            s_R[le] = make_uint4((r.y - e_lo) | ((r.x >> 24) << 16) | (h == q.dst ? 0x80000000u : 0u),
+                                 (ri - e_lo) | (rn << 16), (uint32_t)wgt, (uint32_t)(wgt >> 32));
+            s_cost[le] = c;
+            s_rev[le] = a.rev_edge[e] - e_lo;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < nws * a.apb; i += nthr) s_aux[i] = 0;
+    __syncthreads();
+
+    const uint32_t grp = tid / L, j = tid % L;
+    const uint32_t k = part * a.apb + grp;
+    const bool active = grp < a.apb && k < a.ants;
+    const uint32_t NA = a.nq * a.ants;
+    const uint32_t ant = v * a.ants + k;
+    uint32_t s = 0, ncand = 0, cs = 0;
+    bool ok = false;
+    uint32_t *path = a.path + ant;
+    if (active) {
+        uint32_t *bits = s_aux + grp * nws;
+        uint32_t rs = a.row_ptr[q.src] - e_lo, d = a.row_ptr[q.src + 1] - a.row_ptr[q.src];
+        uint32_t rv = a.rev_ptr[q.src] - e_lo, ind = a.rev_ptr[q.src + 1] - a.rev_ptr[q.src];
+        uint64_t csl = 0;   // this lane's share of the path cost
+        const uint32_t m_last = e_cnt - 1;
+        const uint32_t it = a.iter + slot_iter(a.pher, v, 0);
+        uint64_t myr = philox_u64(q.qid, k, it, s + j, a.seed_lo, a.seed_hi);
+        uint32_t *ps = path;
+        for (;;) {
+            // the draw of the next L steps advances inside these L steps
+            PhiloxState nx{q.qid, k, it, s + L + j};
+            if (!rv_steps<L, CH, 0>(s_R, s_cost, s_rev, bits, j, m_last, myr, e_lo, nx, a.seed_lo, a.seed_hi,
+                                    a.max_steps, NA, rs, d, rv, ind, s, ncand, csl, ok, ps))
+                break;
+            myr = ((uint64_t)nx.c1 << 32) | nx.c0;
+        }
+        const uint64_t cs64 = grp_sum<L>(csl);
+        cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
+        if (j == 0) {
+            a.ant_len[ant] = s;
+            a.ant_cost[ant] = ok ? cs : kNoCost;
+        }
+    }
+    lds_block_finish<L>(a, s_mem, e_lo, e_cnt, v, k, active, ok, s, cs, ncand, j, path, NA);
 }
 
 struct GlbWalkArgs {
@@ -847,7 +1098,7 @@ struct GlbWalkArgs {
     uint32_t *iter_max;
 };
 
-constexpr uint8_t kWalkerNone = 0, kWalkerGlobal = 8;   // 1..3: LDS walker size classes
+constexpr uint8_t kWalkerNone = 0, kWalkerGlobal = 8;   // 1..6: LDS walker classes
 
 __device__ __forceinline__ uint32_t bloom_h1(uint32_t x, uint32_t lg) { return (x * 0x9E3779B1u) >> (32 - lg); }
 __device__ __forceinline__ uint32_t bloom_h2(uint32_t x, uint32_t lg)
@@ -931,11 +1182,11 @@ __device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, const PherRead &t
     if (sel_c == 0) return false;   // unreachable when T > 0; keeps every index in range
     const uint32_t xsel = sel_x & 0xFFFFFFu;
     if (j == 0) {
-        *path_s = rs + sel_c - 1;
         const uint32_t xl = xsel - n_lo;
         const uint32_t b1 = bloom_h1(xl, lg), b2 = bloom_h2(xl, lg);
         atomicOr(&bloom[b1 >> 5], 1u << (b1 & 31));
         atomicOr(&bloom[b2 >> 5], 1u << (b2 & 31));
+        *path_s = rs + sel_c - 1;
         atomicOr(&gb[xl >> 5], 1u << (xl & 31));
     }
     hist[3] = hist[2];
@@ -1315,7 +1566,7 @@ unsigned blocks_for(uint64_t work, unsigned per_block)
 
 struct gmacop_graph {
     int device = 0;
-    uint32_t n = 0, m = 0, n_inst = 1, max_deg = 0;
+    uint32_t n = 0, m = 0, n_inst = 1, max_deg = 0, max_indeg = 0;
     int max_lds = 65536;               // dynamic LDS a block may use on this device
     std::vector<uint32_t> inst_off;    // host copy, [n_inst+1]
     // static graph (device)
@@ -1533,20 +1784,30 @@ struct WalkPlan {
     bool legacy = false;           // k_walk for every vehicle (graphs with 2^24 nodes or more)
     uint32_t lds_lanes = 4, lds_apb = 0, lds_bpv = 0;
     bool lds_repl = false;                // replicated-lane steps (k_walk_lds<..., true>)
-    size_t lds_bytes[4] = {0, 0, 0, 0};   // [1..3]: dynamic LDS of each LDS size-class launch, 0 = none
+    uint32_t road_maxd = 4;               // candidate and in-road bound of k_walk_ldsr
+    size_t lds_bytes[kLdsClasses + 1] = {};   // [c]: dynamic LDS of LDS class c's launch, 0 = none
     bool glb = false;              // some city is served by k_walk_glb
     uint32_t glb_lanes = 4, glb_apb = 0, bloom_log2 = 11, glb_nwords = 0;
     size_t glb_lds_bytes = 0;
-    std::vector<uint8_t> city_class;      // per city: LDS class 1..3, or 0 = global walker
+    std::vector<uint8_t> city_class;      // per city: LDS class 1..kLdsClasses, or 0 = global walker
+    bool any_lds() const
+    {
+        for (int c = 1; c <= kLdsClasses; ++c)
+            if (lds_bytes[c]) return true;
+        return false;
+    }
 };
 
 template <int L, int MAXD>
 int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup)
 {
     constexpr int CH = (MAXD + L - 1) / L;
-    auto kern = pl.lds_repl ? k_walk_lds<L, MAXD, true> : k_walk_lds<L, CH, false>;
-    if (setup) {   // before any launch: allow the largest dynamic LDS of the plan
-        const size_t mx = std::max(pl.lds_bytes[1], std::max(pl.lds_bytes[2], pl.lds_bytes[3]));
+    const bool road = is_road_class(wa.cls);
+    auto kern = road ? k_walk_ldsr<L, CH> : pl.lds_repl ? k_walk_lds<L, MAXD, true> : k_walk_lds<L, CH, false>;
+    if (setup) {   // before any launch: allow the largest dynamic LDS of the classes this kernel serves
+        size_t mx = 0;
+        for (uint32_t c = 1; c <= kLdsClasses; ++c)
+            if (is_road_class(c) == road) mx = std::max(mx, pl.lds_bytes[c]);
         if (mx > 65536)
             HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mx));
         return GMACOP_OK;
@@ -1560,7 +1821,7 @@ int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, b
 template <int L>
 int launch_walk_lds_d(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup)
 {
-    switch (pl.maxd) {
+    switch (is_road_class(wa.cls) ? pl.road_maxd : pl.maxd) {
     case 4: return launch_walk_lds<L, 4>(wa, pl, st, setup);
     case 8: return launch_walk_lds<L, 8>(wa, pl, st, setup);
     case 16: return launch_walk_lds<L, 16>(wa, pl, st, setup);
@@ -1568,7 +1829,32 @@ int launch_walk_lds_d(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st,
     }
 }
 
-int launch_walk_lds_any(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup = false)
+int launch_walk_lds_any(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup = false);
+
+// Before the first launch: raise the dynamic-LDS limit of both LDS walker kernels as the plan needs.
+int setup_walk_lds(LdsWalkArgs wa, const WalkPlan &pl, hipStream_t st)
+{
+    int rc = GMACOP_OK;
+    for (uint32_t c : {1u, 4u}) {
+        wa.cls = c;
+        if ((rc = launch_walk_lds_any(wa, pl, st, true))) return rc;
+    }
+    return rc;
+}
+
+// One launch per LDS class that some city of the plan uses.
+int launch_walk_lds_classes(LdsWalkArgs wa, const WalkPlan &pl, hipStream_t st)
+{
+    int rc = GMACOP_OK;
+    for (uint32_t c = 1; c <= (uint32_t)kLdsClasses && !rc; ++c)
+        if (pl.lds_bytes[c]) {
+            wa.cls = c;
+            rc = launch_walk_lds_any(wa, pl, st);
+        }
+    return rc;
+}
+
+int launch_walk_lds_any(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, bool setup)
 {
     switch (pl.lds_lanes) {
     case 1: return launch_walk_lds_d<1>(wa, pl, st, setup);
@@ -1618,13 +1904,16 @@ uint32_t env_u32(const char *name, uint32_t dflt)
 
 uint32_t lanes_or(uint32_t L, uint32_t dflt) { return (L == 1 || L == 2 || L == 4 || L == 8) ? L : dflt; }
 
-// The per-size schedule.  Every city whose roads, goal terms and visited
-// bits fit in LDS goes to k_walk_lds, in one of three size classes (up to a
+// The per-size schedule.  Every city whose staged roads and visited state
+// fit in LDS goes to an LDS walker, in one of three size tiers (up to a
 // quarter, a half, or all of the LDS a block may use), so small cities are
-// not charged the largest city's LDS; larger cities go to k_walk_glb.
-// GMACOP_WALK_KERNEL (lds | global | legacy), GMACOP_WALK_LANES,
-// GMACOP_GLB_LANES (1, 2, 4, 8) and GMACOP_BLOOM_LOG2 (8..16) override the
-// choices for tuning; results do not depend on them.
+// not charged the largest city's LDS: k_walk_ldsr (visited state per road,
+// classes 1..3) where its layout fits, else k_walk_lds (visited state per
+// node, classes 4..6); larger cities go to k_walk_glb.  GMACOP_WALK_KERNEL
+// (lds | global | legacy), GMACOP_LDS_VARIANT (node | repl: k_walk_lds
+// only), GMACOP_WALK_LANES, GMACOP_GLB_LANES (1, 2, 4, 8) and
+// GMACOP_BLOOM_LOG2 (8..16) override the choices for tuning; results do not
+// depend on them.
 WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
 {
     WalkPlan pl;
@@ -1635,21 +1924,38 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     pl.city_class.assign(g->n_inst, 0);
     if (pl.legacy) return pl;
     pl.lds_lanes = lanes_or(env_u32("GMACOP_WALK_LANES", 4), 4);
+    bool road_ok = true;
     {
         const char *var = getenv("GMACOP_LDS_VARIANT");
-        pl.lds_repl = var && strcmp(var, "repl") == 0 && pl.maxd <= 8;
+        const bool repl = var && strcmp(var, "repl") == 0;
+        pl.lds_repl = repl && pl.maxd <= 8;
+        const uint32_t md = std::max(g->max_deg, g->max_indeg);
+        road_ok = !(var && (strcmp(var, "node") == 0 || repl)) && md <= kMaxDegree;
+        pl.road_maxd = md <= 4 ? 4 : md <= 8 ? 8 : md <= 16 ? 16 : 32;
     }
     pl.lds_apb = std::max<uint32_t>(1, std::min<uint32_t>(p->ants, 512 / pl.lds_lanes));
     pl.lds_bpv = (p->ants + pl.lds_apb - 1) / pl.lds_apb;
-    const size_t t3 = (size_t)max_lds, t2 = t3 / 2, t1 = t3 / 4;
+    const size_t t3 = (size_t)max_lds - kStaticLds, t2 = t3 / 2, t1 = t3 / 4;   // static block aggregates aside
     uint32_t glb_nodes = 0;
     for (uint32_t i = 0; i < g->n_inst; ++i) {
         const uint32_t nc = g->inst_off[i + 1] - g->inst_off[i];
         const uint32_t ec = g->inst_eoff[i + 1] - g->inst_eoff[i];
-        const size_t need = (size_t)ec * 16 + (size_t)((ec + 1) & ~1u) * 4 +
-                            std::max<size_t>(nc, (size_t)(((nc + 31) / 32) | 1u) * pl.lds_apb) * 4;
+        // k_walk_ldsr: 16-byte record, cost and in-road entry per road; goal terms, then road bits per ant
+        const size_t need_r = (size_t)ec * 24 + std::max<size_t>(nc, (size_t)(((ec + 31) / 32) | 1u) * pl.lds_apb) * 4;
+        // k_walk_lds: 8-byte record, weight and cost per road; goal terms, then node bits per ant
+        const size_t need_n = (size_t)ec * 16 + (size_t)((ec + 1) & ~1u) * 4 +
+                              std::max<size_t>(nc, (size_t)(((nc + 31) / 32) | 1u) * pl.lds_apb) * 4;
+        auto tier = [&](size_t need) -> uint8_t { return need <= t1 ? 1 : need <= t2 ? 2 : need <= t3 ? 3 : 0; };
         uint8_t c = 0;
-        if (!force_global && ec > 0) c = need <= t1 ? 1 : need <= t2 ? 2 : need <= t3 ? 3 : 0;
+        size_t need = 0;
+        if (!force_global && ec > 0) {
+            if (road_ok && ec < 65536 && (c = tier(need_r)) != 0) {
+                need = need_r;
+            } else if ((c = tier(need_n)) != 0) {
+                c += 3;
+                need = need_n;
+            }
+        }
         pl.city_class[i] = c;
         if (c)
             pl.lds_bytes[c] = std::max(pl.lds_bytes[c], need);
@@ -1695,7 +2001,10 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
     // incoming roads of every node (the approaches of its signal)
     std::vector<uint32_t> rev_ptr(g->n + 1, 0), rev_edge(g->m);
     for (uint32_t e = 0; e < g->m; ++e) rev_ptr[d->col[e] + 1]++;
-    for (uint32_t v = 0; v < g->n; ++v) rev_ptr[v + 1] += rev_ptr[v];
+    for (uint32_t v = 0; v < g->n; ++v) {
+        g->max_indeg = std::max(g->max_indeg, rev_ptr[v + 1]);
+        rev_ptr[v + 1] += rev_ptr[v];
+    }
     {
         std::vector<uint32_t> fill(rev_ptr.begin(), rev_ptr.end() - 1);
         for (uint32_t e = 0; e < g->m; ++e) rev_edge[fill[d->col[e]]++] = e;
@@ -1874,7 +2183,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     wa.iter_max = g->iter_max;
     LdsWalkArgs la{};
     la.row_ptr = g->row_ptr; la.col = g->col; la.cost = g->cost; la.pher = pv; la.depv = dv; la.x = g->x; la.y = g->y;
-    la.rec = g->rec; la.tail = g->tail;
+    la.rec = g->rec; la.tail = g->tail; la.rev_ptr = g->rev_ptr; la.rev_edge = g->rev_edge;
     la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev; la.inst_eoff = g->inst_eoff_dev; la.vclass = g->vclass;
     la.od = od; la.n = g->n; la.m = g->m; la.nq = nq; la.ants = p->ants; la.apb = plan.lds_apb; la.bpv = plan.lds_bpv;
     la.max_steps = S; la.alpha = p->alpha; la.beta = p->beta; la.kgoal = wa.kgoal; la.nwords = nwords;
@@ -1896,8 +2205,8 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     ga.seed_hi = wa.seed_hi; ga.q_deposit = p->q_deposit; ga.path = g->path; ga.ant_len = g->ant_len;
     ga.ant_cost = g->ant_cost; ga.gbits = g->gbits; ga.iter_key = g->iter_key; ga.steps = steps;
     ga.counters = g->counters; ga.iter_max = g->iter_max;
-    const bool any_lds = !plan.legacy && (plan.lds_bytes[1] || plan.lds_bytes[2] || plan.lds_bytes[3]);
-    if (any_lds && (rc = launch_walk_lds_any(la, plan, st, true))) return rc;
+    const bool any_lds = !plan.legacy && plan.any_lds();
+    if (any_lds && (rc = setup_walk_lds(la, plan, st))) return rc;
 
     const bool timing = (p->flags & GMACOP_TIME_KERNELS) != 0;
     const bool use_graph = (p->flags & GMACOP_HIP_GRAPH) && !timing && st != nullptr;
@@ -1932,11 +2241,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
                           : md <= 16 ? launch_walk<16>(wt, lds, st)
                                      : launch_walk<32>(wt, lds, st);
                 } else {
-                    for (uint32_t c = 1; c <= 3 && !erc; ++c)
-                        if (plan.lds_bytes[c]) {
-                            lt.cls = c;
-                            erc = launch_walk_lds_any(lt, plan, st);
-                        }
+                    erc = launch_walk_lds_classes(lt, plan, st);
                     if (!erc && plan.glb) erc = launch_walk_glb_any(gt, plan, st);
                 }
                 if (erc || (erc = kt.stop(&tm))) return erc;
@@ -1970,9 +2275,9 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
             (uint64_t)(uintptr_t)g->iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
             p->rho_q16, p->tau0_q16, p->tau_min_q16, p->tau_max_q16, p->q_deposit, p->theta, p->th_max,
             p->t_max_ms, p->vmax_kmh, p->mode, p->flags & GMACOP_NO_LOAD_UPDATE, p->seed, p->iter_offset,
-            plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.lds_repl,
-            (uint64_t)plan.lds_bytes[1],
-            (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3], plan.glb, plan.glb_lanes, plan.glb_apb,
+            plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.lds_repl, plan.road_maxd,
+            (uint64_t)plan.lds_bytes[1], (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3],
+            (uint64_t)plan.lds_bytes[4], (uint64_t)plan.lds_bytes[5], (uint64_t)plan.lds_bytes[6], plan.glb, plan.glb_lanes, plan.glb_apb,
             plan.bloom_log2, plan.glb_nwords, (uint64_t)lds, (uint64_t)(uintptr_t)g->vclass,
             (uint64_t)(uintptr_t)g->lazy, (uint64_t)(uintptr_t)g->dep_ind, (uint64_t)(uintptr_t)g->touched,
             (uint64_t)(uintptr_t)g->touched_n, (uint64_t)(uintptr_t)g->dev_gen, tcap};
@@ -2335,20 +2640,16 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
     {
         LdsWalkArgs la{};
         la.row_ptr = g->row_ptr; la.col = g->col; la.cost = s->cost; la.pher = pv; la.depv = dv; la.x = g->x;
-        la.y = g->y; la.rec = g->rec; la.tail = g->tail; la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev;
+        la.y = g->y; la.rec = g->rec; la.tail = g->tail; la.rev_ptr = g->rev_ptr; la.rev_edge = g->rev_edge;
+        la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev;
         la.inst_eoff = g->inst_eoff_dev; la.vclass = s->vclass; la.od = s->slot_od; la.n = g->n; la.m = g->m;
         la.nq = NS; la.ants = A; la.apb = plan.lds_apb; la.bpv = plan.lds_bpv; la.max_steps = S; la.alpha = p.alpha;
         la.beta = p.beta; la.kgoal = kgoal; la.nwords = 0; la.seed_lo = (uint32_t)p.seed;
         la.seed_hi = (uint32_t)(p.seed >> 32); la.iter = p.iter_offset; la.t_local = 0; la.q_deposit = p.q_deposit;
         la.path = s->path; la.ant_len = s->ant_len; la.ant_cost = s->ant_cost; la.iter_key = s->iter_key;
         la.steps = s->steps; la.counters = g->counters; la.iter_max = g->iter_max;
-        const bool any_lds = plan.lds_bytes[1] || plan.lds_bytes[2] || plan.lds_bytes[3];
-        if (any_lds && (rc = launch_walk_lds_any(la, plan, st, true))) return rc;
-        for (uint32_t c = 1; c <= 3; ++c)
-            if (plan.lds_bytes[c]) {
-                la.cls = c;
-                if ((rc = launch_walk_lds_any(la, plan, st))) return rc;
-            }
+        if (plan.any_lds() && ((rc = setup_walk_lds(la, plan, st)) || (rc = launch_walk_lds_classes(la, plan, st))))
+            return rc;
         if (plan.glb) {
             GlbWalkArgs ga{};
             ga.rec16 = g->rec16; ga.row_ptr = g->row_ptr; ga.cost = s->cost; ga.x = g->x; ga.y = g->y;

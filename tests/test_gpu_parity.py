@@ -211,12 +211,13 @@ def test_full_workload_against_stored_oracle_results(name):
     ("legacy", 1, 11, ""), ("global", 1, 11, ""), ("global", 2, 11, ""), ("global", 4, 11, ""),
     ("global", 8, 11, ""), ("global", 4, 8, ""), ("lds", 1, 11, ""), ("lds", 2, 11, ""), ("lds", 4, 11, ""),
     ("lds", 8, 11, ""), ("lds", 1, 11, "repl"), ("lds", 2, 11, "repl"), ("lds", 4, 11, "repl"),
-    ("lds", 8, 11, "repl")])
+    ("lds", 8, 11, "repl"), ("lds", 1, 11, "node"), ("lds", 2, 11, "node"), ("lds", 4, 11, "node"),
+    ("lds", 8, 11, "node")])
 def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes, bloom, variant):
     """Every walker shape (first global-memory walker, global walker with
     1-8 lanes per ant and a small Bloom filter that sends most visited tests
-    to the exact bitset, LDS-staged roads with 1-8 lanes) reproduces the
-    oracle exactly."""
+    to the exact bitset, LDS-staged roads with 1-8 lanes and visited state
+    per road (default) or per node) reproduces the oracle exactly."""
     monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
     monkeypatch.setenv("GMACOP_WALK_LANES", str(lanes))
     monkeypatch.setenv("GMACOP_GLB_LANES", str(lanes))
@@ -244,6 +245,21 @@ def test_mixed_walkers_in_one_iteration():
     p = default_params(ants=16, iterations=5, max_steps=500, vmax_kmh=70)
     check("mixed_cities", packed, V, p)
     check("mixed_cities_indep", packed, V, dict(p, mode=gmacop.MODE_INDEPENDENT), state=False)
+
+
+def test_all_walker_kinds_in_one_iteration():
+    """One launch sequence where a small grid uses the per-road-visited LDS
+    walker, a 2000-node city whose per-road layout does not fit LDS at 128
+    ants per block uses the per-node LDS walker, and a 12000-node city the
+    global walker; all deposit on one shared pheromone vector."""
+    rng = np.random.default_rng(43)
+    gs = [grid_graph(8, 8, rng), planar_graph(2000, rng), planar_graph(12000, rng)]
+    packed = pack_graphs(gs)
+    off = packed.inst_node_off.astype(np.int64)
+    vs = [random_od(gi.n, 3, rng, node_lo=int(off[i]), qid0=3 * i) for i, gi in enumerate(gs)]
+    V = Vehicles(qid=np.concatenate([v.qid for v in vs]), src=np.concatenate([v.src for v in vs]),
+                 dst=np.concatenate([v.dst for v in vs]))
+    check("three_walker_kinds", packed, V, default_params(ants=128, iterations=3, max_steps=400, vmax_kmh=70))
 
 
 def test_hip_graph_replays_match_eager():
