@@ -69,6 +69,7 @@ constexpr uint32_t kMaxDegree = 32;
 constexpr size_t kStaticLds = 256;   // static LDS of the walker kernels (block aggregates), kept out of the dynamic budget
 constexpr int kLdsClasses = 6;       // LDS walker classes: 1..3 k_walk_ldsr, 4..6 k_walk_lds (three size tiers each)
 constexpr bool is_road_class(uint32_t c) { return c >= 1 && c <= 3; }
+constexpr uint64_t kGlbWordsBudget = 4ull << 30;   // bytes of per-slot visited words of k_walk_glb
 constexpr uint32_t kLdsBitsetMaxNodes = 4096;   // 512 B of visited bits per ant in LDS
 
 // ---------------------------------------------------------------------------
@@ -121,12 +122,19 @@ __device__ __forceinline__ void philox_rounds(PhiloxState &x, uint32_t k0, uint3
     if (R1 > R0) asm volatile("" : "+v"(x.c0), "+v"(x.c1), "+v"(x.c2), "+v"(x.c3));
 }
 
-// floor(sqrt(x)) for x < 2^63: a floating-point estimate (single precision
-// below 2^48, where it is within a few units), then exact integer
-// correction so that s*s <= x < (s+1)*(s+1).
+// floor(sqrt(x)) for x < 2^63 from a correctly rounded single-precision
+// square root, then exact integer correction so that s*s <= x < (s+1)^2.
+// Below 2^44 (distances under 2^22 dm) the estimate is within 0.75 of
+// sqrt(x), so one step each way suffices; above, the correction loops (the
+// estimate is within 2^8 up to 2^63, and (s+1)^2 cannot overflow there).
 __device__ __forceinline__ uint64_t isqrt_u64(uint64_t x)
 {
-    uint64_t s = x < (1ull << 48) ? (uint64_t)__fsqrt_rn((float)x) : (uint64_t)sqrt((double)x);
+    uint64_t s = (uint64_t)__fsqrt_rn((float)x);
+    if (x < (1ull << 44)) {
+        s -= s * s > x ? 1u : 0u;
+        s += (s + 1) * (s + 1) <= x ? 1u : 0u;
+        return s;
+    }
     while (s * s > x) --s;
     while ((s + 1) * (s + 1) <= x) ++s;
     return s;
@@ -251,6 +259,7 @@ struct EdgeInitArgs {
     const uint16_t *speed, *green;
     uint32_t *t0, *wf, *tau, *load, *cnt;
     uint64_t *dep;
+    uint32_t *mir;             // road records of the global walker (8 words per road) or NULL
 };
 
 // Per road: free-flow time t0 = floor(len * 360 / speed) in [1, 2^31];
@@ -272,6 +281,7 @@ __global__ void k_init_edges(EdgeInitArgs a)
     }
     a.wf[e] = (uint32_t)w;
     a.tau[e] = a.tau0;
+    if (a.mir) a.mir[(size_t)e * 8 + 5] = a.tau0;
     a.load[e] = a.base_load[e];
     a.dep[e] = 0;
     a.cnt[e] = 0;
@@ -292,6 +302,7 @@ struct CostArgs {
     uint32_t n, theta, th_max;
     const uint32_t *rev_ptr, *rev_edge, *cycle, *load, *t0, *wf;
     uint32_t *cost;
+    uint32_t *mir;             // road records of the global walker (8 words per road) or NULL
 };
 
 // Per intersection v: the approach (incoming road) with the longest
@@ -320,7 +331,9 @@ __global__ void k_cost(CostArgs a)
         const uint32_t t0 = a.t0[e];
         const uint64_t travel = L <= a.theta ? t0 : (uint64_t)t0 * L / a.theta;
         uint64_t c = travel + (green ? 0u : a.wf[e]);
-        a.cost[e] = (uint32_t)(c > kRoadCostCap ? kRoadCostCap : c);
+        c = c > kRoadCostCap ? kRoadCostCap : c;
+        a.cost[e] = (uint32_t)c;
+        if (a.mir) a.mir[(size_t)e * 8 + 4] = (uint32_t)c;
     }
 }
 
@@ -1079,21 +1092,32 @@ __global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
     lds_block_finish<L>(a, s_mem, e_lo, e_cnt, v, k, active, ok, s, cs, ncand, j, path, NA);
 }
 
+// A vehicle served by k_walk_glb, with the walk's start data (k_glb_list).
+struct GlbVeh {
+    uint32_t v, qid, src, dst;
+    uint32_t rs, d, n_lo, pad;   // source's out-road range; first node of the city
+    int32_t dx, dy;              // destination coordinates
+    uint32_t hu_lo, hu_hi;       // goal term of the source
+};
+
 struct GlbWalkArgs {
-    const uint4 *rec16;        // [m] static: head | head_deg << 24, head's first out-road, head x, head y
-    const uint32_t *row_ptr, *cost;
-    const int32_t *x, *y;
-    const uint32_t *node_lo;   // [n] first node of the node's city
-    const uint8_t *vclass;     // [nq] walker serving each vehicle (kWalkerGlobal here)
+    // [m][2] per road: (head | head_deg << 24, head's first out-road, head x, head y), then
+    // (cost, pheromone in shared mode, 0, 0) -- one 32-byte record, so a candidate is one line
+    const uint4 *rec32;
     PherView pher;
     DepView depv;
-    const gmacop_od *od;
-    uint32_t n, m, nq, ants, apb, max_steps, alpha, beta, kgoal;
-    uint32_t nwords;           // visited-bit words per ant (largest city)
-    uint32_t bloom_log2;       // Bloom filter of 2^bloom_log2 bits per ant in LDS
-    uint32_t seed_lo, seed_hi, iter, t_local;
+    const GlbVeh *veh;         // [*glb_n] vehicles of this walker
+    const uint32_t *glb_n;
+    uint32_t *tickets;         // [0]: next ticket (vehicle-major: ticket = list position * ants + ant), [1]: waves done
+    uint32_t *vlen;            // [nq] longest walk of each vehicle in this launch (orders the next list)
+    uint64_t *gwords;          // [slots][nw2] visited words: current walk's epoch << 32 | 32 node bits
+    uint32_t *slot_epoch;      // [slots] epoch of each slot's last walk
+    uint32_t m, ants, apb, max_steps, alpha, beta, kgoal;
+    uint32_t nw2;              // visited words per slot (largest city / 32)
+    uint32_t bloom_log2;       // Bloom filter of 2^bloom_log2 bits per slot in LDS
+    uint32_t seed_lo, seed_hi, iter, t_local, nq;
     uint64_t q_deposit;
-    uint32_t *path, *ant_len, *ant_cost, *gbits;
+    uint32_t *path, *ant_len, *ant_cost;
     uint64_t *iter_key, *steps, *counters;
     uint32_t *iter_max;
 };
@@ -1106,54 +1130,89 @@ __device__ __forceinline__ uint32_t bloom_h2(uint32_t x, uint32_t lg)
     return ((x ^ 0x5BD1E995u) * 0x85EBCA77u + 0x165667B1u) >> (32 - lg);
 }
 
-// One step of an ant whose roads are read from global memory (k_walk_glb).
+// Per-lane-group state of a k_walk_glb walk.
+struct GlbWalk {
+    PherRead tau;
+    uint32_t v, k, qid, dst, n_lo, it;
+    int32_t dx, dy;
+    uint32_t u, rs, d, s, ncand;
+    int64_t hu;
+    uint64_t cs;
+    uint32_t hist[4];          // the last four nodes entered
+    uint32_t *path;            // this ant's path column
+    uint64_t *pw;              // visited word of the node entered last (group lane 0; nullptr: none)
+    uint64_t pval;             // its value, loaded when the node was entered
+    uint32_t pbit;
+    bool ok;
+};
+
+// One step of a k_walk_glb walk.  Candidate roads are 16-byte record
+// gathers (head, head's out-road range, head coordinates) plus their cost and
+// pheromone.  The visited test is exact but rarely touches memory: the last
+// four nodes are in registers, then a per-slot Bloom filter in LDS (two hash
+// bits); only when it reports "maybe" is the slot's visited word read.  Entering a node
+// sets its visited bit by read-modify-write of the slot's word: the word is
+// loaded when the node is entered and written at the next step, behind that
+// step's loads (the node stays in the register history meanwhile, and the
+// same lane's later reads of the word come after the write).  A word written
+// by an earlier walk carries an older epoch and counts as empty, so nothing
+// is cleared between walks.
 template <int L, int CH, int SL>
-__device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, const PherRead &tau, uint32_t *bloom, uint32_t *gb,
-                                         uint32_t n_lo, int32_t dx, int32_t dy, uint32_t j, uint64_t myr,
-                                         uint32_t dst, uint32_t &u, uint32_t &rs, uint32_t &d, int64_t &hu,
-                                         uint32_t (&hist)[4], uint32_t &s, uint32_t &ncand, uint64_t &cs, bool &ok,
-                                         uint32_t *path_s)
+__device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, GlbWalk &w, uint32_t *bloom, uint64_t *gw,
+                                         uint32_t epoch, uint32_t j, uint64_t myr)
 {
-    ncand += d;
+    w.ncand += w.d;
     const uint32_t lg = a.bloom_log2;
-    uint64_t w[CH], incl[CH];
+    uint64_t wt[CH], incl[CH];
     uint4 rec[CH];
     uint32_t cst[CH];
     int64_t hx[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-        const uint32_t idx = min(rs + (uint32_t)(c * L) + j, a.m - 1);   // always a valid address
-        rec[c] = a.rec16[idx];
-        cst[c] = a.cost[idx];
-        w[c] = tau(idx);
+    for (int c = 0; c < CH; ++c) {   // lanes past the out-degree load nothing
+        const uint32_t o = (uint32_t)(c * L) + j, idx = w.rs + o;
+        uint4 r0 = make_uint4(0, 0, 0, 0), r1 = make_uint4(0, 0, 0, 0);
+        uint32_t tl = 0;
+        if (o < w.d) {
+            r0 = a.rec32[2 * (size_t)idx];
+            r1 = a.rec32[2 * (size_t)idx + 1];
+            if (!w.tau.dense) tl = w.tau(idx);
+        }
+        rec[c] = r0;
+        cst[c] = r1.x;
+        wt[c] = w.tau.dense ? r1.y : tl;
+    }
+    if (w.pw) {   // group lane 0: the visited bit of the node entered last step
+        const uint64_t old = w.pval;
+        *w.pw = ((uint32_t)(old >> 32) == epoch ? old : (uint64_t)epoch << 32) | w.pbit;
+        w.pw = nullptr;
     }
     uint64_t base = 0;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         const uint32_t xh = rec[c].x & 0xFFFFFFu;
-        bool live = (uint32_t)(c * L) + j < d;
-        live = live && xh != hist[0] && xh != hist[1] && xh != hist[2] && xh != hist[3];
+        bool live = (uint32_t)(c * L) + j < w.d;
+        live = live && xh != w.hist[0] && xh != w.hist[1] && xh != w.hist[2] && xh != w.hist[3];
         if (live) {
-            const uint32_t xl = xh - n_lo;
+            const uint32_t xl = xh - w.n_lo;
             const uint32_t b1 = bloom_h1(xl, lg), b2 = bloom_h2(xl, lg);
             if (((bloom[b1 >> 5] >> (b1 & 31)) & (bloom[b2 >> 5] >> (b2 & 31)) & 1u) != 0) {
-                // Bloom filter says "maybe": the exact bitset decides (read at the device-coherent level)
-                const uint32_t word = __hip_atomic_load(&gb[xl >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                live = ((word >> (xl & 31)) & 1u) == 0;
+                // Bloom filter says "maybe": the slot's visited word decides (read at the device-coherent level)
+                const uint64_t vw = __hip_atomic_load(&gw[xl >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                live = (uint32_t)(vw >> 32) != epoch || (((uint32_t)vw >> (xl & 31)) & 1u) == 0;
             }
         }
         hx[c] = 0;
         if (live) {
-            hx[c] = goal_ms((int32_t)rec[c].z, (int32_t)rec[c].w, dx, dy, a.kgoal);
-            const uint32_t eta = eta_of((int64_t)cst[c] + hx[c] - hu);
-            const uint32_t t = (uint32_t)w[c];
-            w[c] = (a.alpha == 1 && a.beta == 2) ? (uint64_t)t * (eta * eta)
-                                                 : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
+            hx[c] = goal_ms((int32_t)rec[c].z, (int32_t)rec[c].w, w.dx, w.dy, a.kgoal);
+            const uint32_t eta = eta_of((int64_t)cst[c] + hx[c] - w.hu);
+            const uint32_t t = (uint32_t)wt[c];
+            wt[c] = (a.alpha == 1 && a.beta == 2) ? (uint64_t)t * (eta * eta)
+                                                  : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
         } else {
-            w[c] = 0;
+            wt[c] = 0;
         }
-        incl[c] = grp_prefix<L>(w[c], j) + base;
-        base += grp_sum<L>(w[c]);
+        incl[c] = grp_prefix<L>(wt[c], j) + base;
+        base += grp_sum<L>(wt[c]);
     }
     const uint64_t T = base;
     if (T == 0) return false;   // dead end
@@ -1165,7 +1224,7 @@ __device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, const PherRead &t
     uint32_t sel_x = 0, sel_y = 0, sel_c = 0, sel_cost = 0, sel_hlo = 0, sel_hhi = 0;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-        const bool hit = w[c] != 0 && incl[c] - w[c] <= target && target < incl[c];
+        const bool hit = wt[c] != 0 && incl[c] - wt[c] <= target && target < incl[c];
         sel_x |= hit ? rec[c].x : 0u;
         sel_y |= hit ? rec[c].y : 0u;
         sel_c |= hit ? (uint32_t)(c * L) + j + 1 : 0u;
@@ -1182,148 +1241,251 @@ __device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, const PherRead &t
     if (sel_c == 0) return false;   // unreachable when T > 0; keeps every index in range
     const uint32_t xsel = sel_x & 0xFFFFFFu;
     if (j == 0) {
-        const uint32_t xl = xsel - n_lo;
+        w.path[(size_t)w.s * a.nq * a.ants] = w.rs + sel_c - 1;
+        const uint32_t xl = xsel - w.n_lo;
         const uint32_t b1 = bloom_h1(xl, lg), b2 = bloom_h2(xl, lg);
         atomicOr(&bloom[b1 >> 5], 1u << (b1 & 31));
         atomicOr(&bloom[b2 >> 5], 1u << (b2 & 31));
-        *path_s = rs + sel_c - 1;
-        atomicOr(&gb[xl >> 5], 1u << (xl & 31));
+        w.pw = &gw[xl >> 5];
+        w.pbit = 1u << (xl & 31);
+        w.pval = __hip_atomic_load(w.pw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    hist[3] = hist[2];
-    hist[2] = hist[1];
-    hist[1] = hist[0];
-    hist[0] = xsel;
-    cs += sel_cost;
-    hu = (int64_t)(((uint64_t)sel_hhi << 32) | sel_hlo);
-    ++s;
-    u = xsel;
-    rs = sel_y;
-    d = sel_x >> 24;
-    if (u == dst) {
-        ok = true;
+    w.hist[3] = w.hist[2];
+    w.hist[2] = w.hist[1];
+    w.hist[1] = w.hist[0];
+    w.hist[0] = xsel;
+    w.cs += sel_cost;
+    w.hu = (int64_t)(((uint64_t)sel_hhi << 32) | sel_hlo);
+    ++w.s;
+    w.u = xsel;
+    w.rs = sel_y;
+    w.d = sel_x >> 24;
+    if (w.u == w.dst) {
+        w.ok = true;
         return false;
     }
     return true;
 }
 
 template <int L, int CH, int SL>
-__device__ __forceinline__ bool glb_steps(const GlbWalkArgs &a, const PherRead &tau, uint32_t *bloom, uint32_t *gb,
-                                          uint32_t n_lo, int32_t dx, int32_t dy, uint32_t j, uint64_t myr,
-                                          uint32_t dst, uint32_t NA, uint32_t &u, uint32_t &rs, uint32_t &d,
-                                          int64_t &hu, uint32_t (&hist)[4], uint32_t &s, uint32_t &ncand,
-                                          uint64_t &cs, bool &ok, uint32_t *path)
+__device__ __forceinline__ bool glb_steps(const GlbWalkArgs &a, GlbWalk &w, uint32_t *bloom, uint64_t *gw,
+                                          uint32_t epoch, uint32_t j, uint64_t myr)
 {
-    if (s >= a.max_steps || !glb_step<L, CH, SL>(a, tau, bloom, gb, n_lo, dx, dy, j, myr, dst, u, rs, d, hu, hist, s,
-                                                 ncand, cs, ok, path + (size_t)s * NA))
-        return false;
-    if constexpr (SL + 1 < L)
-        return glb_steps<L, CH, SL + 1>(a, tau, bloom, gb, n_lo, dx, dy, j, myr, dst, NA, u, rs, d, hu, hist, s,
-                                        ncand, cs, ok, path);
+    if (w.s >= a.max_steps || !glb_step<L, CH, SL>(a, w, bloom, gw, epoch, j, myr)) return false;
+    if constexpr (SL + 1 < L) return glb_steps<L, CH, SL + 1>(a, w, bloom, gw, epoch, j, myr);
     return true;
 }
 
-// Walk for graphs too large for LDS.  L lanes per ant (as in k_walk_lds);
-// each candidate road is one 16-byte record gather (head, head's out-road
-// range, head coordinates) plus its cost and pheromone.  The visited test is
-// exact but rarely touches memory: the last four nodes are kept in
-// registers; then a per-ant Bloom filter in LDS (two hash bits); only when
-// it reports "maybe" is the per-ant bitset in global memory read.  Inserts
-// into both are fire-and-forget atomics; the bitset words are cleared from
-// the path when the walk ends.
+// Walk for graphs too large for LDS: a persistent kernel, one slot per group
+// of L lanes (lane j examines candidates j, j+L, ...).  The grid holds as
+// many groups as stay resident; a group walks one ant at a time and, when
+// its walk ends, takes the next ant from a ticket counter, so lanes do not
+// wait for the longest walk of their wave or block.  The groups of a wave
+// that need an ant take their tickets together, from a per-wave range that
+// is refilled one atomic at a time.  The last wave out resets the counters
+// for the next launch.
 template <int L, int CH>
 __global__ __launch_bounds__(256) void k_walk_glb(GlbWalkArgs a)
 {
+    constexpr uint32_t kGroups = kWave / L;   // groups per wave = tickets per refill
     extern __shared__ uint32_t s_bloom[];
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1);
     const uint32_t grp = tid / L, j = tid % L;
+    const uint32_t lead = lane - j;            // wave lane of the group's lane 0
+    const uint32_t slot = blockIdx.x * a.apb + grp;
     const uint32_t NA = a.nq * a.ants;
-    const uint32_t ant = blockIdx.x * a.apb + grp;
-    const bool in_range = grp < a.apb && ant < NA;
-    const uint32_t v = in_range ? ant / a.ants : 0, k = in_range ? ant % a.ants : 0;
-    gmacop_od q = {0, 0, 0};
-    if (in_range) q = a.od[v];
-    const bool active = in_range && a.vclass[v] == kWalkerGlobal;
+    const uint32_t total = *a.glb_n * a.ants;
     const uint32_t bws = (1u << (a.bloom_log2 - 5)) | 1u;   // odd stride spreads banks
     uint32_t *bloom = s_bloom + grp * bws;
-    if (grp < a.apb)
-        for (uint32_t i = j; i < bws; i += L) bloom[i] = 0;
-    uint32_t s = 0, ncand = 0, arrived = 0;
-    if (active) {
-        const PherRead tau = pher_at(a.pher, v, a.t_local);
-        const uint32_t n_lo = a.node_lo[q.src];
-        uint32_t *gb = a.gbits + (size_t)ant * a.nwords;
-        const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
-        uint32_t u = q.src;
-        uint32_t rs = a.row_ptr[u], d = a.row_ptr[u + 1] - rs;
-        int64_t hu = goal_ms(a.x[u], a.y[u], dx, dy, a.kgoal);
-        uint32_t hist[4] = {u, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-        if (j == 0) {
-            const uint32_t ul = u - n_lo;
-            atomicOr(&bloom[bloom_h1(ul, a.bloom_log2) >> 5], 1u << (bloom_h1(ul, a.bloom_log2) & 31));
-            atomicOr(&bloom[bloom_h2(ul, a.bloom_log2) >> 5], 1u << (bloom_h2(ul, a.bloom_log2) & 31));
-            atomicOr(&gb[ul >> 5], 1u << (ul & 31));
+    uint64_t *gw = a.gwords + (size_t)slot * a.nw2;
+    uint32_t epoch = a.slot_epoch[slot];
+    uint64_t c_steps = 0, c_cand = 0, c_arr = 0, c_dh = 0;   // group lane 0 counts
+    uint32_t c_max = 0;
+    uint32_t w_next = 0, w_end = 0;            // this wave's unused tickets (equal in every lane)
+    bool have = false, done = false;
+    GlbWalk w{};
+    for (;;) {
+        // groups without an ant take the next tickets
+        const bool need = !have && !done;
+        const uint64_t mask = __ballot(need && j == 0);
+        if (mask) {
+            const uint32_t n = (uint32_t)__popcll(mask);
+            const uint32_t avail = w_end - w_next;
+            uint32_t base2 = 0;
+            if (n > avail) {
+                const uint32_t first = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+                uint32_t got = 0;
+                if (lane == first) got = atomicAdd(a.tickets, kGroups);
+                base2 = __shfl(got, (int)first);
+            }
+            if (need) {
+                const uint32_t rk = (uint32_t)__popcll(mask & ((1ull << lead) - 1));
+                const uint32_t t = rk < avail ? w_next + rk : base2 + (rk - avail);
+                if (t >= total) {
+                    done = true;
+                } else {
+                    // start the walk of ticket t
+                    const uint32_t pos = t / a.ants;
+                    const uint4 *vr = (const uint4 *)(a.veh + pos);
+                    const uint4 r0 = vr[0], r1 = vr[1], r2 = vr[2];
+                    w.k = t - pos * a.ants;
+                    w.v = r0.x; w.qid = r0.y; w.u = r0.z; w.dst = r0.w;
+                    w.rs = r1.x; w.d = r1.y; w.n_lo = r1.z;
+                    w.dx = (int32_t)r2.x; w.dy = (int32_t)r2.y;
+                    w.hu = (int64_t)(((uint64_t)r2.w << 32) | r2.z);
+                    w.tau = pher_at(a.pher, w.v, a.t_local);
+                    w.it = a.iter + slot_iter(a.pher, w.v, 0);
+                    w.s = 0; w.ncand = 0; w.cs = 0; w.ok = false;
+                    w.hist[0] = w.u; w.hist[1] = w.hist[2] = w.hist[3] = 0xFFFFFFFFu;
+                    w.path = a.path + (size_t)w.v * a.ants + w.k;
+                    if (++epoch == 0) {   // epochs would repeat: clear the slot's words once
+                        for (uint32_t i = j; i < a.nw2; i += L) gw[i] = 0;
+                        epoch = 1;
+                    }
+                    for (uint32_t i = j; i < bws; i += L) bloom[i] = 0;
+                    w.pw = nullptr;
+                    if (j == 0) {
+                        const uint32_t ul = w.u - w.n_lo;
+                        atomicOr(&bloom[bloom_h1(ul, a.bloom_log2) >> 5], 1u << (bloom_h1(ul, a.bloom_log2) & 31));
+                        atomicOr(&bloom[bloom_h2(ul, a.bloom_log2) >> 5], 1u << (bloom_h2(ul, a.bloom_log2) & 31));
+                        w.pw = &gw[ul >> 5];
+                        w.pbit = 1u << (ul & 31);
+                        w.pval = __hip_atomic_load(w.pw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    have = true;
+                }
+            }
+            if (n > avail) {
+                w_next = base2 + (n - avail);
+                w_end = base2 + kGroups;
+            } else {
+                w_next += n;
+            }
         }
-        bool ok = false;
-        uint64_t cs64 = 0;
-        uint32_t *path = a.path + ant;
-        const uint32_t it = a.iter + slot_iter(a.pher, v, 0);
-        for (;;) {
-            const uint64_t myr = philox_u64(q.qid, k, it, s + j, a.seed_lo, a.seed_hi);
-            if (!glb_steps<L, CH, 0>(a, tau, bloom, gb, n_lo, dx, dy, j, myr, q.dst, NA, u, rs, d, hu, hist, s, ncand,
-                                     cs64, ok, path))
-                break;
-        }
-        const uint32_t cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
-        if (ok) {
-            arrived = 1;
+        if (__ballot(!done) == 0) break;   // no group of the wave has work left
+        if (!have) continue;
+        const uint64_t myr = philox_u64(w.qid, w.k, w.it, w.s + j, a.seed_lo, a.seed_hi);
+        if (glb_steps<L, CH, 0>(a, w, bloom, gw, epoch, j, myr)) continue;
+        // the walk is over
+        const uint32_t ant = w.v * a.ants + w.k;
+        const uint32_t cs = w.cs > kPathCostCap ? kPathCostCap : (uint32_t)w.cs;
+        if (w.ok) {
             const uint64_t dpos = a.q_deposit / cs;
             if (dpos) {
                 uint32_t i = j;
-                for (; i + 3 * L < s; i += 4 * L) {
-                    const uint32_t e0 = path[(size_t)i * NA], e1 = path[(size_t)(i + L) * NA];
-                    const uint32_t e2 = path[(size_t)(i + 2 * L) * NA], e3 = path[(size_t)(i + 3 * L) * NA];
-                    a.depv.add(v, e0, dpos);
-                    a.depv.add(v, e1, dpos);
-                    a.depv.add(v, e2, dpos);
-                    a.depv.add(v, e3, dpos);
+                for (; i + 3 * L < w.s; i += 4 * L) {
+                    const uint32_t e0 = a.path[(size_t)i * NA + ant], e1 = a.path[(size_t)(i + L) * NA + ant];
+                    const uint32_t e2 = a.path[(size_t)(i + 2 * L) * NA + ant];
+                    const uint32_t e3 = a.path[(size_t)(i + 3 * L) * NA + ant];
+                    a.depv.add(w.v, e0, dpos);
+                    a.depv.add(w.v, e1, dpos);
+                    a.depv.add(w.v, e2, dpos);
+                    a.depv.add(w.v, e3, dpos);
                 }
-                for (; i < s; i += L) a.depv.add(v, path[(size_t)i * NA], dpos);
+                for (; i < w.s; i += L) a.depv.add(w.v, a.path[(size_t)i * NA + ant], dpos);
             }
             if (j == 0)
-                atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)(((uint64_t)cs << 32) | k));
+                atomicMin((unsigned long long *)&a.iter_key[w.v], (unsigned long long)(((uint64_t)cs << 32) | w.k));
         }
         if (j == 0) {
-            a.ant_len[ant] = s;
-            a.ant_cost[ant] = ok ? cs : kNoCost;
+            a.ant_len[ant] = w.s;
+            a.ant_cost[ant] = w.ok ? cs : kNoCost;
+            atomicMax(&a.vlen[w.v], w.s);
+            c_steps += w.s;
+            c_cand += w.ncand;
+            c_arr += w.ok ? 1 : 0;
+            c_dh += w.ok ? w.s : 0;
+            c_max = max(c_max, w.s);
         }
-        // clear this ant's visited words for the next walk
-        if (j == 0) gb[(q.src - n_lo) >> 5] = 0;
-        for (uint32_t i = j; i < s; i += L) {
-            const uint32_t xl = (a.rec16[path[(size_t)i * NA]].x & 0xFFFFFFu) - n_lo;
-            gb[xl >> 5] = 0;
-        }
-    } else if (in_range && j == 0 && a.vclass[v] == kWalkerNone) {
-        a.ant_len[ant] = 0;
-        a.ant_cost[ant] = kNoCost;
+        w.pw = nullptr;
+        have = false;
     }
-    uint64_t cnt = j == 0 ? s : 0, cand = j == 0 ? ncand : 0, arr = j == 0 ? arrived : 0,
-             dh = (j == 0 && arrived) ? s : 0;
-    uint32_t smax = s;
+    if (j == 0) a.slot_epoch[slot] = epoch;
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
-        cnt += __shfl_xor(cnt, off);
-        cand += __shfl_xor(cand, off);
-        arr += __shfl_xor(arr, off);
-        dh += __shfl_xor(dh, off);
-        smax = max(smax, (uint32_t)__shfl_xor((int)smax, off));
+        c_steps += __shfl_xor(c_steps, off);
+        c_cand += __shfl_xor(c_cand, off);
+        c_arr += __shfl_xor(c_arr, off);
+        c_dh += __shfl_xor(c_dh, off);
+        c_max = max(c_max, (uint32_t)__shfl_xor((int)c_max, off));
     }
-    if ((threadIdx.x & (kWave - 1)) == 0 && cnt) {
-        atomicAdd((unsigned long long *)a.steps, (unsigned long long)cnt);
-        atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)cnt);
-        atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)cand);
-        atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)arr);
-        atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)dh);
-        atomicMax(a.iter_max, smax);
+    if (lane == 0) {
+        if (c_steps) {
+            atomicAdd((unsigned long long *)a.steps, (unsigned long long)c_steps);
+            atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)c_steps);
+            atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)c_cand);
+            atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)c_arr);
+            atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)c_dh);
+            atomicMax(a.iter_max, c_max);
+        }
+        // the last wave out resets the ticket counters for the next launch
+        const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+        if (atomicAdd(&a.tickets[1], 1u) == waves - 1) {
+            a.tickets[0] = 0;
+            a.tickets[1] = 0;
+        }
+    }
+}
+
+struct GlbListArgs {
+    const gmacop_od *od;
+    const uint8_t *vclass;
+    const uint32_t *row_ptr, *node_lo;
+    const int32_t *x, *y;
+    uint32_t nq, ants, kgoal;
+    GlbVeh *veh;
+    uint32_t *glb_n;
+    uint32_t *vlen;            // [nq] longest walk of each vehicle in the previous launch; reset here
+    uint32_t *ant_len, *ant_cost;
+};
+
+constexpr uint32_t kOrderBuckets = 256;   // longest-walk buckets of 4 steps (the last: 1020 and more)
+
+// One block, before every k_walk_glb launch: the vehicles that walker
+// serves, with the start data of their walks, ordered by the longest walk
+// each had in the previous launch, longest first.  Walk lengths persist from
+// one iteration to the next, so long walks start early instead of trailing
+// at the end of the launch; the order only schedules work (every ant's walk
+// is fixed by its own counters).  Ants of vehicles no walker serves get an
+// empty result.
+__global__ __launch_bounds__(1024) void k_glb_list(GlbListArgs a)
+{
+    __shared__ uint32_t s_hist[kOrderBuckets];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t b = tid; b < kOrderBuckets; b += blockDim.x) s_hist[b] = 0;
+    __syncthreads();
+    for (uint32_t v = tid; v < a.nq; v += blockDim.x)
+        if (a.vclass[v] == kWalkerGlobal) atomicAdd(&s_hist[min(a.vlen[v] >> 2, kOrderBuckets - 1)], 1u);
+    __syncthreads();
+    if (tid == 0) {   // bucket start positions, longest bucket first
+        uint32_t sum = 0;
+        for (uint32_t b = kOrderBuckets; b-- > 0;) {
+            const uint32_t c = s_hist[b];
+            s_hist[b] = sum;
+            sum += c;
+        }
+        *a.glb_n = sum;
+    }
+    __syncthreads();
+    for (uint32_t v = tid; v < a.nq; v += blockDim.x) {
+        const uint8_t cls = a.vclass[v];
+        if (cls == kWalkerGlobal) {
+            const uint32_t pos = atomicAdd(&s_hist[min(a.vlen[v] >> 2, kOrderBuckets - 1)], 1u);
+            a.vlen[v] = 0;
+            const gmacop_od q = a.od[v];
+            GlbVeh r;
+            r.v = v; r.qid = q.qid; r.src = q.src; r.dst = q.dst;
+            r.rs = a.row_ptr[q.src]; r.d = a.row_ptr[q.src + 1] - r.rs; r.n_lo = a.node_lo[q.src]; r.pad = 0;
+            r.dx = a.x[q.dst]; r.dy = a.y[q.dst];
+            const uint64_t hu = (uint64_t)goal_ms(a.x[q.src], a.y[q.src], r.dx, r.dy, a.kgoal);
+            r.hu_lo = (uint32_t)hu; r.hu_hi = (uint32_t)(hu >> 32);
+            a.veh[pos] = r;
+        } else if (cls == kWalkerNone) {
+            for (uint32_t k = 0; k < a.ants; ++k) {
+                a.ant_len[(size_t)v * a.ants + k] = 0;
+                a.ant_cost[(size_t)v * a.ants + k] = kNoCost;
+            }
+        }
     }
 }
 
@@ -1374,6 +1536,7 @@ struct EdgeArgs {
     uint32_t *tau, *load, *cnt;
     const uint32_t *base_load;
     uint64_t *dep;
+    uint32_t *mir;             // road records of the global walker (8 words per road) or NULL
 };
 
 // Per road: tau <- clamp(floor(tau * (65536 - rho) / 65536) + Dp), with the
@@ -1391,6 +1554,7 @@ __global__ void k_edge(EdgeArgs a)
     uint64_t t = (((uint64_t)a.tau[e] * (65536u - a.rho)) >> 16) + dp;
     t = t < a.tau_min ? a.tau_min : (t > a.tau_max ? a.tau_max : t);
     a.tau[e] = (uint32_t)t;
+    if (a.mir) a.mir[(size_t)e * 8 + 5] = (uint32_t)t;
     a.dep[e] = 0;
     if (a.load_update) {
         a.load[e] = a.base_load[e] + a.cnt[e];
@@ -1564,6 +1728,30 @@ unsigned blocks_for(uint64_t work, unsigned per_block)
 
 }  // namespace
 
+// Workspace of k_walk_glb: its vehicle list, counters, and per-slot visited
+// words and epochs.  The words keep their meaning across calls as long as
+// the slot layout stays the same; a new layout clears them.
+struct GlbWork {
+    GlbVeh *veh = nullptr;
+    size_t cap_veh = 0;
+    uint32_t *vlen = nullptr;          // [vehicles] longest walk in the last launch
+    size_t cap_vlen = 0;
+    uint32_t *ctl = nullptr;           // [0]: vehicles listed, [1]: next ticket, [2]: waves done
+    uint64_t *words = nullptr;
+    size_t cap_words = 0;
+    uint32_t *epoch = nullptr;
+    size_t cap_epoch = 0;
+    uint64_t slots = 0, nw2 = 0;       // layout of `words`
+
+    void release()
+    {
+        dfree(veh); dfree(vlen); dfree(ctl); dfree(words); dfree(epoch);
+        veh = nullptr; vlen = nullptr; ctl = nullptr; words = nullptr; epoch = nullptr;
+        cap_veh = cap_vlen = cap_words = cap_epoch = 0;
+        slots = nw2 = 0;
+    }
+};
+
 struct gmacop_graph {
     int device = 0;
     uint32_t n = 0, m = 0, n_inst = 1, max_deg = 0, max_indeg = 0;
@@ -1573,7 +1761,7 @@ struct gmacop_graph {
     uint32_t *row_ptr = nullptr, *col = nullptr, *len_dm = nullptr, *cycle = nullptr, *base_load = nullptr;
     uint32_t *rev_ptr = nullptr, *rev_edge = nullptr, *tail = nullptr;
     uint2 *rec = nullptr;              // head | head_out_degree << 24, head's first out-road (n < 2^24)
-    uint4 *rec16 = nullptr;            // rec plus head coordinates
+    uint4 *rec32 = nullptr;            // [m][2] global-walker road records: rec, head coordinates; cost, pheromone
     uint32_t *node_lo = nullptr, *node_inst = nullptr;   // first node / index of each node's city
     uint32_t *inst_off_dev = nullptr, *inst_eoff_dev = nullptr;   // node / road range of each city
     uint8_t *inst_fits = nullptr;      // per city: served by the LDS walker in the current plan
@@ -1593,6 +1781,7 @@ struct gmacop_graph {
     uint64_t *iter_key = nullptr, *steps = nullptr;
     uint32_t *best_path = nullptr, *best_len = nullptr, *best_cost = nullptr;
     gmacop_od *od = nullptr;
+    GlbWork glb;
     // statistics
     uint64_t *counters = nullptr;         // device [5]
     uint32_t *iter_max = nullptr;         // device [1]
@@ -1616,12 +1805,13 @@ struct gmacop_graph {
     {
         (void)hipSetDevice(device);
         dfree(row_ptr); dfree(col); dfree(len_dm); dfree(cycle); dfree(base_load);
-        dfree(rev_ptr); dfree(rev_edge); dfree(tail); dfree(rec); dfree(rec16); dfree(node_lo); dfree(node_inst);
+        dfree(rev_ptr); dfree(rev_edge); dfree(tail); dfree(rec); dfree(rec32); dfree(node_lo); dfree(node_inst);
         dfree(inst_fits); dfree(vclass); dfree(inst_off_dev); dfree(inst_eoff_dev); dfree(speed); dfree(green); dfree(x); dfree(y);
         dfree(t0); dfree(wf); dfree(tau); dfree(load); dfree(cost); dfree(cnt); dfree(dep);
         dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_key); dfree(steps);
         dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters); dfree(iter_max);
         dfree(lazy); dfree(dep_ind); dfree(touched); dfree(touched_n); dfree(dev_gen);
+        glb.release();
         for (auto &t : pending) {
             (void)hipEventDestroy(t.a);
             (void)hipEventDestroy(t.b);
@@ -1656,6 +1846,32 @@ int grow(T **p, size_t *cap, size_t need, bool zero)
         HIP_TRY(hipDeviceSynchronize());   // ordered before work on any stream
     }
     *cap = need;
+    return GMACOP_OK;
+}
+
+// Size the k_walk_glb workspace for nq vehicles and `slots` slots of nw2 words.
+int glb_prepare(GlbWork &w, uint32_t nq, uint64_t slots, uint32_t nw2)
+{
+    int rc;
+    if ((rc = grow(&w.veh, &w.cap_veh, std::max<size_t>(nq, 1), false)) ||
+        (rc = grow(&w.vlen, &w.cap_vlen, std::max<size_t>(nq, 1), true)))
+        return rc;
+    if (!w.ctl) {
+        if ((rc = dalloc(&w.ctl, 3))) return rc;
+        HIP_TRY(hipMemset(w.ctl, 0, 3 * sizeof(uint32_t)));
+        HIP_TRY(hipDeviceSynchronize());
+    }
+    if (slots != w.slots || nw2 != w.nw2) {
+        const size_t need = (size_t)slots * nw2;
+        if ((rc = grow(&w.words, &w.cap_words, std::max<size_t>(need, 1), false)) ||
+            (rc = grow(&w.epoch, &w.cap_epoch, std::max<size_t>(slots, 1), false)))
+            return rc;
+        HIP_TRY(hipMemset(w.words, 0, std::max<size_t>(need, 1) * sizeof(uint64_t)));
+        HIP_TRY(hipMemset(w.epoch, 0, std::max<size_t>(slots, 1) * sizeof(uint32_t)));
+        HIP_TRY(hipDeviceSynchronize());
+        w.slots = slots;
+        w.nw2 = nw2;
+    }
     return GMACOP_OK;
 }
 
@@ -1788,6 +2004,7 @@ struct WalkPlan {
     size_t lds_bytes[kLdsClasses + 1] = {};   // [c]: dynamic LDS of LDS class c's launch, 0 = none
     bool glb = false;              // some city is served by k_walk_glb
     uint32_t glb_lanes = 4, glb_apb = 0, bloom_log2 = 11, glb_nwords = 0;
+    uint32_t glb_blocks = 0;       // resident grid of k_walk_glb (glb_grid)
     size_t glb_lds_bytes = 0;
     std::vector<uint8_t> city_class;      // per city: LDS class 1..kLdsClasses, or 0 = global walker
     bool any_lds() const
@@ -1868,9 +2085,7 @@ template <int L, int MAXD>
 int launch_walk_glb(const GlbWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
 {
     constexpr int CH = (MAXD + L - 1) / L;
-    const uint64_t NA = (uint64_t)wa.nq * wa.ants;
-    hipLaunchKernelGGL((k_walk_glb<L, CH>), dim3(blocks_for(NA, pl.glb_apb)), dim3(pl.glb_apb * L), pl.glb_lds_bytes,
-                       st, wa);
+    hipLaunchKernelGGL((k_walk_glb<L, CH>), dim3(pl.glb_blocks), dim3(pl.glb_apb * L), pl.glb_lds_bytes, st, wa);
     HIP_TRY(hipGetLastError());
     return GMACOP_OK;
 }
@@ -1894,6 +2109,39 @@ int launch_walk_glb_any(const GlbWalkArgs &wa, const WalkPlan &pl, hipStream_t s
     case 4: return launch_walk_glb_d<4>(wa, pl, st);
     default: return launch_walk_glb_d<8>(wa, pl, st);
     }
+}
+
+template <int L, int MAXD>
+const void *glb_kernel()
+{
+    constexpr int CH = (MAXD + L - 1) / L;
+    return (const void *)k_walk_glb<L, CH>;
+}
+
+template <int L>
+const void *glb_kernel_d(uint32_t maxd)
+{
+    return maxd <= 4 ? glb_kernel<L, 4>() : maxd <= 8 ? glb_kernel<L, 8>() : maxd <= 16 ? glb_kernel<L, 16>()
+                                                                                       : glb_kernel<L, 32>();
+}
+
+// The persistent grid of k_walk_glb: as many blocks as stay resident on the
+// device (fewer when there are fewer ants), and no more than keep the
+// per-slot visited words within kGlbWordsBudget.
+int glb_grid(int device, WalkPlan &pl, uint64_t NA)
+{
+    const uint32_t L = pl.glb_lanes;
+    const void *kern = L == 1 ? glb_kernel_d<1>(pl.maxd) : L == 2 ? glb_kernel_d<2>(pl.maxd)
+                       : L == 4 ? glb_kernel_d<4>(pl.maxd) : glb_kernel_d<8>(pl.maxd);
+    int nb = 0, cus = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, (int)(pl.glb_apb * L), pl.glb_lds_bytes));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    uint64_t blocks = (uint64_t)std::max(nb, 1) * (uint64_t)std::max(cus, 1);
+    blocks = std::min<uint64_t>(blocks, (NA + pl.glb_apb - 1) / pl.glb_apb);
+    const uint64_t per_block = (uint64_t)pl.glb_apb * std::max<uint32_t>(pl.glb_nwords, 1) * sizeof(uint64_t);
+    blocks = std::min<uint64_t>(blocks, std::max<uint64_t>((uint64_t)std::max(cus, 1), kGlbWordsBudget / per_block));
+    pl.glb_blocks = (uint32_t)std::max<uint64_t>(blocks, 1);
+    return GMACOP_OK;
 }
 
 uint32_t env_u32(const char *name, uint32_t dflt)
@@ -2020,10 +2268,11 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
             const uint32_t deg = d->row_ptr[x + 1] - d->row_ptr[x];
             rec[e] = make_uint2((x & 0xFFFFFFu) | (std::min(deg, 255u) << 24), d->row_ptr[x]);
         }
-    std::vector<uint4> rec16(m);
+    std::vector<uint4> rec32(2 * (size_t)m);   // the cost and pheromone words are written per call
     for (uint32_t e = 0; e < m; ++e) {
         const uint32_t x = d->col[e];
-        rec16[e] = make_uint4(rec[e].x, rec[e].y, (uint32_t)d->x_dm[x], (uint32_t)d->y_dm[x]);
+        rec32[2 * (size_t)e] = make_uint4(rec[e].x, rec[e].y, (uint32_t)d->x_dm[x], (uint32_t)d->y_dm[x]);
+        rec32[2 * (size_t)e + 1] = make_uint4(0, 0, 0, 0);
     }
     std::vector<uint32_t> node_lo(n), node_inst(n);
     g->inst_eoff.resize(g->n_inst + 1);
@@ -2037,7 +2286,7 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
     }
     g->inst_eoff[g->n_inst] = m;
     if ((rc = upload(&g->tail, tail.data(), m)) || (rc = upload(&g->rec, rec.data(), m)) ||
-        (rc = upload(&g->rec16, rec16.data(), m)) || (rc = upload(&g->node_lo, node_lo.data(), n)) ||
+        (rc = upload(&g->rec32, rec32.data(), 2 * (size_t)m)) || (rc = upload(&g->node_lo, node_lo.data(), n)) ||
         (rc = upload(&g->node_inst, node_inst.data(), n)) || (rc = dalloc(&g->inst_fits, g->n_inst)) ||
         (rc = upload(&g->inst_off_dev, g->inst_off.data(), g->n_inst + 1)) ||
         (rc = upload(&g->inst_eoff_dev, g->inst_eoff.data(), g->n_inst + 1))) {
@@ -2094,7 +2343,8 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     const uint32_t S = p->max_steps;
     const uint64_t NA = (uint64_t)nq * p->ants;
     const bool lds = g->n <= kLdsBitsetMaxNodes;
-    const WalkPlan plan = plan_walk(g, p, g->max_lds);
+    WalkPlan plan = plan_walk(g, p, g->max_lds);
+    if (!plan.legacy && plan.glb && (rc = glb_grid(g->device, plan, NA))) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     const uint32_t nwords = (g->n + 31) / 32;
 
@@ -2108,7 +2358,8 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         g->cap_ants = std::min(c1, c2);
     }
     if (plan.legacy && !lds && (rc = grow(&g->gbits, &g->cap_bits, (size_t)NA * nwords, true))) return rc;
-    if (!plan.legacy && plan.glb && (rc = grow(&g->gbits, &g->cap_bits, (size_t)NA * plan.glb_nwords, true)))
+    if (!plan.legacy && plan.glb &&
+        (rc = glb_prepare(g->glb, nq, (uint64_t)plan.glb_blocks * plan.glb_apb, plan.glb_nwords)))
         return rc;
     if ((rc = grow(&g->vclass, &g->cap_vclass, std::max<size_t>(nq, 1), false))) return rc;
     if (plan.city_class != g->city_class_dev) {   // per-city walker choice, uploaded when it changes
@@ -2162,9 +2413,10 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     }
 
     const bool load_update = !(p->flags & GMACOP_NO_LOAD_UPDATE);
+    uint32_t *mir = (!plan.legacy && plan.glb) ? (uint32_t *)g->rec32 : nullptr;   // the global walker's records
     EdgeInitArgs ia{g->m, p->tau0_q16, p->t_max_ms, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
-                    g->t0, g->wf, g->tau, g->load, g->cnt, g->dep};
-    CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost};
+                    g->t0, g->wf, g->tau, g->load, g->cnt, g->dep, mir};
+    CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost, mir};
     PherView pv{};
     pv.dense = indep ? nullptr : g->tau;
     pv.lazy = g->lazy;
@@ -2194,17 +2446,21 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     BestArgs ba{nq, p->ants, S, update_loads ? 1u : 0u, g->iter_max, g->counters, g->path, g->ant_len, g->iter_key,
                 best_path, best_len, best_cost, g->cnt};
     EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, update_loads ? 1u : 0u,
-                g->tau, g->load, g->cnt, g->base_load, g->dep};
+                g->tau, g->load, g->cnt, g->base_load, g->dep, mir};
     ApplyArgs aa{g->m, tcap, 0, p->tau0_q16, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, g->load, g->dev_gen,
                  nullptr, nullptr, g->lazy, g->dep_ind, g->touched, g->touched_n};
     GlbWalkArgs ga{};
-    ga.rec16 = g->rec16; ga.row_ptr = g->row_ptr; ga.cost = g->cost; ga.x = g->x; ga.y = g->y; ga.node_lo = g->node_lo;
-    ga.vclass = g->vclass; ga.pher = pv; ga.depv = dv; ga.od = od; ga.n = g->n; ga.m = g->m; ga.nq = nq;
+    ga.rec32 = g->rec32; ga.pher = pv; ga.depv = dv;
+    ga.veh = g->glb.veh; ga.glb_n = g->glb.ctl; ga.tickets = g->glb.ctl + 1; ga.gwords = g->glb.words;
+    ga.vlen = g->glb.vlen;
+    ga.slot_epoch = g->glb.epoch; ga.m = g->m; ga.nq = nq;
     ga.ants = p->ants; ga.apb = plan.glb_apb; ga.max_steps = S; ga.alpha = p->alpha; ga.beta = p->beta;
-    ga.kgoal = wa.kgoal; ga.nwords = plan.glb_nwords; ga.bloom_log2 = plan.bloom_log2; ga.seed_lo = wa.seed_lo;
+    ga.kgoal = wa.kgoal; ga.nw2 = plan.glb_nwords; ga.bloom_log2 = plan.bloom_log2; ga.seed_lo = wa.seed_lo;
     ga.seed_hi = wa.seed_hi; ga.q_deposit = p->q_deposit; ga.path = g->path; ga.ant_len = g->ant_len;
-    ga.ant_cost = g->ant_cost; ga.gbits = g->gbits; ga.iter_key = g->iter_key; ga.steps = steps;
+    ga.ant_cost = g->ant_cost; ga.iter_key = g->iter_key; ga.steps = steps;
     ga.counters = g->counters; ga.iter_max = g->iter_max;
+    const GlbListArgs gla{od, g->vclass, g->row_ptr, g->node_lo, g->x, g->y, nq, p->ants, wa.kgoal,
+                          g->glb.veh, g->glb.ctl, g->glb.vlen, g->ant_len, g->ant_cost};
     const bool any_lds = !plan.legacy && plan.any_lds();
     if (any_lds && (rc = setup_walk_lds(la, plan, st))) return rc;
 
@@ -2221,9 +2477,10 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
                            best_len, best_cost, g->iter_key, steps);
         hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
-        if (nq && !plan.legacy)
+        if (nq && !plan.legacy) {
             hipLaunchKernelGGL(k_classify, dim3(blocks_for(nq, 256)), dim3(256), 0, st, od, nq, g->n,
                                (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, g->vclass);
+        }
         HIP_TRY(hipGetLastError());
         WalkArgs wt = wa;
         LdsWalkArgs lt = la;
@@ -2242,7 +2499,10 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
                                      : launch_walk<32>(wt, lds, st);
                 } else {
                     erc = launch_walk_lds_classes(lt, plan, st);
-                    if (!erc && plan.glb) erc = launch_walk_glb_any(gt, plan, st);
+                    if (!erc && plan.glb) {
+                        hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, st, gla);
+                        erc = launch_walk_glb_any(gt, plan, st);
+                    }
                 }
                 if (erc || (erc = kt.stop(&tm))) return erc;
                 if ((erc = kt.start(1, &tm))) return erc;
@@ -2278,7 +2538,9 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
             plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.lds_repl, plan.road_maxd,
             (uint64_t)plan.lds_bytes[1], (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3],
             (uint64_t)plan.lds_bytes[4], (uint64_t)plan.lds_bytes[5], (uint64_t)plan.lds_bytes[6], plan.glb, plan.glb_lanes, plan.glb_apb,
-            plan.bloom_log2, plan.glb_nwords, (uint64_t)lds, (uint64_t)(uintptr_t)g->vclass,
+            plan.bloom_log2, plan.glb_nwords, plan.glb_blocks, (uint64_t)(uintptr_t)g->glb.veh, (uint64_t)(uintptr_t)g->glb.vlen,
+            (uint64_t)(uintptr_t)g->glb.ctl, (uint64_t)(uintptr_t)g->glb.words, (uint64_t)(uintptr_t)g->glb.epoch,
+            (uint64_t)lds, (uint64_t)(uintptr_t)g->vclass,
             (uint64_t)(uintptr_t)g->lazy, (uint64_t)(uintptr_t)g->dep_ind, (uint64_t)(uintptr_t)g->touched,
             (uint64_t)(uintptr_t)g->touched_n, (uint64_t)(uintptr_t)g->dev_gen, tcap};
         if (!g->gexec || key != g->gkey) {
@@ -2421,7 +2683,7 @@ extern "C" const char *gmacop_last_error(void)
 struct gmacop_server {
     gmacop_graph *g = nullptr;
     gmacop_params p{};
-    uint32_t slots = 0, tcap = 0, nwords_legacy = 0;
+    uint32_t slots = 0, tcap = 0;
     size_t per_slot = 0;
     WalkPlan plan;
     // device, per slot
@@ -2429,7 +2691,9 @@ struct gmacop_server {
     uint32_t *slot_t = nullptr, *slot_gen = nullptr, *best_path = nullptr, *best_len = nullptr, *best_cost = nullptr;
     uint64_t *iter_key = nullptr, *lazy = nullptr, *dep = nullptr, *steps = nullptr, *counters = nullptr;
     uint32_t *touched = nullptr, *touched_n = nullptr, *path = nullptr, *ant_len = nullptr, *ant_cost = nullptr;
-    uint32_t *gbits = nullptr, *iter_max = nullptr;
+    uint32_t *iter_max = nullptr;
+    uint4 *rec32 = nullptr;   // global-walker road records with this router's costs
+    GlbWork glb;
     uint8_t *vclass = nullptr;
     // device, per road: this router's frozen-load cost table
     uint32_t *t0 = nullptr, *wf = nullptr, *load = nullptr, *cost = nullptr, *cnt = nullptr, *tau = nullptr;
@@ -2448,7 +2712,8 @@ struct gmacop_server {
         (void)hipSetDevice(g ? g->device : 0);
         dfree(slot_od); dfree(slot_t); dfree(slot_gen); dfree(best_path); dfree(best_len); dfree(best_cost);
         dfree(iter_key); dfree(lazy); dfree(dep); dfree(steps); dfree(counters); dfree(touched); dfree(touched_n);
-        dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_max); dfree(vclass);
+        dfree(path); dfree(ant_len); dfree(ant_cost); dfree(iter_max); dfree(vclass); dfree(rec32);
+        glb.release();
         dfree(t0); dfree(wf); dfree(load); dfree(cost); dfree(cnt); dfree(tau); dfree(dep_shared);
         dfree(adm_slots); dfree(adm_gen); dfree(done_slots); dfree(done_path); dfree(done_len); dfree(done_cost);
         dfree(adm_od);
@@ -2492,16 +2757,25 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
     }
     const uint32_t A = pp.ants, S = pp.max_steps, m = g->m;
     s->tcap = (uint32_t)std::min<uint64_t>(m, (uint64_t)A * S);
-    s->nwords_legacy = (g->n + 31) / 32;
-    const uint64_t words = s->plan.legacy ? (g->n <= kLdsBitsetMaxNodes ? 0 : s->nwords_legacy) : s->plan.glb_nwords;
-    s->per_slot = (size_t)m * 16 + (size_t)s->tcap * 4 + (size_t)A * S * 4 + (size_t)A * 8 + (size_t)A * words * 4 +
-                  (size_t)S * 8 + 64;
+    s->per_slot = (size_t)m * 16 + (size_t)s->tcap * 4 + (size_t)A * S * 4 + (size_t)A * 8 +
+                  (size_t)S * 8 + sizeof(GlbVeh) + 64;
     size_t budget = mem_budget_bytes;
     if (!budget) {
         size_t fr = 0, tot = 0;
         HIP_TRY(hipMemGetInfo(&fr, &tot));
         budget = fr / 2;
     }
+    // the global walker's visited words: a fixed amount, at most that of its full resident grid
+    size_t fixed = 0;
+    if (s->plan.glb) {
+        WalkPlan full = s->plan;
+        if ((rc = glb_grid(g->device, full, 0xFFFFFFFFull))) {
+            delete s;
+            return rc;
+        }
+        fixed = (size_t)full.glb_blocks * full.glb_apb * ((size_t)full.glb_nwords * sizeof(uint64_t) + 4);
+    }
+    budget = budget > fixed ? budget - fixed : 0;
     uint64_t cap_slots = budget / std::max<size_t>(s->per_slot, 1);
     if (max_slots) cap_slots = std::min<uint64_t>(cap_slots, max_slots);
     cap_slots = std::min<uint64_t>(cap_slots, 0xFFFFFFFFull / std::max<uint32_t>(A, 1));
@@ -2519,24 +2793,36 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
         (rc = dalloc_zero(&s->lazy, (size_t)NS * m)) || (rc = dalloc_zero(&s->dep, (size_t)NS * m)) ||
         (rc = dalloc_zero(&s->touched_n, NS)) || (rc = dalloc(&s->touched, (size_t)NS * s->tcap)) ||
         (rc = dalloc(&s->path, (size_t)S * NA)) || (rc = dalloc(&s->ant_len, NA)) || (rc = dalloc(&s->ant_cost, NA)) ||
-        (rc = dalloc_zero(&s->gbits, (size_t)NA * words)) || (rc = dalloc_zero(&s->steps, 1)) ||
+        (rc = dalloc_zero(&s->steps, 1)) ||
         (rc = dalloc_zero(&s->counters, 5)) || (rc = dalloc_zero(&s->iter_max, 1)) || (rc = dalloc(&s->vclass, NS)) ||
         (rc = dalloc(&s->t0, m)) || (rc = dalloc(&s->wf, m)) || (rc = dalloc(&s->load, m)) ||
         (rc = dalloc(&s->cost, m)) || (rc = dalloc(&s->cnt, m)) || (rc = dalloc(&s->tau, m)) ||
         (rc = dalloc(&s->dep_shared, m)) || (rc = dalloc(&s->adm_slots, NS)) || (rc = dalloc(&s->adm_gen, NS)) ||
         (rc = dalloc(&s->adm_od, NS)) || (rc = dalloc(&s->done_slots, NS)) ||
         (rc = dalloc(&s->done_path, (size_t)NS * S)) || (rc = dalloc(&s->done_len, NS)) ||
-        (rc = dalloc(&s->done_cost, NS))) {
+        (rc = dalloc(&s->done_cost, NS)) || (s->plan.glb && (rc = glb_grid(g->device, s->plan, NA))) ||
+        (s->plan.glb &&
+         (rc = glb_prepare(s->glb, NS, (uint64_t)s->plan.glb_blocks * s->plan.glb_apb, s->plan.glb_nwords)))) {
         std::string keep = t_err;
         delete s;
         t_err = keep;
         return rc;
     }
     // this router's cost table: loads frozen at the sensed loads
+    if (s->plan.glb) {   // the global walker's road records, with this router's cost table
+        if ((rc = dalloc(&s->rec32, 2 * (size_t)m))) {
+            std::string keep = t_err;
+            delete s;
+            t_err = keep;
+            return rc;
+        }
+        HIP_TRY(hipMemcpy(s->rec32, g->rec32, 2 * (size_t)m * sizeof(uint4), hipMemcpyDeviceToDevice));
+    }
     EdgeInitArgs ia{m, pp.tau0_q16, pp.t_max_ms, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
-                    s->t0, s->wf, s->tau, s->load, s->cnt, s->dep_shared};
+                    s->t0, s->wf, s->tau, s->load, s->cnt, s->dep_shared, (uint32_t *)s->rec32};
     hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(m, 256)), dim3(256), 0, 0, ia);
-    CostArgs ca{g->n, pp.theta, pp.th_max, g->rev_ptr, g->rev_edge, g->cycle, s->load, s->t0, s->wf, s->cost};
+    CostArgs ca{g->n, pp.theta, pp.th_max, g->rev_ptr, g->rev_edge, g->cycle, s->load, s->t0, s->wf, s->cost,
+                (uint32_t *)s->rec32};
     hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, 0, ca);
     const hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -2636,6 +2922,11 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
     const uint32_t NAll = NS * A;
     hipLaunchKernelGGL(k_classify, dim3(blocks_for(NS, 256)), dim3(256), 0, st, (const gmacop_od *)s->slot_od, NS,
                        g->n, (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, s->vclass);
+    if (plan.glb) {
+        const GlbListArgs gla{s->slot_od, s->vclass, g->row_ptr, g->node_lo, g->x, g->y, NS, A, kgoal,
+                              s->glb.veh, s->glb.ctl, s->glb.vlen, s->ant_len, s->ant_cost};
+        hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, st, gla);
+    }
     if ((rc = kt.start(0, &tm))) return rc;
     {
         LdsWalkArgs la{};
@@ -2652,13 +2943,14 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
             return rc;
         if (plan.glb) {
             GlbWalkArgs ga{};
-            ga.rec16 = g->rec16; ga.row_ptr = g->row_ptr; ga.cost = s->cost; ga.x = g->x; ga.y = g->y;
-            ga.node_lo = g->node_lo; ga.vclass = s->vclass; ga.pher = pv; ga.depv = dv; ga.od = s->slot_od;
-            ga.n = g->n; ga.m = g->m; ga.nq = NS; ga.ants = A; ga.apb = plan.glb_apb; ga.max_steps = S;
-            ga.alpha = p.alpha; ga.beta = p.beta; ga.kgoal = kgoal; ga.nwords = plan.glb_nwords;
+            ga.rec32 = s->rec32; ga.pher = pv; ga.depv = dv;
+            ga.veh = s->glb.veh; ga.glb_n = s->glb.ctl; ga.tickets = s->glb.ctl + 1; ga.gwords = s->glb.words;
+            ga.vlen = s->glb.vlen;
+            ga.slot_epoch = s->glb.epoch; ga.m = g->m; ga.nq = NS; ga.ants = A; ga.apb = plan.glb_apb;
+            ga.max_steps = S; ga.alpha = p.alpha; ga.beta = p.beta; ga.kgoal = kgoal; ga.nw2 = plan.glb_nwords;
             ga.bloom_log2 = plan.bloom_log2; ga.seed_lo = la.seed_lo; ga.seed_hi = la.seed_hi; ga.iter = p.iter_offset;
             ga.t_local = 0; ga.q_deposit = p.q_deposit; ga.path = s->path; ga.ant_len = s->ant_len;
-            ga.ant_cost = s->ant_cost; ga.gbits = s->gbits; ga.iter_key = s->iter_key; ga.steps = s->steps;
+            ga.ant_cost = s->ant_cost; ga.iter_key = s->iter_key; ga.steps = s->steps;
             ga.counters = g->counters; ga.iter_max = g->iter_max;
             if ((rc = launch_walk_glb_any(ga, plan, st))) return rc;
         }
