@@ -561,7 +561,10 @@ struct LdsWalkArgs {
     uint32_t t_local;
     const uint2 *rec;          // [m] static: head | head_out_degree << 24, head's first out-road
     const uint32_t *tail;      // [m] static: tail node of each road
-    const uint32_t *rev_ptr, *rev_edge;   // roads into each node (k_walk_ldsr)
+    const uint32_t *rev_ptr;   // roads into each node, by node
+    // [m] static per road, city-local (cities under 2^16 roads): head's first out-road | out-degree << 16,
+    // head's first in-road | in-degree << 16, head | tail << 16, the road's entry of the in-road list
+    const uint4 *rvs;
     const int32_t *x, *y;
     const gmacop_od *od;
     uint32_t n, m, nq, ants, apb, bpv, max_steps, alpha, beta, kgoal, nwords;
@@ -572,65 +575,107 @@ struct LdsWalkArgs {
     uint32_t *iter_max;    // longest walk of this iteration
 };
 
+// Per-group scratch at the end of an LDS walker's dynamic LDS: the deposit
+// of each group's ant (u64), then the exclusive prefix of the deposited path
+// lengths (apb + 1 words).
+constexpr size_t lds_group_bytes(uint32_t apb) { return (size_t)apb * 12 + 4; }
+
 // End of an LDS walker block: every ant of the block has walked, so the
 // staged road records are no longer read and their space becomes one u64
-// deposit accumulator per city road.  Arriving ants add floor(q / cost) to
-// the roads of their path with LDS atomics (exact integer sums, so the order
-// does not matter); then the block adds each non-zero sum to the global
-// deposit once, and its best (cost, ant) key and step counters once, instead
-// of one global atomic per road of every path -- those contend on the roads
-// that many ants share.
+// deposit accumulator per city road.  The paths of the arriving ants are laid
+// end to end and every thread of the block takes an equal slice of their
+// entries (its group found in the prefix of path lengths), adding
+// floor(q / cost) of the entry's ant to the road with an LDS atomic -- exact
+// integer sums, so the order does not matter; all path reads of the block
+// are in flight together instead of a long path's lanes reading it a few
+// entries at a time.  Then the block adds each non-zero sum to the global
+// deposit once, and its best (cost, ant) key and step counters once.
 template <int L>
-__device__ __forceinline__ void lds_block_finish(const LdsWalkArgs &a, uint64_t *s_mem, uint32_t e_lo,
-                                                 uint32_t e_cnt, uint32_t v, uint32_t k, bool active, bool ok,
-                                                 uint32_t s, uint32_t cs, uint32_t ncand, uint32_t j,
-                                                 const uint32_t *path, uint32_t NA)
+__device__ __forceinline__ void lds_block_finish(const LdsWalkArgs &a, uint64_t *s_mem, uint32_t *s_grp,
+                                                 uint32_t e_lo, uint32_t e_cnt, uint32_t v, uint32_t k0, bool active,
+                                                 bool ok, uint32_t s, uint32_t cs, uint32_t ncand, uint32_t grp,
+                                                 uint32_t j, uint32_t NA)
 {
     __shared__ uint64_t s_blk[6];   // best key, steps, candidates, arrivals, deposited roads, longest walk
-    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
-    uint64_t *acc = s_mem;          // [e_cnt]
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x, apb = a.apb;
+    uint64_t *acc = s_mem;                      // [e_cnt]
+    uint64_t *s_dp = (uint64_t *)s_grp;         // [apb]
+    uint32_t *s_off = s_grp + 2 * apb;          // [apb + 1]
     const bool arrived = active && ok;
     const uint64_t dpos = arrived ? a.q_deposit / cs : 0;
     __syncthreads();
     for (uint32_t i = tid; i < e_cnt; i += nthr) acc[i] = 0;
     if (tid < 6) s_blk[tid] = tid == 0 ? ~0ull : 0;
+    if (j == 0 && grp < apb) {
+        s_dp[grp] = dpos;
+        s_off[grp] = dpos ? s : 0;
+    }
     __syncthreads();
-    if (dpos) {
-        // lane j takes path entries j, j+L, ...; eight loads in flight before the LDS adds
-        uint32_t i = j;
-        for (; i + 7 * L < s; i += 8 * L) {
-            uint32_t e[8];
+    if (tid < kWave) {   // exclusive prefix of the lengths, groups [tid * per, tid * per + per) per lane
+        // (a block of fewer than 64 threads has fewer lanes here: the total comes from its last lane)
+        const uint32_t nl = min(nthr, (uint32_t)kWave);
+        const uint32_t per = (apb + kWave - 1) / kWave;
+        uint32_t sum = 0;
+        for (uint32_t g = tid * per; g < min(apb, tid * per + per); ++g) sum += s_off[g];
+        uint32_t incl = sum;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) e[u] = path[(size_t)(i + u * L) * NA];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) atomicAdd((unsigned long long *)&acc[e[u] - e_lo], (unsigned long long)dpos);
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_up((int)incl, off);
+            incl += (int)tid >= off ? o : 0u;
         }
-        for (; i < s; i += L) atomicAdd((unsigned long long *)&acc[path[(size_t)i * NA] - e_lo], (unsigned long long)dpos);
-    }
-    if (arrived && j == 0) atomicMin((unsigned long long *)&s_blk[0], (unsigned long long)(((uint64_t)cs << 32) | k));
-    // counters: one contribution per ant (its first lane), summed over the wave, then over the block
-    uint64_t cnt = (active && j == 0) ? s : 0, cand = (active && j == 0) ? ncand : 0;
-    uint64_t arr = (arrived && j == 0) ? 1 : 0, dh = (arrived && j == 0) ? s : 0;
-    uint32_t smax = active ? s : 0;
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        cnt += __shfl_xor(cnt, off);
-        cand += __shfl_xor(cand, off);
-        arr += __shfl_xor(arr, off);
-        dh += __shfl_xor(dh, off);
-        smax = max(smax, (uint32_t)__shfl_xor((int)smax, off));
-    }
-    if ((tid & (kWave - 1)) == 0 && cnt) {
-        atomicAdd((unsigned long long *)&s_blk[1], (unsigned long long)cnt);
-        atomicAdd((unsigned long long *)&s_blk[2], (unsigned long long)cand);
-        atomicAdd((unsigned long long *)&s_blk[3], (unsigned long long)arr);
-        atomicAdd((unsigned long long *)&s_blk[4], (unsigned long long)dh);
-        atomicMax((unsigned long long *)&s_blk[5], (unsigned long long)smax);
+        uint32_t run = incl - sum;
+        for (uint32_t g = tid * per; g < min(apb, tid * per + per); ++g) {
+            const uint32_t len = s_off[g];
+            s_off[g] = run;
+            run += len;
+        }
+        if (tid == nl - 1) s_off[apb] = incl;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < e_cnt; i += nthr) {
-        const uint64_t x = acc[i];
-        if (x) a.depv.add(v, e_lo + i, x);
+    const uint32_t total = s_off[apb];
+    const uint32_t per_t = (total + nthr - 1) / nthr;
+    uint32_t i = tid * per_t;
+    const uint32_t iend = min(total, i + per_t);
+    if (i < iend) {
+        uint32_t g = 0, hi = apb;   // the group whose entries hold i: s_off[g] <= i < s_off[g + 1]
+        while (hi - g > 1) {
+            const uint32_t mid = (g + hi) / 2;
+            if (s_off[mid] <= i) g = mid; else hi = mid;
+        }
+        const size_t ant0 = (size_t)v * a.ants + k0;
+        while (i < iend) {   // eight path reads in flight, then their LDS adds
+            uint32_t e8[8], g8[8];
+            const uint32_t n8 = min(8u, iend - i);
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) {
+                if (u < n8) {
+                    while (g + 1 < apb && i + u >= s_off[g + 1]) ++g;
+                    g8[u] = g;
+                    e8[u] = a.path[(size_t)(i + u - s_off[g]) * NA + ant0 + g];
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u)
+                if (u < n8) atomicAdd((unsigned long long *)&acc[e8[u] - e_lo], (unsigned long long)s_dp[g8[u]]);
+            i += n8;
+        }
+    }
+    // best key and counters: one contribution per ant (its first lane), into the block's LDS totals
+    if (active && j == 0) {
+        if (arrived)
+            atomicMin((unsigned long long *)&s_blk[0], (unsigned long long)(((uint64_t)cs << 32) | (k0 + grp)));
+        atomicAdd((unsigned long long *)&s_blk[1], (unsigned long long)s);
+        atomicAdd((unsigned long long *)&s_blk[2], (unsigned long long)ncand);
+        if (arrived) {
+            atomicAdd((unsigned long long *)&s_blk[3], 1ull);
+            atomicAdd((unsigned long long *)&s_blk[4], (unsigned long long)s);
+        }
+        atomicMax((unsigned long long *)&s_blk[5], (unsigned long long)s);
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < e_cnt; e += nthr) {
+        const uint64_t x = acc[e];
+        if (x) a.depv.add(v, e_lo + e, x);
     }
     if (tid == 0) {
         if (s_blk[0] != ~0ull) atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)s_blk[0]);
@@ -677,7 +722,7 @@ __device__ __forceinline__ bool lds_step(const uint2 *s_rec, const uint64_t *s_w
     uint64_t r = myr;
     if (L == 2) r = SL == 0 ? dpp64<kDppQuad(0, 0, 2, 2)>(myr) : dpp64<kDppQuad(1, 1, 3, 3)>(myr);
     if (L == 4) r = dpp64<kDppQuad(SL, SL, SL, SL)>(myr);
-    if (L >= 8) r = __shfl(myr, SL, L);   // no fixed DPP pattern reaches across quads
+    if (L >= 8) r = __shfl(myr, SL, L);
     const uint64_t target = __umul64hi(r, T);
     // exactly one (chunk, lane) holds the target in its prefix interval
     uint32_t sel_x = 0, sel_y = 0, sel_c = 0;
@@ -726,86 +771,6 @@ __device__ __forceinline__ bool lds_steps(const uint2 *s_rec, const uint64_t *s_
                                         s, ncand, cs, ok, path);
     return true;
 }
-
-// Replicated-lane step: every lane of the group reads all candidates of the
-// current node (the same LDS addresses, served as broadcasts) and computes the
-// prefix sums, target and winner locally, so no value crosses lanes except
-// this step's Philox word (drawn by group lane SL).  s_rw holds per road
-// (head | head_deg << 24, head's first road, weight lo, weight hi).
-template <int L, int MAXD, int SL>
-__device__ __forceinline__ bool lds_step_repl(const uint4 *s_rw, const uint32_t *s_cost, uint32_t *bits, uint32_t j,
-                                              uint32_t m_last, uint64_t myr, uint32_t dst, uint32_t e_lo,
-                                              uint32_t &u, uint32_t &rs, uint32_t &d, uint32_t &s, uint32_t &ncand,
-                                              uint64_t &cs, bool &ok, uint32_t *path_s)
-{
-    ncand += d;
-    uint4 rec[MAXD];
-    uint64_t w[MAXD];
-#pragma unroll
-    for (int c = 0; c < MAXD; ++c) rec[c] = s_rw[min(rs + (uint32_t)c, m_last)];
-    uint64_t T = 0;
-#pragma unroll
-    for (int c = 0; c < MAXD; ++c) {
-        const uint32_t xh = rec[c].x & 0xFFFFFFu;
-        const bool live = (uint32_t)c < d && !((bits[xh >> 5] >> (xh & 31)) & 1u);
-        w[c] = live ? (((uint64_t)rec[c].w << 32) | rec[c].z) : 0;
-        T += w[c];
-    }
-    if (T == 0) return false;   // dead end
-    uint64_t r = myr;
-    if (L == 2) r = SL == 0 ? dpp64<kDppQuad(0, 0, 2, 2)>(myr) : dpp64<kDppQuad(1, 1, 3, 3)>(myr);
-    if (L == 4) r = dpp64<kDppQuad(SL, SL, SL, SL)>(myr);
-    if (L >= 8) r = __shfl(myr, SL, L);
-    const uint64_t target = __umul64hi(r, T);
-    // first candidate whose inclusive prefix exceeds the target
-    // exactly one candidate c has prefix_{c-1} <= target < prefix_c with w_c > 0
-    uint64_t prefix = 0;
-    uint32_t sel1 = 0, sx = 0, sy = 0;
-#pragma unroll
-    for (int c = 0; c < MAXD; ++c) {
-        const uint64_t before = prefix;
-        prefix += w[c];
-        const bool take = before <= target && target < prefix;
-        sel1 |= take ? (uint32_t)c + 1 : 0u;
-        sx |= take ? rec[c].x : 0u;
-        sy |= take ? rec[c].y : 0u;
-    }
-    if (sel1 == 0) return false;   // unreachable when T > 0
-    const uint4 rs4 = make_uint4(sx, sy, 0, 0);
-    const uint32_t xsel = rs4.x & 0xFFFFFFu;
-    const uint32_t esel = rs + sel1 - 1;
-    if (j == 0) {
-        *path_s = e_lo + esel;
-        atomicOr(&bits[xsel >> 5], 1u << (xsel & 31));
-    }
-    cs += s_cost[esel];
-    ++s;
-    u = xsel;
-    rs = rs4.y;
-    d = rs4.x >> 24;
-    if (u == dst) {
-        ok = true;
-        return false;
-    }
-    return true;
-}
-
-template <int L, int MAXD, int SL>
-__device__ __forceinline__ bool lds_steps_repl(const uint4 *s_rw, const uint32_t *s_cost, uint32_t *bits,
-                                               uint32_t j, uint32_t m_last, uint64_t myr, uint32_t dst,
-                                               uint32_t max_steps, uint32_t NA, uint32_t e_lo, uint32_t &u,
-                                               uint32_t &rs, uint32_t &d, uint32_t &s, uint32_t &ncand, uint64_t &cs,
-                                               bool &ok, uint32_t *path)
-{
-    if (s >= max_steps || !lds_step_repl<L, MAXD, SL>(s_rw, s_cost, bits, j, m_last, myr, dst, e_lo, u, rs, d, s,
-                                                      ncand, cs, ok, path + (size_t)s * NA))
-        return false;
-    if constexpr (SL + 1 < L)
-        return lds_steps_repl<L, MAXD, SL + 1>(s_rw, s_cost, bits, j, m_last, myr, dst, max_steps, NA, e_lo, u, rs,
-                                               d, s, ncand, cs, ok, path);
-    return true;
-}
-
 // Walk for graphs whose roads fit in LDS.  One block serves `apb` ants of one
 // vehicle (blocks_per_vehicle = bpv).  Prologue: the block derives the
 // vehicle's goal term for every node and stages, per road, the head node,
@@ -820,7 +785,7 @@ __device__ __forceinline__ bool lds_steps_repl(const uint4 *s_rw, const uint32_t
 // fixed DPP pattern.  A step is three dependent LDS reads (road record,
 // visited word, chosen road's cost).  Deposits are gathered per block
 // (lds_block_finish).
-template <int L, int CH, bool REPL>
+template <int L, int CH>
 __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
 {
     extern __shared__ uint64_t s_mem[];
@@ -837,6 +802,7 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
     uint32_t *s_cost = (uint32_t *)(s_mem + 2 * (size_t)e_cnt);   // [e_cnt] road cost
     uint32_t *s_aux = s_cost + ((e_cnt + 1) & ~1u);  // goal terms, then visited bits
     const uint32_t nws = ((n_cnt + 31) / 32) | 1u;   // visited words per ant (odd stride spreads banks)
+    uint32_t *s_grp = s_aux + ((max(n_cnt, nws * a.apb) + 1) & ~1u);   // per-group scratch (lds_block_finish)
 
     // ---- prologue: choice table of this vehicle, one coalesced pass per road ----
     {
@@ -855,13 +821,8 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
             const uint32_t xl = (r.x & 0xFFFFFFu) - n_lo;
             const uint32_t eta = eta_of((int64_t)c + (int64_t)s_aux[xl] - (int64_t)s_aux[tl]);
             const uint64_t wgt = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
-            if (REPL) {
-                ((uint4 *)s_mem)[le] = make_uint4(xl | (r.x & 0xFF000000u), r.y - e_lo, (uint32_t)wgt,
-                                                  (uint32_t)(wgt >> 32));
-            } else {
-                s_w[le] = wgt;
-                s_rec[le] = make_uint2(xl | (r.x & 0xFF000000u), r.y - e_lo);
-            }
+            s_w[le] = wgt;
+            s_rec[le] = make_uint2(xl | (r.x & 0xFF000000u), r.y - e_lo);
             s_cost[le] = c;
         }
     }
@@ -888,14 +849,9 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
         const uint32_t it = a.iter + slot_iter(a.pher, v, 0);
         for (;;) {
             const uint64_t myr = philox_u64(q.qid, k, it, s + j, a.seed_lo, a.seed_hi);
-            if (REPL) {
-                if (!lds_steps_repl<L, CH, 0>((const uint4 *)s_mem, s_cost, bits, j, m_last, myr, q.dst - n_lo,
-                                              a.max_steps, NA, e_lo, u, rs, d, s, ncand, cs64, ok, path))
-                    break;
-            } else if (!lds_steps<L, CH, 0>(s_rec, s_w, s_cost, bits, j, m_last, myr, q.dst - n_lo, a.max_steps, NA,
-                                            e_lo, u, rs, d, s, ncand, cs64, ok, path)) {
+            if (!lds_steps<L, CH, 0>(s_rec, s_w, s_cost, bits, j, m_last, myr, q.dst - n_lo, a.max_steps, NA, e_lo, u,
+                                     rs, d, s, ncand, cs64, ok, path))
                 break;
-            }
         }
         cs = cs64 > kPathCostCap ? kPathCostCap : (uint32_t)cs64;
         if (j == 0) {
@@ -903,7 +859,7 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
             a.ant_cost[ant] = ok ? cs : kNoCost;
         }
     }
-    lds_block_finish<L>(a, s_mem, e_lo, e_cnt, v, k, active, ok, s, cs, ncand, j, path, NA);
+    lds_block_finish<L>(a, s_mem, s_grp, e_lo, e_cnt, v, part * a.apb, active, ok, s, cs, ncand, grp, j, NA);
 }
 
 // Value of the last lane of the group (the group total of an inclusive prefix).
@@ -1029,6 +985,7 @@ __global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
     uint32_t *s_rev = s_cost + e_cnt;                             // [e_cnt] city-local roads, grouped by head
     uint32_t *s_aux = s_rev + e_cnt;                              // goal terms, then visited road bits
     const uint32_t nws = ((e_cnt + 31) / 32) | 1u;                // visited words per ant (odd stride)
+    uint32_t *s_grp = s_aux + ((max(n_cnt, nws * a.apb) + 1) & ~1u);   // per-group scratch (lds_block_finish)
 
     {
         const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
@@ -1037,20 +994,36 @@ __global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
     }
     __syncthreads();
     {
+        // four roads per thread at a time, their loads (all independent) ahead of the arithmetic
         const bool a1b2 = a.alpha == 1 && a.beta == 2;
         const PherRead tau = pher_at(a.pher, v, a.t_local);
-        for (uint32_t le = tid; le < e_cnt; le += nthr) {
-            const uint32_t e = e_lo + le;
-            const uint2 r = a.rec[e];
-            const uint32_t c = a.cost[e], t = tau(e), tl = a.tail[e] - n_lo;
-            const uint32_t h = r.x & 0xFFFFFFu, xl = h - n_lo;
-            const uint32_t eta = eta_of((int64_t)c + (int64_t)s_aux[xl] - (int64_t)s_aux[tl]);
-            const uint64_t wgt = a1b2 ? (uint64_t)t * (eta * eta) : ipow_u64(t, a.alpha) * ipow_u64(eta, a.beta);
-            const uint32_t ri = a.rev_ptr[h], rn = a.rev_ptr[h + 1] - ri;
-            s_R[le] = make_uint4((r.y - e_lo) | ((r.x >> 24) << 16) | (h == q.dst ? 0x80000000u : 0u),
-                                 (ri - e_lo) | (rn << 16), (uint32_t)wgt, (uint32_t)(wgt >> 32));
-            s_cost[le] = c;
-            s_rev[le] = a.rev_edge[e] - e_lo;
+        const uint32_t dst_l = q.dst - n_lo;
+        for (uint32_t b0 = tid; b0 < e_cnt; b0 += 4 * nthr) {
+            uint4 st[4];
+            uint32_t c[4], t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t le = b0 + u * nthr;
+                if (le < e_cnt) {
+                    st[u] = a.rvs[e_lo + le];
+                    c[u] = a.cost[e_lo + le];
+                    t[u] = tau(e_lo + le);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t le = b0 + u * nthr;
+                if (le < e_cnt) {
+                    const uint32_t xl = st[u].z & 0xFFFFu, tl = st[u].z >> 16;
+                    const uint32_t eta = eta_of((int64_t)c[u] + (int64_t)s_aux[xl] - (int64_t)s_aux[tl]);
+                    const uint64_t wgt = a1b2 ? (uint64_t)t[u] * (eta * eta)
+                                              : ipow_u64(t[u], a.alpha) * ipow_u64(eta, a.beta);
+                    s_R[le] = make_uint4(st[u].x | (xl == dst_l ? 0x80000000u : 0u), st[u].y, (uint32_t)wgt,
+                                         (uint32_t)(wgt >> 32));
+                    s_cost[le] = c[u];
+                    s_rev[le] = st[u].w;
+                }
+            }
         }
     }
     __syncthreads();
@@ -1089,7 +1062,7 @@ __global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
             a.ant_cost[ant] = ok ? cs : kNoCost;
         }
     }
-    lds_block_finish<L>(a, s_mem, e_lo, e_cnt, v, k, active, ok, s, cs, ncand, j, path, NA);
+    lds_block_finish<L>(a, s_mem, s_grp, e_lo, e_cnt, v, part * a.apb, active, ok, s, cs, ncand, grp, j, NA);
 }
 
 // A vehicle served by k_walk_glb, with the walk's start data (k_glb_list).
@@ -1762,6 +1735,7 @@ struct gmacop_graph {
     uint32_t *rev_ptr = nullptr, *rev_edge = nullptr, *tail = nullptr;
     uint2 *rec = nullptr;              // head | head_out_degree << 24, head's first out-road (n < 2^24)
     uint4 *rec32 = nullptr;            // [m][2] global-walker road records: rec, head coordinates; cost, pheromone
+    uint4 *rvs = nullptr;              // [m] static city-local road records of k_walk_ldsr
     uint32_t *node_lo = nullptr, *node_inst = nullptr;   // first node / index of each node's city
     uint32_t *inst_off_dev = nullptr, *inst_eoff_dev = nullptr;   // node / road range of each city
     uint8_t *inst_fits = nullptr;      // per city: served by the LDS walker in the current plan
@@ -1805,7 +1779,7 @@ struct gmacop_graph {
     {
         (void)hipSetDevice(device);
         dfree(row_ptr); dfree(col); dfree(len_dm); dfree(cycle); dfree(base_load);
-        dfree(rev_ptr); dfree(rev_edge); dfree(tail); dfree(rec); dfree(rec32); dfree(node_lo); dfree(node_inst);
+        dfree(rev_ptr); dfree(rev_edge); dfree(tail); dfree(rec); dfree(rec32); dfree(rvs); dfree(node_lo); dfree(node_inst);
         dfree(inst_fits); dfree(vclass); dfree(inst_off_dev); dfree(inst_eoff_dev); dfree(speed); dfree(green); dfree(x); dfree(y);
         dfree(t0); dfree(wf); dfree(tau); dfree(load); dfree(cost); dfree(cnt); dfree(dep);
         dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_key); dfree(steps);
@@ -1999,7 +1973,6 @@ struct WalkPlan {
     uint32_t maxd = 4;             // candidate bound the kernels are built for
     bool legacy = false;           // k_walk for every vehicle (graphs with 2^24 nodes or more)
     uint32_t lds_lanes = 4, lds_apb = 0, lds_bpv = 0;
-    bool lds_repl = false;                // replicated-lane steps (k_walk_lds<..., true>)
     uint32_t road_maxd = 4;               // candidate and in-road bound of k_walk_ldsr
     size_t lds_bytes[kLdsClasses + 1] = {};   // [c]: dynamic LDS of LDS class c's launch, 0 = none
     bool glb = false;              // some city is served by k_walk_glb
@@ -2020,7 +1993,7 @@ int launch_walk_lds(const LdsWalkArgs &wa, const WalkPlan &pl, hipStream_t st, b
 {
     constexpr int CH = (MAXD + L - 1) / L;
     const bool road = is_road_class(wa.cls);
-    auto kern = road ? k_walk_ldsr<L, CH> : pl.lds_repl ? k_walk_lds<L, MAXD, true> : k_walk_lds<L, CH, false>;
+    auto kern = road ? k_walk_ldsr<L, CH> : k_walk_lds<L, CH>;
     if (setup) {   // before any launch: allow the largest dynamic LDS of the classes this kernel serves
         size_t mx = 0;
         for (uint32_t c = 1; c <= kLdsClasses; ++c)
@@ -2158,10 +2131,9 @@ uint32_t lanes_or(uint32_t L, uint32_t dflt) { return (L == 1 || L == 2 || L == 
 // not charged the largest city's LDS: k_walk_ldsr (visited state per road,
 // classes 1..3) where its layout fits, else k_walk_lds (visited state per
 // node, classes 4..6); larger cities go to k_walk_glb.  GMACOP_WALK_KERNEL
-// (lds | global | legacy), GMACOP_LDS_VARIANT (node | repl: k_walk_lds
-// only), GMACOP_WALK_LANES, GMACOP_GLB_LANES (1, 2, 4, 8) and
-// GMACOP_BLOOM_LOG2 (8..16) override the choices for tuning; results do not
-// depend on them.
+// (lds | global | legacy), GMACOP_LDS_VARIANT (node: k_walk_lds only),
+// GMACOP_WALK_LANES, GMACOP_GLB_LANES (1, 2, 4, 8) and GMACOP_BLOOM_LOG2
+// (8..16) override the choices for tuning; results do not depend on them.
 WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
 {
     WalkPlan pl;
@@ -2175,10 +2147,8 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     bool road_ok = true;
     {
         const char *var = getenv("GMACOP_LDS_VARIANT");
-        const bool repl = var && strcmp(var, "repl") == 0;
-        pl.lds_repl = repl && pl.maxd <= 8;
         const uint32_t md = std::max(g->max_deg, g->max_indeg);
-        road_ok = !(var && (strcmp(var, "node") == 0 || repl)) && md <= kMaxDegree;
+        road_ok = !(var && strcmp(var, "node") == 0) && md <= kMaxDegree;
         pl.road_maxd = md <= 4 ? 4 : md <= 8 ? 8 : md <= 16 ? 16 : 32;
     }
     pl.lds_apb = std::max<uint32_t>(1, std::min<uint32_t>(p->ants, 512 / pl.lds_lanes));
@@ -2188,11 +2158,14 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     for (uint32_t i = 0; i < g->n_inst; ++i) {
         const uint32_t nc = g->inst_off[i + 1] - g->inst_off[i];
         const uint32_t ec = g->inst_eoff[i + 1] - g->inst_eoff[i];
-        // k_walk_ldsr: 16-byte record, cost and in-road entry per road; goal terms, then road bits per ant
-        const size_t need_r = (size_t)ec * 24 + std::max<size_t>(nc, (size_t)(((ec + 31) / 32) | 1u) * pl.lds_apb) * 4;
-        // k_walk_lds: 8-byte record, weight and cost per road; goal terms, then node bits per ant
-        const size_t need_n = (size_t)ec * 16 + (size_t)((ec + 1) & ~1u) * 4 +
-                              std::max<size_t>(nc, (size_t)(((nc + 31) / 32) | 1u) * pl.lds_apb) * 4;
+        // k_walk_ldsr: 16-byte record, cost and in-road entry per road; goal terms, then road bits per
+        // ant (an even count of words); per-group scratch
+        const size_t aux_r = std::max<size_t>(nc, (size_t)(((ec + 31) / 32) | 1u) * pl.lds_apb);
+        const size_t need_r = (size_t)ec * 24 + ((aux_r + 1) & ~(size_t)1) * 4 + lds_group_bytes(pl.lds_apb);
+        // k_walk_lds: 8-byte record, weight and cost per road; goal terms, then node bits per ant; scratch
+        const size_t aux_n = std::max<size_t>(nc, (size_t)(((nc + 31) / 32) | 1u) * pl.lds_apb);
+        const size_t need_n = (size_t)ec * 16 + (size_t)((ec + 1) & ~1u) * 4 + ((aux_n + 1) & ~(size_t)1) * 4 +
+                              lds_group_bytes(pl.lds_apb);
         auto tier = [&](size_t need) -> uint8_t { return need <= t1 ? 1 : need <= t2 ? 2 : need <= t3 ? 3 : 0; };
         uint8_t c = 0;
         size_t need = 0;
@@ -2285,8 +2258,20 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
         }
     }
     g->inst_eoff[g->n_inst] = m;
+    // static city-local road records of k_walk_ldsr (meaningful in cities under 2^16 roads, the only ones it serves)
+    std::vector<uint4> rvs(m);
+    for (uint32_t u = 0; u < n; ++u) {
+        const uint32_t c = node_inst[u], e_lo = g->inst_eoff[c], n_lo = g->inst_off[c];
+        for (uint32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; ++e) {
+            const uint32_t x = d->col[e];
+            const uint32_t deg = d->row_ptr[x + 1] - d->row_ptr[x], ind = rev_ptr[x + 1] - rev_ptr[x];
+            rvs[e] = make_uint4(((d->row_ptr[x] - e_lo) & 0xFFFFu) | (std::min(deg, 0xFFFFu) << 16),
+                                ((rev_ptr[x] - e_lo) & 0xFFFFu) | (std::min(ind, 0xFFFFu) << 16),
+                                ((x - n_lo) & 0xFFFFu) | (((u - n_lo) & 0xFFFFu) << 16), (rev_edge[e] - e_lo) & 0xFFFFu);
+        }
+    }
     if ((rc = upload(&g->tail, tail.data(), m)) || (rc = upload(&g->rec, rec.data(), m)) ||
-        (rc = upload(&g->rec32, rec32.data(), 2 * (size_t)m)) || (rc = upload(&g->node_lo, node_lo.data(), n)) ||
+        (rc = upload(&g->rec32, rec32.data(), 2 * (size_t)m)) || (rc = upload(&g->rvs, rvs.data(), m)) || (rc = upload(&g->node_lo, node_lo.data(), n)) ||
         (rc = upload(&g->node_inst, node_inst.data(), n)) || (rc = dalloc(&g->inst_fits, g->n_inst)) ||
         (rc = upload(&g->inst_off_dev, g->inst_off.data(), g->n_inst + 1)) ||
         (rc = upload(&g->inst_eoff_dev, g->inst_eoff.data(), g->n_inst + 1))) {
@@ -2435,7 +2420,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     wa.iter_max = g->iter_max;
     LdsWalkArgs la{};
     la.row_ptr = g->row_ptr; la.col = g->col; la.cost = g->cost; la.pher = pv; la.depv = dv; la.x = g->x; la.y = g->y;
-    la.rec = g->rec; la.tail = g->tail; la.rev_ptr = g->rev_ptr; la.rev_edge = g->rev_edge;
+    la.rec = g->rec; la.tail = g->tail; la.rev_ptr = g->rev_ptr; la.rvs = g->rvs;
     la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev; la.inst_eoff = g->inst_eoff_dev; la.vclass = g->vclass;
     la.od = od; la.n = g->n; la.m = g->m; la.nq = nq; la.ants = p->ants; la.apb = plan.lds_apb; la.bpv = plan.lds_bpv;
     la.max_steps = S; la.alpha = p->alpha; la.beta = p->beta; la.kgoal = wa.kgoal; la.nwords = nwords;
@@ -2535,7 +2520,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
             (uint64_t)(uintptr_t)g->iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
             p->rho_q16, p->tau0_q16, p->tau_min_q16, p->tau_max_q16, p->q_deposit, p->theta, p->th_max,
             p->t_max_ms, p->vmax_kmh, p->mode, p->flags & GMACOP_NO_LOAD_UPDATE, p->seed, p->iter_offset,
-            plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.lds_repl, plan.road_maxd,
+            plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.road_maxd,
             (uint64_t)plan.lds_bytes[1], (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3],
             (uint64_t)plan.lds_bytes[4], (uint64_t)plan.lds_bytes[5], (uint64_t)plan.lds_bytes[6], plan.glb, plan.glb_lanes, plan.glb_apb,
             plan.bloom_log2, plan.glb_nwords, plan.glb_blocks, (uint64_t)(uintptr_t)g->glb.veh, (uint64_t)(uintptr_t)g->glb.vlen,
@@ -2931,7 +2916,7 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
     {
         LdsWalkArgs la{};
         la.row_ptr = g->row_ptr; la.col = g->col; la.cost = s->cost; la.pher = pv; la.depv = dv; la.x = g->x;
-        la.y = g->y; la.rec = g->rec; la.tail = g->tail; la.rev_ptr = g->rev_ptr; la.rev_edge = g->rev_edge;
+        la.y = g->y; la.rec = g->rec; la.tail = g->tail; la.rev_ptr = g->rev_ptr; la.rvs = g->rvs;
         la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev;
         la.inst_eoff = g->inst_eoff_dev; la.vclass = s->vclass; la.od = s->slot_od; la.n = g->n; la.m = g->m;
         la.nq = NS; la.ants = A; la.apb = plan.lds_apb; la.bpv = plan.lds_bpv; la.max_steps = S; la.alpha = p.alpha;

@@ -210,8 +210,7 @@ def test_full_workload_against_stored_oracle_results(name):
 @pytest.mark.parametrize("kernel,lanes,bloom,variant", [
     ("legacy", 1, 11, ""), ("global", 1, 11, ""), ("global", 2, 11, ""), ("global", 4, 11, ""),
     ("global", 8, 11, ""), ("global", 4, 8, ""), ("lds", 1, 11, ""), ("lds", 2, 11, ""), ("lds", 4, 11, ""),
-    ("lds", 8, 11, ""), ("lds", 1, 11, "repl"), ("lds", 2, 11, "repl"), ("lds", 4, 11, "repl"),
-    ("lds", 8, 11, "repl"), ("lds", 1, 11, "node"), ("lds", 2, 11, "node"), ("lds", 4, 11, "node"),
+    ("lds", 8, 11, ""), ("lds", 1, 11, "node"), ("lds", 2, 11, "node"), ("lds", 4, 11, "node"),
     ("lds", 8, 11, "node")])
 def test_walker_shapes_give_identical_results(monkeypatch, kernel, lanes, bloom, variant):
     """Every walker shape (first global-memory walker, global walker with
