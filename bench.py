@@ -32,7 +32,10 @@ BYTES_PER_CANDIDATE = 20
 BYTES_PER_DEPOSIT_ROAD = 12
 
 
-PMC_PROFILE = os.path.join(ROOT, "profiles", "k_walk_lds_grid32x32_256veh_128ants_100it.md")
+PMC_PROFILE = os.path.join(ROOT, "profiles", "k_walk_ldsr_grid32x32_256veh_128ants_100it.md")
+# the walker kernels of each workload's walk phase
+WALK_KERNEL = {"grid8": "k_walk_ldsr", "grid32": "k_walk_ldsr", "planar100k": "k_walk_glb",
+               "multicity": "k_walk_ldsr + k_walk_lds + k_walk_glb"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_14244_amd", "csrc", "gmacop.hip")
 
 
@@ -268,7 +271,8 @@ def main():
                             BYTES_PER_DEPOSIT_ROAD * kt["deposit_roads"]) / nl
         achieved = bytes_per_launch / (walk_ms * 1e-3) / 1e9
         traffic = measured_walk_traffic() if args.workload == "grid32" else None
-        roofline = {"bound": "hbm", "kernel": "k_walk", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        roofline = {"bound": "hbm", "kernel": WALK_KERNEL[args.workload], "achieved": round(achieved, 2),
+                    "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                     "traffic": None if traffic is None else round(traffic),
                     "avg_launch_ms": round(walk_ms, 5), "launches_timed": nl,

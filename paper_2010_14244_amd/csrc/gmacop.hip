@@ -1406,21 +1406,44 @@ struct GlbListArgs {
     const uint32_t *row_ptr, *node_lo;
     const int32_t *x, *y;
     uint32_t nq, ants, kgoal;
-    GlbVeh *veh;
+    GlbVeh *vrec;              // [nq] start data of each vehicle of this walker (k_glb_prep)
+    GlbVeh *veh;               // [*glb_n] the launch's ordered list (k_glb_list)
     uint32_t *glb_n;
-    uint32_t *vlen;            // [nq] longest walk of each vehicle in the previous launch; reset here
+    uint32_t *vlen;            // [nq] longest walk of each vehicle in the previous launch; reset by k_glb_list
     uint32_t *ant_len, *ant_cost;
 };
+
+// Once per call: the start data of every vehicle served by k_walk_glb; ants
+// of vehicles no walker serves get an empty result.
+__global__ void k_glb_prep(GlbListArgs a)
+{
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.nq) return;
+    const uint8_t cls = a.vclass[v];
+    if (cls == kWalkerGlobal) {
+        const gmacop_od q = a.od[v];
+        GlbVeh r;
+        r.v = v; r.qid = q.qid; r.src = q.src; r.dst = q.dst;
+        r.rs = a.row_ptr[q.src]; r.d = a.row_ptr[q.src + 1] - r.rs; r.n_lo = a.node_lo[q.src]; r.pad = 0;
+        r.dx = a.x[q.dst]; r.dy = a.y[q.dst];
+        const uint64_t hu = (uint64_t)goal_ms(a.x[q.src], a.y[q.src], r.dx, r.dy, a.kgoal);
+        r.hu_lo = (uint32_t)hu; r.hu_hi = (uint32_t)(hu >> 32);
+        a.vrec[v] = r;
+    } else if (cls == kWalkerNone) {
+        for (uint32_t k = 0; k < a.ants; ++k) {
+            a.ant_len[(size_t)v * a.ants + k] = 0;
+            a.ant_cost[(size_t)v * a.ants + k] = kNoCost;
+        }
+    }
+}
 
 constexpr uint32_t kOrderBuckets = 256;   // longest-walk buckets of 4 steps (the last: 1020 and more)
 
 // One block, before every k_walk_glb launch: the vehicles that walker
-// serves, with the start data of their walks, ordered by the longest walk
-// each had in the previous launch, longest first.  Walk lengths persist from
-// one iteration to the next, so long walks start early instead of trailing
-// at the end of the launch; the order only schedules work (every ant's walk
-// is fixed by its own counters).  Ants of vehicles no walker serves get an
-// empty result.
+// serves, ordered by the longest walk each had in the previous launch,
+// longest first.  Walk lengths persist from one iteration to the next, so
+// long walks start early instead of trailing at the end of the launch; the
+// order only schedules work (every ant's walk is fixed by its own counters).
 __global__ __launch_bounds__(1024) void k_glb_list(GlbListArgs a)
 {
     __shared__ uint32_t s_hist[kOrderBuckets];
@@ -1430,36 +1453,35 @@ __global__ __launch_bounds__(1024) void k_glb_list(GlbListArgs a)
     for (uint32_t v = tid; v < a.nq; v += blockDim.x)
         if (a.vclass[v] == kWalkerGlobal) atomicAdd(&s_hist[min(a.vlen[v] >> 2, kOrderBuckets - 1)], 1u);
     __syncthreads();
-    if (tid == 0) {   // bucket start positions, longest bucket first
-        uint32_t sum = 0;
-        for (uint32_t b = kOrderBuckets; b-- > 0;) {
-            const uint32_t c = s_hist[b];
-            s_hist[b] = sum;
-            sum += c;
+    if (tid < kWave) {   // bucket start positions, longest bucket first: lane t scans buckets 255-4t .. 252-4t
+        constexpr uint32_t per = kOrderBuckets / kWave;
+        uint32_t c[per], sum = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < per; ++i) {
+            c[i] = s_hist[kOrderBuckets - 1 - (tid * per + i)];
+            sum += c[i];
         }
-        *a.glb_n = sum;
+        uint32_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_up((int)incl, off);
+            incl += (int)tid >= off ? o : 0u;
+        }
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (uint32_t i = 0; i < per; ++i) {
+            s_hist[kOrderBuckets - 1 - (tid * per + i)] = run;
+            run += c[i];
+        }
+        if (tid == kWave - 1) *a.glb_n = incl;
     }
     __syncthreads();
-    for (uint32_t v = tid; v < a.nq; v += blockDim.x) {
-        const uint8_t cls = a.vclass[v];
-        if (cls == kWalkerGlobal) {
+    for (uint32_t v = tid; v < a.nq; v += blockDim.x)
+        if (a.vclass[v] == kWalkerGlobal) {
             const uint32_t pos = atomicAdd(&s_hist[min(a.vlen[v] >> 2, kOrderBuckets - 1)], 1u);
             a.vlen[v] = 0;
-            const gmacop_od q = a.od[v];
-            GlbVeh r;
-            r.v = v; r.qid = q.qid; r.src = q.src; r.dst = q.dst;
-            r.rs = a.row_ptr[q.src]; r.d = a.row_ptr[q.src + 1] - r.rs; r.n_lo = a.node_lo[q.src]; r.pad = 0;
-            r.dx = a.x[q.dst]; r.dy = a.y[q.dst];
-            const uint64_t hu = (uint64_t)goal_ms(a.x[q.src], a.y[q.src], r.dx, r.dy, a.kgoal);
-            r.hu_lo = (uint32_t)hu; r.hu_hi = (uint32_t)(hu >> 32);
-            a.veh[pos] = r;
-        } else if (cls == kWalkerNone) {
-            for (uint32_t k = 0; k < a.ants; ++k) {
-                a.ant_len[(size_t)v * a.ants + k] = 0;
-                a.ant_cost[(size_t)v * a.ants + k] = kNoCost;
-            }
+            a.veh[pos] = a.vrec[v];
         }
-    }
 }
 
 struct BestArgs {
@@ -1705,8 +1727,8 @@ unsigned blocks_for(uint64_t work, unsigned per_block)
 // words and epochs.  The words keep their meaning across calls as long as
 // the slot layout stays the same; a new layout clears them.
 struct GlbWork {
-    GlbVeh *veh = nullptr;
-    size_t cap_veh = 0;
+    GlbVeh *veh = nullptr, *vrec = nullptr;   // the launch's ordered list; start data per vehicle
+    size_t cap_veh = 0, cap_vrec = 0;
     uint32_t *vlen = nullptr;          // [vehicles] longest walk in the last launch
     size_t cap_vlen = 0;
     uint32_t *ctl = nullptr;           // [0]: vehicles listed, [1]: next ticket, [2]: waves done
@@ -1718,9 +1740,9 @@ struct GlbWork {
 
     void release()
     {
-        dfree(veh); dfree(vlen); dfree(ctl); dfree(words); dfree(epoch);
-        veh = nullptr; vlen = nullptr; ctl = nullptr; words = nullptr; epoch = nullptr;
-        cap_veh = cap_vlen = cap_words = cap_epoch = 0;
+        dfree(veh); dfree(vrec); dfree(vlen); dfree(ctl); dfree(words); dfree(epoch);
+        veh = nullptr; vrec = nullptr; vlen = nullptr; ctl = nullptr; words = nullptr; epoch = nullptr;
+        cap_veh = cap_vrec = cap_vlen = cap_words = cap_epoch = 0;
         slots = nw2 = 0;
     }
 };
@@ -1828,6 +1850,7 @@ int glb_prepare(GlbWork &w, uint32_t nq, uint64_t slots, uint32_t nw2)
 {
     int rc;
     if ((rc = grow(&w.veh, &w.cap_veh, std::max<size_t>(nq, 1), false)) ||
+        (rc = grow(&w.vrec, &w.cap_vrec, std::max<size_t>(nq, 1), false)) ||
         (rc = grow(&w.vlen, &w.cap_vlen, std::max<size_t>(nq, 1), true)))
         return rc;
     if (!w.ctl) {
@@ -2445,7 +2468,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     ga.ant_cost = g->ant_cost; ga.iter_key = g->iter_key; ga.steps = steps;
     ga.counters = g->counters; ga.iter_max = g->iter_max;
     const GlbListArgs gla{od, g->vclass, g->row_ptr, g->node_lo, g->x, g->y, nq, p->ants, wa.kgoal,
-                          g->glb.veh, g->glb.ctl, g->glb.vlen, g->ant_len, g->ant_cost};
+                          g->glb.vrec, g->glb.veh, g->glb.ctl, g->glb.vlen, g->ant_len, g->ant_cost};
     const bool any_lds = !plan.legacy && plan.any_lds();
     if (any_lds && (rc = setup_walk_lds(la, plan, st))) return rc;
 
@@ -2465,6 +2488,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         if (nq && !plan.legacy) {
             hipLaunchKernelGGL(k_classify, dim3(blocks_for(nq, 256)), dim3(256), 0, st, od, nq, g->n,
                                (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, g->vclass);
+            if (plan.glb) hipLaunchKernelGGL(k_glb_prep, dim3(blocks_for(nq, 256)), dim3(256), 0, st, gla);
         }
         HIP_TRY(hipGetLastError());
         WalkArgs wt = wa;
@@ -2523,7 +2547,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
             plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.road_maxd,
             (uint64_t)plan.lds_bytes[1], (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3],
             (uint64_t)plan.lds_bytes[4], (uint64_t)plan.lds_bytes[5], (uint64_t)plan.lds_bytes[6], plan.glb, plan.glb_lanes, plan.glb_apb,
-            plan.bloom_log2, plan.glb_nwords, plan.glb_blocks, (uint64_t)(uintptr_t)g->glb.veh, (uint64_t)(uintptr_t)g->glb.vlen,
+            plan.bloom_log2, plan.glb_nwords, plan.glb_blocks, (uint64_t)(uintptr_t)g->glb.veh, (uint64_t)(uintptr_t)g->glb.vrec, (uint64_t)(uintptr_t)g->glb.vlen,
             (uint64_t)(uintptr_t)g->glb.ctl, (uint64_t)(uintptr_t)g->glb.words, (uint64_t)(uintptr_t)g->glb.epoch,
             (uint64_t)lds, (uint64_t)(uintptr_t)g->vclass,
             (uint64_t)(uintptr_t)g->lazy, (uint64_t)(uintptr_t)g->dep_ind, (uint64_t)(uintptr_t)g->touched,
@@ -2909,7 +2933,8 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
                        g->n, (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, s->vclass);
     if (plan.glb) {
         const GlbListArgs gla{s->slot_od, s->vclass, g->row_ptr, g->node_lo, g->x, g->y, NS, A, kgoal,
-                              s->glb.veh, s->glb.ctl, s->glb.vlen, s->ant_len, s->ant_cost};
+                              s->glb.vrec, s->glb.veh, s->glb.ctl, s->glb.vlen, s->ant_len, s->ant_cost};
+        hipLaunchKernelGGL(k_glb_prep, dim3(blocks_for(NS, 256)), dim3(256), 0, st, gla);
         hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, st, gla);
     }
     if ((rc = kt.start(0, &tm))) return rc;
