@@ -1784,6 +1784,9 @@ struct gmacop_graph {
     uint64_t launches[4] = {0, 0, 0, 0};
     double ms[4] = {0, 0, 0, 0};
     struct Timed { hipEvent_t a, b; int kernel; };
+    // a second stream for the global walker, run beside the LDS walkers of the same iteration
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     std::vector<Timed> pending;           // recorded, not yet summed
     std::vector<hipEvent_t> spare;
     // independent mode: lazy pheromone and deposits per vehicle slot
@@ -1813,6 +1816,9 @@ struct gmacop_graph {
             (void)hipEventDestroy(t.b);
         }
         for (auto e : spare) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
         if (gexec) (void)hipGraphExecDestroy(gexec);
     }
 };
@@ -2369,6 +2375,11 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     if (!plan.legacy && plan.glb &&
         (rc = glb_prepare(g->glb, nq, (uint64_t)plan.glb_blocks * plan.glb_apb, plan.glb_nwords)))
         return rc;
+    if (!plan.legacy && plan.glb && plan.any_lds() && !g->side) {   // stream and events of the side launch
+        HIP_TRY(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&g->join, hipEventDisableTiming));
+    }
     if ((rc = grow(&g->vclass, &g->cap_vclass, std::max<size_t>(nq, 1), false))) return rc;
     if (plan.city_class != g->city_class_dev) {   // per-city walker choice, uploaded when it changes
         HIP_TRY(hipMemcpy(g->inst_fits, plan.city_class.data(), g->n_inst, hipMemcpyHostToDevice));
@@ -2506,6 +2517,15 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
                           : md <= 8 ? launch_walk<8>(wt, lds, st)
                           : md <= 16 ? launch_walk<16>(wt, lds, st)
                                      : launch_walk<32>(wt, lds, st);
+                } else if (plan.glb && plan.any_lds()) {
+                    // both kinds of walker: the global one on the side stream, beside the LDS ones
+                    HIP_TRY(hipEventRecord(g->fork, st));
+                    HIP_TRY(hipStreamWaitEvent(g->side, g->fork, 0));
+                    hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, g->side, gla);
+                    erc = launch_walk_glb_any(gt, plan, g->side);
+                    if (!erc) erc = launch_walk_lds_classes(lt, plan, st);
+                    HIP_TRY(hipEventRecord(g->join, g->side));
+                    HIP_TRY(hipStreamWaitEvent(st, g->join, 0));
                 } else {
                     erc = launch_walk_lds_classes(lt, plan, st);
                     if (!erc && plan.glb) {

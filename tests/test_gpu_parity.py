@@ -250,7 +250,8 @@ def test_all_walker_kinds_in_one_iteration():
     """One launch sequence where a small grid uses the per-road-visited LDS
     walker, a 2000-node city whose per-road layout does not fit LDS at 128
     ants per block uses the per-node LDS walker, and a 12000-node city the
-    global walker; all deposit on one shared pheromone vector."""
+    global walker (on a second stream, beside the LDS walkers); all deposit on
+    one shared pheromone vector.  Eager and HIP-graph launches."""
     rng = np.random.default_rng(43)
     gs = [grid_graph(8, 8, rng), planar_graph(2000, rng), planar_graph(12000, rng)]
     packed = pack_graphs(gs)
@@ -258,7 +259,24 @@ def test_all_walker_kinds_in_one_iteration():
     vs = [random_od(gi.n, 3, rng, node_lo=int(off[i]), qid0=3 * i) for i, gi in enumerate(gs)]
     V = Vehicles(qid=np.concatenate([v.qid for v in vs]), src=np.concatenate([v.src for v in vs]),
                  dst=np.concatenate([v.dst for v in vs]))
-    check("three_walker_kinds", packed, V, default_params(ants=128, iterations=3, max_steps=400, vmax_kmh=70))
+    p = default_params(ants=128, iterations=3, max_steps=400, vmax_kmh=70)
+    check("three_walker_kinds", packed, V, p)
+    # the same call captured in a HIP graph (global walker forked onto a second stream), replayed twice
+    import torch
+    want = oracle.route(packed, V, p)
+    G = gmacop.gmacop_graph_create(packed)
+    stream = torch.cuda.Stream()
+    try:
+        b = gmacop.DeviceBatch(V, p["max_steps"])
+        for rep in range(2):
+            gmacop.gmacop_route_batch_device(G, b, dict(p, flags=gmacop.HIP_GRAPH), stream.cuda_stream)
+            stream.synchronize()
+            assert_same(b.result(), want, p["max_steps"], state=False)
+            tau, load = gmacop.gmacop_state_get(G)
+            assert np.array_equal(tau, want["tau"]) and np.array_equal(load, want["load"])
+            assert_same(gmacop.gmacop_route_batch(G, V, p), want, p["max_steps"], state=False)
+    finally:
+        gmacop.gmacop_release(G)
 
 
 def test_hip_graph_replays_match_eager():
