@@ -122,40 +122,48 @@ __device__ __forceinline__ void philox_rounds(PhiloxState &x, uint32_t k0, uint3
     if (R1 > R0) asm volatile("" : "+v"(x.c0), "+v"(x.c1), "+v"(x.c2), "+v"(x.c3));
 }
 
-// floor(sqrt(x)) for x < 2^63 from a correctly rounded single-precision
-// square root, then exact integer correction so that s*s <= x < (s+1)^2.
-// Below 2^44 (distances under 2^22 dm) the estimate is within 0.75 of
-// sqrt(x), so one step each way suffices; above, the correction loops (the
-// estimate is within 2^8 up to 2^63, and (s+1)^2 cannot overflow there).
-__device__ __forceinline__ uint64_t isqrt_u64(uint64_t x)
+// floor(sqrt(ex^2 + ey^2)) for |ex|, |ey| < 2^31.  Below 2^44 (distances
+// under 2^22 dm) the single-precision estimate formed from ex and ey
+// themselves -- both exact in float there, two rounded operations, then a
+// square root within one ulp -- is within 0.75 of the root, so one step each
+// way from the exact integer square gives the floor.  Farther apart, the
+// estimate from the rounded sum is corrected by exact integer loops.
+__device__ __forceinline__ uint32_t isqrt_dist(int32_t ex, int32_t ey)
 {
-    uint64_t s = (uint64_t)__fsqrt_rn((float)x);
+    const uint64_t x = (uint64_t)((int64_t)ex * ex) + (uint64_t)((int64_t)ey * ey);
     if (x < (1ull << 44)) {
-        s -= s * s > x ? 1u : 0u;
-        s += (s + 1) * (s + 1) <= x ? 1u : 0u;
-        return s;
+        const float fx = (float)ex, fy = (float)ey;
+        const uint32_t s = (uint32_t)__builtin_amdgcn_sqrtf(__fmaf_rn(fx, fx, fy * fy));
+        const uint64_t s2 = (uint64_t)s * s;
+        return s2 > x ? s - 1 : (s2 + 2ull * s + 1 <= x ? s + 1 : s);
     }
+    uint64_t s = (uint64_t)__fsqrt_rn((float)x);
     while (s * s > x) --s;
     while ((s + 1) * (s + 1) <= x) ++s;
-    return s;
+    return (uint32_t)s;
 }
 
 // Straight-line time-to-go from (x, y) to the destination at vmax:
 // floor(isqrt(dx^2 + dy^2) * kgoal / 2^16), kgoal = floor(360 * 2^16 / vmax).
+// Coordinates are below 2^30 in magnitude, so the differences fit 32 bits.
 __device__ __forceinline__ int64_t goal_ms(int32_t x, int32_t y, int32_t dx, int32_t dy, uint32_t kgoal)
 {
     if (kgoal == 0) return 0;
-    const int64_t ex = (int64_t)x - dx, ey = (int64_t)y - dy;
-    const uint64_t d2 = (uint64_t)(ex * ex) + (uint64_t)(ey * ey);
-    return (int64_t)((isqrt_u64(d2) * kgoal) >> 16);
+    return (int64_t)(((uint64_t)isqrt_dist(x - dx, y - dy) * kgoal) >> 16);
 }
 
-// eta = clamp(floor(2^26 / max(delta, 1)), 1, 65535).
+// eta = clamp(floor(2^26 / max(delta, 1)), 1, 65535).  On (1024, 2^26] the
+// quotient is below 2^16, so a single-precision reciprocal (within one ulp of
+// the rounded divisor) puts the estimate within 0.02 of it, and one step each
+// way from the exact remainder gives the floor.  Divisors above 2^26 give 1,
+// as 2^26 does.
 __device__ __forceinline__ uint32_t eta_of(int64_t delta)
 {
-    if (delta >= (int64_t(1) << 26)) return 1;
-    if (delta <= 1024) return 65535;
-    return (1u << 26) / (uint32_t)delta;
+    const uint32_t d = delta < 1025 ? 1025u : delta > (int64_t(1) << 26) ? (1u << 26) : (uint32_t)delta;
+    uint32_t q = (uint32_t)(__builtin_amdgcn_rcpf((float)d) * 67108864.0f);
+    const int32_t r = (int32_t)((1u << 26) - q * d);
+    q = r < 0 ? q - 1 : (r >= (int32_t)d ? q + 1 : q);
+    return delta <= 1024 ? 65535u : q;
 }
 
 __device__ __forceinline__ uint64_t ipow_u64(uint64_t b, uint32_t e)
