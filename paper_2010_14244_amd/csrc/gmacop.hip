@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -1774,6 +1775,7 @@ struct gmacop_graph {
     uint32_t max_city_nodes = 0;
     std::vector<uint8_t> city_class_dev;   // host copy of inst_fits
     std::vector<uint32_t> inst_eoff;   // host: first road of each city
+    std::vector<uint64_t> inst_span2;  // host: squared diagonal of each city's bounding box
     uint16_t *speed = nullptr, *green = nullptr;
     int32_t *x = nullptr, *y = nullptr;
     // per-call state (device)
@@ -2191,6 +2193,16 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     pl.lds_apb = std::max<uint32_t>(1, std::min<uint32_t>(p->ants, 512 / pl.lds_lanes));
     pl.lds_bpv = (p->ants + pl.lds_apb - 1) / pl.lds_apb;
     const size_t t3 = (size_t)max_lds - kStaticLds, t2 = t3 / 2, t1 = t3 / 4;   // static block aggregates aside
+    // the LDS walkers keep each node's goal term in 32 bits: a city whose
+    // largest possible term (its bounding-box diagonal at this vmax) does not
+    // fit goes to the global walker, which keeps 64
+    const uint64_t kgoal = p->vmax_kmh ? (360ull << 16) / p->vmax_kmh : 0;
+    auto goal_fits = [&](uint32_t i) {
+        const uint64_t x = g->inst_span2[i];
+        uint64_t r = (uint64_t)std::sqrt((double)x);
+        while (r * r < x) ++r;   // ceil(sqrt(x)) <= 2^31.5: no overflow
+        return ((r * kgoal) >> 16) <= 0xFFFFFFFFull;
+    };
     uint32_t glb_nodes = 0;
     for (uint32_t i = 0; i < g->n_inst; ++i) {
         const uint32_t nc = g->inst_off[i + 1] - g->inst_off[i];
@@ -2206,7 +2218,7 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
         auto tier = [&](size_t need) -> uint8_t { return need <= t1 ? 1 : need <= t2 ? 2 : need <= t3 ? 3 : 0; };
         uint8_t c = 0;
         size_t need = 0;
-        if (!force_global && ec > 0) {
+        if (!force_global && ec > 0 && goal_fits(i)) {
             if (road_ok && ec < 65536 && (c = tier(need_r)) != 0) {
                 need = need_r;
             } else if ((c = tier(need_n)) != 0) {
@@ -2289,6 +2301,12 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
     for (uint32_t i = 0; i < g->n_inst; ++i) {
         g->inst_eoff[i] = d->row_ptr[g->inst_off[i]];
         g->max_city_nodes = std::max(g->max_city_nodes, g->inst_off[i + 1] - g->inst_off[i]);
+        int64_t x0 = INT64_MAX, x1 = INT64_MIN, y0 = INT64_MAX, y1 = INT64_MIN;
+        for (uint32_t u = g->inst_off[i]; u < g->inst_off[i + 1]; ++u) {
+            x0 = std::min<int64_t>(x0, d->x_dm[u]); x1 = std::max<int64_t>(x1, d->x_dm[u]);
+            y0 = std::min<int64_t>(y0, d->y_dm[u]); y1 = std::max<int64_t>(y1, d->y_dm[u]);
+        }
+        g->inst_span2.push_back((uint64_t)((x1 - x0) * (x1 - x0)) + (uint64_t)((y1 - y0) * (y1 - y0)));
         for (uint32_t u = g->inst_off[i]; u < g->inst_off[i + 1]; ++u) {
             node_lo[u] = g->inst_off[i];
             node_inst[u] = i;

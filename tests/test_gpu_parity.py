@@ -95,6 +95,67 @@ def test_planar_small_lds_degree5():
     check("planar3000", g, V, p)
 
 
+def _hub_far_graph(rng, n=48, hub=32):
+    """Node 0 has out-degree 32 and node n-1 in-degree 32 (the widest walker
+    template); coordinates spread to the validated limit |x|, |y| < 2^30, with
+    a few nodes clustered, so squared distances pass 2^44 and goal terms 2^32
+    at low vmax; road lengths from 1 dm to 3e6 dm put eta at both clamps and
+    give negative deltas (roads shorter than the straight line)."""
+    tails = [0] * hub + list(range(1, hub + 1))
+    heads = list(range(1, hub + 1)) + [n - 1] * hub
+    seen = set(zip(tails, heads))
+    for u in range(1, n):
+        for h in rng.choice(n - 1, size=4, replace=False):
+            h = int(h)
+            if h != u and h != 0 and (u, h) not in seen:
+                seen.add((u, h))
+                tails.append(u)
+                heads.append(h)
+    m = len(tails)
+    lim = 2 ** 30 - 1
+    x = rng.integers(-lim, lim + 1, n)
+    y = rng.integers(-lim, lim + 1, n)
+    x[36:44] = rng.integers(-40, 40, 8)    # a cluster: short roads, eta at 65535
+    y[36:44] = rng.integers(-40, 40, 8)
+    x[:2] = [-lim, lim]
+    y[:2] = [lim, -lim]
+    ln = np.where(rng.random(m) < 0.25, rng.integers(1, 100, m), rng.integers(1000, 3_000_000, m))
+    return from_edges(n, tails, heads, len_dm=ln, speed_kmh=rng.integers(5, 131, m),
+                      green_pm=rng.integers(0, 1001, m), cycle_ms=rng.integers(0, 120_000, n),
+                      x_dm=x, y_dm=y, base_load=rng.integers(0, 12, m))
+
+
+@pytest.mark.parametrize("kernel,lanes,variant", [
+    ("", 4, ""), ("lds", 1, ""), ("lds", 8, "node"), ("global", 4, ""), ("global", 1, ""), ("legacy", 1, "")])
+def test_high_degree_and_far_coordinates(monkeypatch, kernel, lanes, variant):
+    """Out- and in-degree 32, coordinates at the validated limit: the goal
+    term's far-distance root, eta's clamps, and (at vmax 20) goal terms
+    above 2^32, which send the city to the global walker; a packed pair of
+    a near city and a far one mixes walkers in one iteration."""
+    monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
+    monkeypatch.setenv("GMACOP_WALK_LANES", str(lanes))
+    monkeypatch.setenv("GMACOP_GLB_LANES", str(lanes))
+    monkeypatch.setenv("GMACOP_LDS_VARIANT", variant)
+    rng = np.random.default_rng(31)
+    g = _hub_far_graph(rng)
+    assert g.out_degree().max() == 32
+    V = Vehicles(qid=np.arange(40, dtype=np.uint32),
+                 src=np.concatenate([np.zeros(8, np.uint32), rng.integers(0, g.n, 32).astype(np.uint32)]),
+                 dst=np.concatenate([np.full(8, g.n - 1, np.uint32), rng.integers(0, g.n, 32).astype(np.uint32)]))
+    V = Vehicles(qid=V.qid, src=V.src, dst=np.where(V.dst == V.src, (V.src + 1) % g.n, V.dst).astype(np.uint32))
+    for vmax in (0, 400, 20):
+        p = default_params(ants=16, iterations=4, max_steps=40, vmax_kmh=vmax)
+        check(f"hub_far_{kernel or 'plan'}_L{lanes}{variant}_vmax{vmax}", g, V, p)
+    near = grid_graph(4, 5, rng)
+    packed = pack_graphs([near, g])
+    off = int(packed.inst_node_off[1])
+    vn = random_od(near.n, 10, rng)
+    Vp = Vehicles(qid=np.arange(20, dtype=np.uint32), src=np.concatenate([vn.src, off + V.src[:10]]).astype(np.uint32),
+                  dst=np.concatenate([vn.dst, off + V.dst[:10]]).astype(np.uint32))
+    check(f"hub_far_packed_{kernel or 'plan'}_L{lanes}{variant}", packed, Vp,
+          default_params(ants=16, iterations=3, max_steps=40, vmax_kmh=20))
+
+
 def test_parameter_variants():
     w = grid32(vehicles=16, ants=8, iterations=5)
     g, V = w.graph, w.vehicles
