@@ -319,30 +319,63 @@ struct CostArgs {
 // approach whose queue exceeds Th_max.  Road cost = congestion-scaled travel
 // time (t0 while load <= theta, else floor(t0 * load / theta)) + the fixed
 // wait unless the approach has green; capped at 2^31.
+__device__ __forceinline__ uint64_t approach_key(uint32_t L, uint32_t e)
+{
+    return L ? (((uint64_t)L << 32) | (0xFFFFFFFFu - e)) : 0;
+}
+
+__device__ __forceinline__ void store_cost(const CostArgs &a, uint32_t e, uint32_t L, uint32_t t0, uint32_t wf,
+                                           bool green)
+{
+    const uint64_t travel = L <= a.theta ? t0 : (uint64_t)t0 * L / a.theta;
+    uint64_t c = travel + (green ? 0u : wf);
+    c = c > kRoadCostCap ? kRoadCostCap : c;
+    a.cost[e] = (uint32_t)c;
+    if (a.mir) a.mir[(size_t)e * 8 + 4] = (uint32_t)c;
+}
+
+// One thread per intersection.  The first kCostBatch approaches are read
+// with all their loads in flight at once (road ids, then loads, base times
+// and waits), so a node of ordinary degree costs three memory round trips;
+// approaches beyond them are read one by one.
+constexpr uint32_t kCostBatch = 8;
 __global__ void k_cost(CostArgs a)
 {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= a.n) return;
     const uint32_t rb = a.rev_ptr[v], re = a.rev_ptr[v + 1];
     const bool signal = a.cycle[v] != 0;
+    uint32_t e[kCostBatch], L[kCostBatch], t0[kCostBatch], wf[kCostBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kCostBatch; ++u) e[u] = rb + u < re ? a.rev_edge[rb + u] : 0u;
+#pragma unroll
+    for (uint32_t u = 0; u < kCostBatch; ++u) {
+        L[u] = t0[u] = wf[u] = 0;
+        if (rb + u < re) {
+            L[u] = a.load[e[u]];
+            t0[u] = a.t0[e[u]];
+            wf[u] = a.wf[e[u]];
+        }
+    }
     uint64_t best = 0;
-    for (uint32_t i = rb; i < re; ++i) {
-        const uint32_t e = a.rev_edge[i];
-        const uint32_t L = a.load[e];
-        const uint64_t key = L ? (((uint64_t)L << 32) | (0xFFFFFFFFu - e)) : 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kCostBatch; ++u) {
+        const uint64_t key = rb + u < re ? approach_key(L[u], e[u]) : 0;
         best = key > best ? key : best;
     }
-    for (uint32_t i = rb; i < re; ++i) {
-        const uint32_t e = a.rev_edge[i];
-        const uint32_t L = a.load[e];
-        const uint64_t key = L ? (((uint64_t)L << 32) | (0xFFFFFFFFu - e)) : 0;
-        const bool green = signal && L && (L > a.th_max || key == best);
-        const uint32_t t0 = a.t0[e];
-        const uint64_t travel = L <= a.theta ? t0 : (uint64_t)t0 * L / a.theta;
-        uint64_t c = travel + (green ? 0u : a.wf[e]);
-        c = c > kRoadCostCap ? kRoadCostCap : c;
-        a.cost[e] = (uint32_t)c;
-        if (a.mir) a.mir[(size_t)e * 8 + 4] = (uint32_t)c;
+    for (uint32_t i = rb + kCostBatch; i < re; ++i) {
+        const uint32_t ei = a.rev_edge[i];
+        const uint64_t key = approach_key(a.load[ei], ei);
+        best = key > best ? key : best;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kCostBatch; ++u)
+        if (rb + u < re)
+            store_cost(a, e[u], L[u], t0[u], wf[u],
+                       signal && L[u] && (L[u] > a.th_max || approach_key(L[u], e[u]) == best));
+    for (uint32_t i = rb + kCostBatch; i < re; ++i) {
+        const uint32_t ei = a.rev_edge[i], Li = a.load[ei];
+        store_cost(a, ei, Li, a.t0[ei], a.wf[ei], signal && Li && (Li > a.th_max || approach_key(Li, ei) == best));
     }
 }
 
