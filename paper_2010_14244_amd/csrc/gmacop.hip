@@ -2203,9 +2203,11 @@ uint32_t lanes_or(uint32_t L, uint32_t dflt) { return (L == 1 || L == 2 || L == 
 // not charged the largest city's LDS: k_walk_ldsr (visited state per road,
 // classes 1..3) where its layout fits, else k_walk_lds (visited state per
 // node, classes 4..6); larger cities go to k_walk_glb.  GMACOP_WALK_KERNEL
-// (lds | global | legacy), GMACOP_LDS_VARIANT (node: k_walk_lds only),
-// GMACOP_WALK_LANES, GMACOP_GLB_LANES (1, 2, 4, 8) and GMACOP_BLOOM_LOG2
-// (8..16) override the choices for tuning; results do not depend on them.
+// (lds: LDS walkers wherever a city fits, whatever the occupancy | global |
+// legacy), GMACOP_LDS_VARIANT (node: k_walk_lds only), GMACOP_LDS_MAX_TIER
+// (1..3), GMACOP_WALK_LANES, GMACOP_GLB_LANES (1, 2, 4, 8) and
+// GMACOP_BLOOM_LOG2 (8..16) override the choices for tuning; results do not
+// depend on them.
 WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
 {
     WalkPlan pl;
@@ -2236,6 +2238,13 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
         while (r * r < x) ++r;   // ceil(sqrt(x)) <= 2^31.5: no overflow
         return ((r * kgoal) >> 16) <= 0xFFFFFFFFull;
     };
+    // A tier holds 4, 2 or 1 blocks per CU.  A city gets an LDS tier only if
+    // that keeps at least one wave per SIMD (blocks x waves per block >= 4);
+    // otherwise most of the CU would idle, and the persistent global walker,
+    // which fills every CU whatever the city, serves it instead.
+    const uint32_t wpb = (pl.lds_apb * pl.lds_lanes + kWave - 1) / kWave;
+    const bool force_lds = kind && strcmp(kind, "lds") == 0;
+    const uint32_t max_tier = std::min(3u, std::max(1u, env_u32("GMACOP_LDS_MAX_TIER", 3)));
     uint32_t glb_nodes = 0;
     for (uint32_t i = 0; i < g->n_inst; ++i) {
         const uint32_t nc = g->inst_off[i + 1] - g->inst_off[i];
@@ -2248,7 +2257,10 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
         const size_t aux_n = std::max<size_t>(nc, (size_t)(((nc + 31) / 32) | 1u) * pl.lds_apb);
         const size_t need_n = (size_t)ec * 16 + (size_t)((ec + 1) & ~1u) * 4 + ((aux_n + 1) & ~(size_t)1) * 4 +
                               lds_group_bytes(pl.lds_apb);
-        auto tier = [&](size_t need) -> uint8_t { return need <= t1 ? 1 : need <= t2 ? 2 : need <= t3 ? 3 : 0; };
+        auto tier = [&](size_t need) -> uint8_t {
+            const uint8_t t = need <= t1 ? 1 : need <= t2 ? 2 : need <= t3 ? 3 : 0;
+            return t && t <= max_tier && ((4u >> (t - 1)) * wpb >= 4 || force_lds) ? t : 0;
+        };
         uint8_t c = 0;
         size_t need = 0;
         if (!force_global && ec > 0 && goal_fits(i)) {

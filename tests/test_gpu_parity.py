@@ -67,14 +67,24 @@ def test_grid8_workload():
     check(w.name, w.graph, w.vehicles, w.params)
 
 
-def test_grid32_reduced():
+# With few ants per vehicle a city that needs a whole CU's LDS would leave most
+# of the CU idle, so the default plan sends it to the global walker; "lds"
+# forces the LDS walkers for the same case.
+PLAN_KINDS = pytest.mark.parametrize("kernel", ["", "lds"])
+
+
+@PLAN_KINDS
+def test_grid32_reduced(monkeypatch, kernel):
+    monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
     w = grid32(vehicles=48, ants=32, iterations=12)
-    check(w.name, w.graph, w.vehicles, w.params)
+    check(f"{w.name}_{kernel or 'plan'}", w.graph, w.vehicles, w.params)
 
 
-def test_grid32_frozen_loads():
+@PLAN_KINDS
+def test_grid32_frozen_loads(monkeypatch, kernel):
+    monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
     w = grid32(vehicles=32, ants=16, iterations=8)
-    check(w.name + "_frozen", w.graph, w.vehicles, dict(w.params, flags=gmacop.NO_LOAD_UPDATE))
+    check(f"{w.name}_frozen_{kernel or 'plan'}", w.graph, w.vehicles, dict(w.params, flags=gmacop.NO_LOAD_UPDATE))
 
 
 def test_planar_global_bitset_and_degree5():
@@ -87,12 +97,14 @@ def test_planar_global_bitset_and_degree5():
     check("planar6000", g, V, p)
 
 
-def test_planar_small_lds_degree5():
+@PLAN_KINDS
+def test_planar_small_lds_degree5(monkeypatch, kernel):
+    monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
     rng = np.random.default_rng(22)
     g = planar_graph(3000, rng)
     V = random_od(g.n, 20, rng)
     p = default_params(ants=16, iterations=6, max_steps=300, vmax_kmh=70)
-    check("planar3000", g, V, p)
+    check(f"planar3000_{kernel or 'plan'}", g, V, p)
 
 
 def _hub_far_graph(rng, n=48, hub=32):
@@ -156,7 +168,9 @@ def test_high_degree_and_far_coordinates(monkeypatch, kernel, lanes, variant):
           default_params(ants=16, iterations=3, max_steps=40, vmax_kmh=20))
 
 
-def test_parameter_variants():
+@PLAN_KINDS
+def test_parameter_variants(monkeypatch, kernel):
+    monkeypatch.setenv("GMACOP_WALK_KERNEL", kernel)
     w = grid32(vehicles=16, ants=8, iterations=5)
     g, V = w.graph, w.vehicles
     for kw in (dict(alpha=0, beta=0), dict(alpha=2, beta=1, tau_max_q16=2 ** 20),
@@ -164,7 +178,7 @@ def test_parameter_variants():
                dict(rho_q16=0, q_deposit=0), dict(rho_q16=65536), dict(vmax_kmh=0, max_steps=200),
                dict(theta=1, th_max=0), dict(seed=0xDEADBEEF12345678, iter_offset=77), dict(max_steps=1),
                dict(ants=1), dict(t_max_ms=0)):
-        check(f"grid32_{kw}", g, V, dict(w.params, **kw))
+        check(f"grid32_{kernel or 'plan'}_{kw}", g, V, dict(w.params, **kw))
 
 
 def test_edge_cases():
