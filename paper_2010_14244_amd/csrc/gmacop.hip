@@ -1030,21 +1030,16 @@ __global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
     uint32_t *s_grp = s_aux + ((max(n_cnt, nws * a.apb) + 1) & ~1u);   // per-group scratch (lds_block_finish)
 
     {
-        const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
-        for (uint32_t i = tid; i < n_cnt; i += nthr)
-            s_aux[i] = (uint32_t)goal_ms(a.x[n_lo + i], a.y[n_lo + i], dx, dy, a.kgoal);
-    }
-    __syncthreads();
-    {
-        // four roads per thread at a time, their loads (all independent) ahead of the arithmetic
+        // the roads in batches of eight per thread, their loads (all independent) ahead of the arithmetic;
+        // the first batch's loads are issued before the goal terms are computed, so they overlap
         const bool a1b2 = a.alpha == 1 && a.beta == 2;
         const PherRead tau = pher_at(a.pher, v, a.t_local);
         const uint32_t dst_l = q.dst - n_lo;
-        for (uint32_t b0 = tid; b0 < e_cnt; b0 += 4 * nthr) {
-            uint4 st[4];
-            uint32_t c[4], t[4];
+        uint4 st[8];
+        uint32_t c[8], t[8];
+        auto load_batch = [&](uint32_t b0) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const uint32_t le = b0 + u * nthr;
                 if (le < e_cnt) {
                     st[u] = a.rvs[e_lo + le];
@@ -1052,8 +1047,10 @@ __global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
                     t[u] = tau(e_lo + le);
                 }
             }
+        };
+        auto stage_batch = [&](uint32_t b0) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const uint32_t le = b0 + u * nthr;
                 if (le < e_cnt) {
                     const uint32_t xl = st[u].z & 0xFFFFu, tl = st[u].z >> 16;
@@ -1066,6 +1063,16 @@ __global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
                     s_rev[le] = st[u].w;
                 }
             }
+        };
+        load_batch(tid);
+        const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
+        for (uint32_t i = tid; i < n_cnt; i += nthr)
+            s_aux[i] = (uint32_t)goal_ms(a.x[n_lo + i], a.y[n_lo + i], dx, dy, a.kgoal);
+        __syncthreads();
+        stage_batch(tid);
+        for (uint32_t b0 = tid + 8 * nthr; b0 < e_cnt; b0 += 8 * nthr) {
+            load_batch(b0);
+            stage_batch(b0);
         }
     }
     __syncthreads();
