@@ -685,20 +685,30 @@ __device__ __forceinline__ void lds_block_finish(const LdsWalkArgs &a, uint64_t 
             if (s_off[mid] <= i) g = mid; else hi = mid;
         }
         const size_t ant0 = (size_t)v * a.ants + k0;
+        // the current group's first entry, the next group's, and its deposit stay in registers: LDS is read
+        // again only where the slice crosses into the next ant's entries
+        uint32_t cur = s_off[g], nxt = g + 1 < apb ? s_off[g + 1] : total;
+        uint64_t dp = s_dp[g];
         while (i < iend) {   // eight path reads in flight, then their LDS adds
-            uint32_t e8[8], g8[8];
+            uint32_t e8[8];
+            uint64_t d8[8];
             const uint32_t n8 = min(8u, iend - i);
 #pragma unroll
             for (uint32_t u = 0; u < 8; ++u) {
                 if (u < n8) {
-                    while (g + 1 < apb && i + u >= s_off[g + 1]) ++g;
-                    g8[u] = g;
-                    e8[u] = a.path[(size_t)(i + u - s_off[g]) * NA + ant0 + g];
+                    while (i + u >= nxt) {   // never past the last group: i + u < total
+                        ++g;
+                        cur = nxt;
+                        nxt = g + 1 < apb ? s_off[g + 1] : total;
+                        dp = s_dp[g];
+                    }
+                    d8[u] = dp;
+                    e8[u] = a.path[(size_t)(i + u - cur) * NA + ant0 + g];
                 }
             }
 #pragma unroll
             for (uint32_t u = 0; u < 8; ++u)
-                if (u < n8) atomicAdd((unsigned long long *)&acc[e8[u] - e_lo], (unsigned long long)s_dp[g8[u]]);
+                if (u < n8) atomicAdd((unsigned long long *)&acc[e8[u] - e_lo], (unsigned long long)d8[u]);
             i += n8;
         }
     }
