@@ -1403,18 +1403,18 @@ __global__ __launch_bounds__(256) void k_walk_glb(GlbWalkArgs a)
         const uint32_t cs = w.cs > kPathCostCap ? kPathCostCap : (uint32_t)w.cs;
         if (w.ok) {
             const uint64_t dpos = a.q_deposit / cs;
-            if (dpos) {
-                uint32_t i = j;
-                for (; i + 3 * L < w.s; i += 4 * L) {
-                    const uint32_t e0 = a.path[(size_t)i * NA + ant], e1 = a.path[(size_t)(i + L) * NA + ant];
-                    const uint32_t e2 = a.path[(size_t)(i + 2 * L) * NA + ant];
-                    const uint32_t e3 = a.path[(size_t)(i + 3 * L) * NA + ant];
-                    a.depv.add(w.v, e0, dpos);
-                    a.depv.add(w.v, e1, dpos);
-                    a.depv.add(w.v, e2, dpos);
-                    a.depv.add(w.v, e3, dpos);
+            if (dpos) {   // sixteen path reads per lane in flight (the rest of the wave waits for this)
+                for (uint32_t i0 = j; i0 < w.s; i0 += 16 * L) {
+                    uint32_t e[16];
+#pragma unroll
+                    for (uint32_t u = 0; u < 16; ++u) {
+                        const uint32_t i = i0 + u * L;
+                        e[u] = i < w.s ? a.path[(size_t)i * NA + ant] : 0u;
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < 16; ++u)
+                        if (i0 + u * L < w.s) a.depv.add(w.v, e[u], dpos);
                 }
-                for (; i < w.s; i += L) a.depv.add(w.v, a.path[(size_t)i * NA + ant], dpos);
             }
             if (j == 0)
                 atomicMin((unsigned long long *)&a.iter_key[w.v], (unsigned long long)(((uint64_t)cs << 32) | w.k));
