@@ -48,7 +48,7 @@ def serve(server: "gmacop.Server", od: np.ndarray, arrivals: np.ndarray, *, warm
             if nxt < n:
                 time.sleep(max(0.0, min(arrivals[nxt] - now, 0.01)))
             continue
-        k = min(nxt - head, server.slots - in_flight)
+        k = max(0, min(nxt - head, server.slots - in_flight))
         admitted, done = server.step(od[head:head + k], stream)
         head += admitted
         in_flight += admitted - len(done)
