@@ -2516,6 +2516,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         steps = out->steps_total;
     } else if (nq) {
         HIP_TRY(hipMemcpyAsync(g->od, q, sizeof(gmacop_od) * nq, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));   // the caller's queries are read before any later error returns
         od = g->od;
     }
 
@@ -2822,6 +2823,11 @@ struct gmacop_server {
     // host mirror
     std::vector<uint32_t> free_list, t_host, qid_host, gen_host;
     std::vector<uint8_t> active;
+    // host sources of a step's asynchronous copies: they live as long as the router, so a copy
+    // still in flight (the step synchronises only at its end, or not at all on an error) never
+    // reads freed memory
+    std::vector<uint32_t> adm_slots_host, adm_gen_host, fin_host;
+    std::vector<gmacop_od> adm_od_host;
     uint64_t ticks = 0, admitted = 0, completed = 0;
 
     ~gmacop_server()
@@ -2950,6 +2956,10 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
     for (uint32_t i = 0; i < NS; ++i) s->free_list[i] = NS - 1 - i;   // pop_back hands out slot 0 first
     s->t_host.assign(NS, 0);
     s->qid_host.assign(NS, 0);
+    s->adm_slots_host.reserve(NS);   // never reallocated: a pending copy keeps a valid source
+    s->adm_gen_host.reserve(NS);
+    s->fin_host.reserve(NS);
+    s->adm_od_host.reserve(NS);
     s->gen_host.assign(NS, 0);
     s->active.assign(NS, 0);
     *out = s;
@@ -3000,7 +3010,9 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
 
     // 1. admissions
     if (take) {
-        std::vector<uint32_t> sl(take), gens(take);
+        std::vector<uint32_t> &sl = s->adm_slots_host, &gens = s->adm_gen_host;
+        sl.resize(take);
+        gens.resize(take);
         for (uint32_t i = 0; i < take; ++i) {
             const uint32_t x = s->free_list.back();
             s->free_list.pop_back();
@@ -3018,7 +3030,8 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
         }
         HIP_TRY(hipMemcpyAsync(s->adm_slots, sl.data(), 4 * take, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(s->adm_gen, gens.data(), 4 * take, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(s->adm_od, admit, sizeof(gmacop_od) * take, hipMemcpyHostToDevice, st));
+        s->adm_od_host.assign(admit, admit + take);   // the caller's array may go before the copy runs
+        HIP_TRY(hipMemcpyAsync(s->adm_od, s->adm_od_host.data(), sizeof(gmacop_od) * take, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_admit, dim3(blocks_for(take, 256)), dim3(256), 0, st, (const uint32_t *)s->adm_slots,
                            (const gmacop_od *)s->adm_od, (const uint32_t *)s->adm_gen, take, s->slot_od, s->slot_t,
                            s->slot_gen, s->best_len, s->best_cost, s->iter_key);
@@ -3088,7 +3101,8 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
     (void)NAll;
 
     // 3. finished queries
-    std::vector<uint32_t> fin;
+    std::vector<uint32_t> &fin = s->fin_host;
+    fin.clear();
     for (uint32_t i = 0; i < NS; ++i)
         if (s->active[i]) {
             s->t_host[i] += 1;
