@@ -207,7 +207,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(sharding across GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "serve":
