@@ -206,7 +206,7 @@ def main():
                     help="skip the plain-per-query vs batched comparison (independent mode)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 

@@ -35,7 +35,7 @@ extern "C" {
 #define GMACOP_E_RANGE      -2   /* parameters exceed the exact 64-bit integer range */
 #define GMACOP_E_NOMEM      -3   /* device allocation failed                        */
 #define GMACOP_E_DEVICE     -4   /* HIP runtime error                               */
-#define GMACOP_E_UNSUPPORTED -5  /* valid input outside what this build handles      */
+#define GMACOP_E_UNSUPPORTED -5  /* valid input outside what the library handles    */
 
 /* gmacop_params.mode */
 #define GMACOP_MODE_SHARED      0u  /* all vehicles share pheromone and road loads      */
