@@ -1,7 +1,7 @@
 """Host logic of the continuous-batching loop (paper_2010_14244_amd/serve.py)
 against a stand-in server: first-come-first-served admission, no batch
 larger than the free slots, every query completed once, latency counted
-from arrival.  No GPU."""
+from arrival; and bench.py's one-GPU contract.  No GPU."""
 import numpy as np
 
 from paper_2010_14244_amd import serve
@@ -73,3 +73,16 @@ def test_poisson_arrivals_rate():
     gaps = np.diff(arr)
     assert abs(gaps.mean() * 5000.0 - 1.0) < 0.01
     assert abs(gaps.std() / gaps.mean() - 1.0) < 0.02             # exponential: cv = 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for more exits with a message
+    before anything touches a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
