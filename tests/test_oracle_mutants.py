@@ -29,6 +29,22 @@ MUTANTS = {
                            "(uint64_t)tau * (65535u - p->rho_q16) / 65536u"),
     "best_tie": ("(uint32_t)(iter_key >> 32) < *best_cost", "(uint32_t)(iter_key >> 32) <= *best_cost"),
     "load_increment": ("load[path_edges[(size_t)v * S + i]] += 1;", "load[path_edges[(size_t)v * S + i]] += 2;"),
+    "counter_swap": ("const uint32_t ctr[4] = {qid, ant, p->iter_offset + iter, step};",
+                     "const uint32_t ctr[4] = {ant, qid, p->iter_offset + iter, step};"),
+    "word_order": ("return ((uint64_t)x[1] << 32) | x[0];", "return ((uint64_t)x[0] << 32) | x[1];"),
+    "apply_after_load_update": (
+        """            for (uint32_t e = 0; e < m; ++e) tau[e] = orc_apply_tau(p, tau[e], dep[e], load[e]);
+            if (!(p->flags & ORC_FLAG_NO_LOAD_UPDATE)) {
+                for (uint32_t e = 0; e < m; ++e) load[e] = g->base_load[e];
+                for (uint32_t v = 0; v < nv; ++v)
+                    for (uint32_t i = 0; i < path_len[v]; ++i) load[path_edges[(size_t)v * S + i]] += 1;
+            }""",
+        """            if (!(p->flags & ORC_FLAG_NO_LOAD_UPDATE)) {
+                for (uint32_t e = 0; e < m; ++e) load[e] = g->base_load[e];
+                for (uint32_t v = 0; v < nv; ++v)
+                    for (uint32_t i = 0; i < path_len[v]; ++i) load[path_edges[(size_t)v * S + i]] += 1;
+            }
+            for (uint32_t e = 0; e < m; ++e) tau[e] = orc_apply_tau(p, tau[e], dep[e], load[e]);"""),
 }
 
 

@@ -593,3 +593,111 @@ def test_equal_cost_route_found_later_does_not_replace_best(orc):
     first_edge = 0 if _draw_top_bit(orc, p["seed"], qid, 0, 0, 0) == 0 else 1
     assert res["path_edges"][0, :2].tolist() == [first_edge, 2 + first_edge]
     assert res["cost_ms"][0] == 14400
+
+
+# ---------------------------------------------------------------------------
+# the random-number reading: counter layout and output word order
+# ---------------------------------------------------------------------------
+
+def _star_chain(stages):
+    """Hubs 0, 4, 8, ..., 4*stages.  Hub 4k has three roads, to 4k+1, 4k+2
+    and 4k+3, of free-flow time 2^20, 2^21 and 2^22 ms (lengths 2^17, 2^18,
+    2^19 dm at 45 km/h); each of those nodes has one road on to hub 4k+4.
+    No signals, empty roads."""
+    tails, heads, lens = [], [], []
+    for k in range(stages):
+        h = 4 * k
+        for b, ln in zip((1, 2, 3), (2 ** 17, 2 ** 18, 2 ** 19)):
+            tails.append(h)
+            heads.append(h + b)
+            lens.append(ln)
+        for b in (1, 2, 3):
+            tails.append(h + b)
+            heads.append(h + 4)
+            lens.append(1000)
+    return from_edges(4 * stages + 1, tails, heads, len_dm=lens, speed_kmh=45)
+
+
+def test_walk_draws_follow_the_documented_counter_and_word_order(orc, rocrand_ref):
+    """Known answers for the walk's choices.  At hub 4k (step s = 2k) the
+    weights are tau * eta^2 with eta = 2^26 / cost = 64, 32, 16.  The draw of
+    step s of ant `ant` of vehicle `qid` in iteration `it` is Philox4x32-10
+    with key (seed low word, seed high word) and counter (qid, ant,
+    iter_offset + it, s), read as r = x1 * 2^32 + x0; the road taken is the
+    first whose inclusive prefix of weights exceeds floor(r * T / 2^64).  The
+    draws come from rocRAND's engine, the bucket from exact integer
+    arithmetic here, so a different counter layout or word order fails."""
+    stages = 6
+    g = _star_chain(stages)
+    seed = 0x0123456789ABCDEF
+    tau = np.full(g.m, 0x10000, np.uint32)
+    w = [0x10000 * 64 ** 2, 0x10000 * 32 ** 2, 0x10000 * 16 ** 2]
+    T = sum(w)
+    cases = [(7, 3, 0, 0), (3, 7, 0, 0), (1000, 1, 5, 0), (12, 40, 2, 9), (0, 0, 0, 0), (0xFFFFFFFE, 63, 1, 4000),
+             (99, 99, 11, 1), (2 ** 20 + 5, 5, 0, 123)]
+    args, keys = [], []
+    for qid, ant, it, off in cases:
+        for k in range(stages):
+            args += [hex(seed & 0xFFFFFFFF), hex(seed >> 32), hex(qid), hex(ant), hex(off + it), hex(2 * k)]
+            keys.append((qid, ant, it, off, k))
+    out = subprocess.check_output([rocrand_ref] + args, text=True).split("\n")
+    expect = {}
+    for key, line in zip(keys, out):
+        x = [int(v, 16) for v in line.split()]
+        r = (x[1] << 32) | x[0]
+        target = (r * T) >> 64
+        prefix, j = 0, None
+        for jj, wj in enumerate(w):
+            prefix += wj
+            if prefix > target:
+                j = jj
+                break
+        expect[key] = j
+    chosen = {0: 0, 1: 0, 2: 0}
+    for qid, ant, it, off in cases:
+        p = default_params(max_steps=2 * stages, vmax_kmh=0, seed=seed, iter_offset=off)
+        cost, _ = orc.cost_table(g, p, g.base_load)
+        assert cost[:3].tolist() == [2 ** 20, 2 ** 21, 2 ** 22]
+        ok, path, cs, sel = orc.walk(g, p, tau, cost, qid, 0, 4 * stages, ant, it)
+        assert ok and sel == 2 * stages
+        heads = g.col[path].tolist()
+        for k in range(stages):
+            j = heads[2 * k] - 4 * k - 1
+            assert j == expect[(qid, ant, it, off, k)], (qid, ant, it, off, k)
+            chosen[j] += 1
+    assert min(chosen.values()) > 0         # every bucket was exercised
+
+
+# ---------------------------------------------------------------------------
+# step order of an iteration: apply the pheromone before the load update
+# ---------------------------------------------------------------------------
+
+def test_pheromone_is_penalised_by_the_load_the_ants_saw(orc):
+    """Chain 0 -> 1 -> 2 with reverse roads (roads in CSR order: (0,1),
+    (1,0), (1,2), (2,1)), free-flow 7200 ms each, no signals, sensed load 4
+    on road (0,1), theta = 4, three ants, rho = 1/2, q = 65536 * 10^5, loads
+    updated from the best routes.
+
+    Iteration 0: loads (4,0,0,0), all roads cost 7200, the only route costs
+    14400, each ant deposits floor(q / 14400) = 455111, D = 1365333 on roads
+    0 and 2.  The apply uses the loads the ants saw: road 0 has load 4 <=
+    theta, so tau = 32768 + 1365333 = 1398101 on both roads.  Then the load
+    becomes (5,0,1,0).
+    Iteration 1: road 0 costs floor(7200 * 5 / 4) = 9000, the route 16200,
+    each ant deposits floor(q / 16200) = 404543, D = 1213629.  Road 0 is
+    congested: D' = floor(1213629 * 4 / 5) = 970903, tau = floor(1398101 / 2)
+    + 970903 = 1669953; road 2: 699050 + 1213629 = 1912679; reverse roads
+    16384.  16200 is not cheaper than 14400, so the best route keeps cost
+    14400 and the loads stay (5,0,1,0).  Applying after the load update would
+    penalise iteration 0's deposit on road 0 (1125034 instead of 1398101)."""
+    g = from_edges(3, [0, 1, 1, 2], [1, 0, 2, 1], len_dm=1000, base_load=[4, 0, 0, 0])
+    p = default_params(ants=3, iterations=1, max_steps=2, vmax_kmh=0, rho_q16=0x8000, q_deposit=65536 * 100000,
+                       theta=4)
+    one = orc.route(g, veh([0], [2], qid=[4]), p)
+    assert one["cost_ms"][0] == 14400
+    assert one["tau"].tolist() == [1398101, 32768, 1398101, 32768]
+    assert one["load"].tolist() == [5, 0, 1, 0]
+    two = orc.route(g, veh([0], [2], qid=[4]), dict(p, iterations=2))
+    assert two["cost_ms"][0] == 14400 and two["path_len"][0] == 2
+    assert two["tau"].tolist() == [1669953, 16384, 1912679, 16384]
+    assert two["load"].tolist() == [5, 0, 1, 0]
