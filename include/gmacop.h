@@ -204,7 +204,11 @@ int gmacop_server_info(const gmacop_server *s, uint32_t *slots, uint32_t *active
  * done_len[i] (0 = no route), done_cost[i] (0xFFFFFFFF = none) and the route
  * in done_paths[i * max_steps ...] (host buffers of done_cap entries; done_cap
  * must cover every query finishing in the step, at most the slot count);
- * *n_done returns their number.  Synchronous on hip_stream. */
+ * *n_done returns their number.  Synchronous on hip_stream.
+ * Argument errors (GMACOP_E_INVAL) are found before anything changes.  A step
+ * that fails after them (GMACOP_E_DEVICE, GMACOP_E_NOMEM) drops every query in
+ * flight and admits none (*n_admit and *n_done return 0): the router is empty
+ * afterwards and the caller resubmits what it still needs. */
 int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint32_t *n_admit, uint32_t *done_qid,
                        uint32_t *done_len, uint32_t *done_cost, uint32_t *done_paths, uint32_t done_cap,
                        uint32_t *n_done, void *hip_stream);

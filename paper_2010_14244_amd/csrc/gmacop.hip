@@ -1696,14 +1696,16 @@ __global__ void k_classify(const gmacop_od *od, uint32_t nq, uint32_t n, const u
 // ---- serving: slot admission, advance, result gather ----
 
 // Queries enter free slots: the slot's route starts empty at iteration 0
-// with a fresh pheromone generation.
+// with a fresh pheromone generation.  Slot ids at or above nslots are
+// ignored (the host never sends one; the guard keeps every write in range).
 __global__ void k_admit(const uint32_t *slots, const gmacop_od *ods, const uint32_t *gens, uint32_t n,
-                        gmacop_od *slot_od, uint32_t *slot_t, uint32_t *slot_gen, uint32_t *best_len,
-                        uint32_t *best_cost, uint64_t *iter_key)
+                        uint32_t nslots, gmacop_od *slot_od, uint32_t *slot_t, uint32_t *slot_gen,
+                        uint32_t *best_len, uint32_t *best_cost, uint64_t *iter_key)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t sl = slots[i];
+    if (sl >= nslots) return;
     slot_od[sl] = ods[i];
     slot_t[sl] = 0;
     slot_gen[sl] = gens[i];
@@ -1726,13 +1728,21 @@ __global__ void k_advance(uint32_t nslots, uint32_t n, uint32_t iterations, gmac
     if (t >= iterations) slot_od[sl] = gmacop_od{q.qid, 0xFFFFFFFFu, 0xFFFFFFFFu};
 }
 
-// Results of finished slots into contiguous buffers (one block per slot).
-__global__ void k_gather_done(const uint32_t *slots, uint32_t max_steps, const uint32_t *best_path,
+// Results of finished slots into contiguous buffers (one block per slot).  A
+// slot id at or above nslots yields "no route" (the host never sends one).
+__global__ void k_gather_done(const uint32_t *slots, uint32_t nslots, uint32_t max_steps, const uint32_t *best_path,
                               const uint32_t *best_len, const uint32_t *best_cost, uint32_t *out_path,
                               uint32_t *out_len, uint32_t *out_cost)
 {
     const uint32_t i = blockIdx.x, sl = slots[i];
-    const uint32_t len = best_len[sl];
+    if (sl >= nslots) {
+        if (threadIdx.x == 0) {
+            out_len[i] = 0;
+            out_cost[i] = kNoCost;
+        }
+        return;
+    }
+    const uint32_t len = min(best_len[sl], max_steps);
     for (uint32_t s = threadIdx.x; s < len; s += blockDim.x)
         out_path[(size_t)i * max_steps + s] = best_path[(size_t)sl * max_steps + s];
     if (threadIdx.x == 0) {
@@ -2828,6 +2838,7 @@ struct gmacop_server {
     // reads freed memory
     std::vector<uint32_t> adm_slots_host, adm_gen_host, fin_host;
     std::vector<gmacop_od> adm_od_host;
+    bool resync = false;               // a failed step emptied the router: rewrite the device slot table first
     uint64_t ticks = 0, admitted = 0, completed = 0;
 
     ~gmacop_server()
@@ -2975,33 +2986,37 @@ extern "C" int gmacop_server_info(const gmacop_server *s, uint32_t *slots, uint3
     return GMACOP_OK;
 }
 
-extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint32_t *n_admit, uint32_t *done_qid,
-                                  uint32_t *done_len, uint32_t *done_cost, uint32_t *done_paths, uint32_t done_cap,
-                                  uint32_t *n_done, void *hip_stream)
+namespace {
+
+// Empty the router after a step failed past its argument checks: every
+// query in flight is dropped, all slots return to the free list, and the
+// device slot table is rewritten as idle before the next admission.
+void server_drop_all(gmacop_server *s)
 {
-    if (!s || !n_admit || !n_done) return fail(GMACOP_E_INVAL, "server or counts are NULL");
-    if (*n_admit && !admit) return fail(GMACOP_E_INVAL, "admissions are NULL");
+    s->free_list.resize(s->slots);
+    for (uint32_t i = 0; i < s->slots; ++i) s->free_list[i] = s->slots - 1 - i;
+    std::fill(s->active.begin(), s->active.end(), (uint8_t)0);
+    std::fill(s->t_host.begin(), s->t_host.end(), 0u);
+    s->resync = true;
+}
+
+// Rewrite every slot of the device table as idle (after server_drop_all).
+int server_resync(gmacop_server *s, hipStream_t st)
+{
+    std::vector<gmacop_od> &idle = s->adm_od_host;   // lives as long as the router: a pending copy keeps its source
+    idle.assign(s->slots, gmacop_od{0, 0xFFFFFFFFu, 0xFFFFFFFFu});
+    HIP_TRY(hipMemcpyAsync(s->slot_od, idle.data(), sizeof(gmacop_od) * s->slots, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    s->resync = false;
+    return GMACOP_OK;
+}
+
+int server_step_impl(gmacop_server *s, const gmacop_od *admit, uint32_t take, uint32_t *done_qid, uint32_t *done_len,
+                     uint32_t *done_cost, uint32_t *done_paths, uint32_t *n_done, hipStream_t st)
+{
     gmacop_graph *g = s->g;
     const gmacop_params &p = s->p;
     const uint32_t A = p.ants, S = p.max_steps, NS = s->slots;
-    // queries finishing in this step: those admitted iterations-1 steps ago, plus the new ones if iterations == 1
-    uint32_t finishing = 0;
-    for (uint32_t i = 0; i < NS; ++i) finishing += s->active[i] && s->t_host[i] + 1 == p.iterations;
-    const uint32_t take = std::min<uint32_t>(*n_admit, (uint32_t)s->free_list.size());
-    if (finishing + (p.iterations == 1 ? take : 0) > done_cap)
-        return fail(GMACOP_E_INVAL, "done_cap %u below the %u queries finishing in this step", done_cap,
-                    finishing + (p.iterations == 1 ? take : 0));
-    if ((finishing || (p.iterations == 1 && take)) && (!done_qid || !done_len || !done_cost || !done_paths))
-        return fail(GMACOP_E_INVAL, "result buffers are NULL");
-    for (uint32_t i = 0; i < take; ++i) {
-        if (admit[i].qid == 0xFFFFFFFFu) return fail(GMACOP_E_INVAL, "admission %u uses the reserved qid", i);
-        if (admit[i].src >= g->n || admit[i].dst >= g->n || admit[i].src == admit[i].dst)
-            return fail(GMACOP_E_INVAL, "admission %u: invalid nodes", i);
-        if (instance_of(g, admit[i].src) != instance_of(g, admit[i].dst))
-            return fail(GMACOP_E_INVAL, "admission %u: src and dst in different cities", i);
-    }
-    HIP_TRY(hipSetDevice(g->device));
-    hipStream_t st = (hipStream_t)hip_stream;
     int rc;
     if (s->plan.city_class != g->city_class_dev) {
         HIP_TRY(hipMemcpy(g->inst_fits, s->plan.city_class.data(), g->n_inst, hipMemcpyHostToDevice));
@@ -3016,6 +3031,7 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
         for (uint32_t i = 0; i < take; ++i) {
             const uint32_t x = s->free_list.back();
             s->free_list.pop_back();
+            if (x >= NS || s->active[x]) return fail(GMACOP_E_DEVICE, "router slot list corrupt (slot %u)", x);
             sl[i] = x;
             uint32_t gnew = s->gen_host[x] + 1;
             if (gnew > kGenMask) {   // generation numbers would repeat: clear the slot's pheromone row
@@ -3033,11 +3049,11 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
         s->adm_od_host.assign(admit, admit + take);   // the caller's array may go before the copy runs
         HIP_TRY(hipMemcpyAsync(s->adm_od, s->adm_od_host.data(), sizeof(gmacop_od) * take, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_admit, dim3(blocks_for(take, 256)), dim3(256), 0, st, (const uint32_t *)s->adm_slots,
-                           (const gmacop_od *)s->adm_od, (const uint32_t *)s->adm_gen, take, s->slot_od, s->slot_t,
+                           (const gmacop_od *)s->adm_od, (const uint32_t *)s->adm_gen, take, NS, s->slot_od, s->slot_t,
                            s->slot_gen, s->best_len, s->best_cost, s->iter_key);
+        HIP_TRY(hipGetLastError());
         s->admitted += take;
     }
-    *n_admit = take;
 
     // 2. one iteration for every active slot
     const WalkPlan &plan = s->plan;
@@ -3049,7 +3065,6 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
     pv.m = g->m; pv.tau0 = p.tau0_q16; pv.rho = p.rho_q16; pv.tau_min = p.tau_min_q16;
     DepView dv{s->dep, s->touched, s->touched_n, g->m, s->tcap, 1u};
     const uint32_t kgoal = p.vmax_kmh ? (uint32_t)((360ull << 16) / p.vmax_kmh) : 0;
-    const uint32_t NAll = NS * A;
     hipLaunchKernelGGL(k_classify, dim3(blocks_for(NS, 256)), dim3(256), 0, st, (const gmacop_od *)s->slot_od, NS,
                        g->n, (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, s->vclass);
     if (plan.glb) {
@@ -3058,6 +3073,7 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
         hipLaunchKernelGGL(k_glb_prep, dim3(blocks_for(NS, 256)), dim3(256), 0, st, gla);
         hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, st, gla);
     }
+    HIP_TRY(hipGetLastError());
     if ((rc = kt.start(0, &tm))) return rc;
     {
         LdsWalkArgs la{};
@@ -3098,7 +3114,6 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
     hipLaunchKernelGGL(k_advance, dim3(blocks_for(NS, 256)), dim3(256), 0, st, NS, g->n, p.iterations, s->slot_od,
                        s->slot_t);
     HIP_TRY(hipGetLastError());
-    (void)NAll;
 
     // 3. finished queries
     std::vector<uint32_t> &fin = s->fin_host;
@@ -3111,7 +3126,7 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
     const uint32_t nf = (uint32_t)fin.size();
     if (nf) {
         HIP_TRY(hipMemcpyAsync(s->done_slots, fin.data(), 4 * nf, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_gather_done, dim3(nf), dim3(64), 0, st, (const uint32_t *)s->done_slots, S,
+        hipLaunchKernelGGL(k_gather_done, dim3(nf), dim3(64), 0, st, (const uint32_t *)s->done_slots, NS, S,
                            (const uint32_t *)s->best_path, (const uint32_t *)s->best_len,
                            (const uint32_t *)s->best_cost, s->done_path, s->done_len, s->done_cost);
         HIP_TRY(hipGetLastError());
@@ -3128,6 +3143,56 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
     *n_done = nf;
     s->completed += nf;
     s->ticks++;
+    return GMACOP_OK;
+}
+
+}  // namespace
+
+extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint32_t *n_admit, uint32_t *done_qid,
+                                  uint32_t *done_len, uint32_t *done_cost, uint32_t *done_paths, uint32_t done_cap,
+                                  uint32_t *n_done, void *hip_stream)
+{
+    if (!s || !n_admit || !n_done) return fail(GMACOP_E_INVAL, "server or counts are NULL");
+    if (*n_admit && !admit) return fail(GMACOP_E_INVAL, "admissions are NULL");
+    gmacop_graph *g = s->g;
+    const gmacop_params &p = s->p;
+    const uint32_t NS = s->slots;
+    // queries finishing in this step: those admitted iterations-1 steps ago, plus the new ones if iterations == 1
+    uint32_t finishing = 0;
+    for (uint32_t i = 0; i < NS; ++i) finishing += s->active[i] && s->t_host[i] + 1 == p.iterations;
+    const uint32_t take = std::min<uint32_t>(*n_admit, (uint32_t)s->free_list.size());
+    if (finishing + (p.iterations == 1 ? take : 0) > done_cap)
+        return fail(GMACOP_E_INVAL, "done_cap %u below the %u queries finishing in this step", done_cap,
+                    finishing + (p.iterations == 1 ? take : 0));
+    if ((finishing || (p.iterations == 1 && take)) && (!done_qid || !done_len || !done_cost || !done_paths))
+        return fail(GMACOP_E_INVAL, "result buffers are NULL");
+    for (uint32_t i = 0; i < take; ++i) {
+        if (admit[i].qid == 0xFFFFFFFFu) return fail(GMACOP_E_INVAL, "admission %u uses the reserved qid", i);
+        if (admit[i].src >= g->n || admit[i].dst >= g->n || admit[i].src == admit[i].dst)
+            return fail(GMACOP_E_INVAL, "admission %u: invalid nodes", i);
+        if (instance_of(g, admit[i].src) != instance_of(g, admit[i].dst))
+            return fail(GMACOP_E_INVAL, "admission %u: src and dst in different cities", i);
+    }
+    *n_done = 0;
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    int rc;
+    if (s->resync && (rc = server_resync(s, st))) {
+        *n_admit = 0;
+        return rc;
+    }
+    rc = server_step_impl(s, admit, take, done_qid, done_len, done_cost, done_paths, n_done, st);
+    if (rc) {
+        const std::string keep = t_err;
+        (void)hipStreamSynchronize(st);   // nothing of the failed step may still read the router's buffers
+        (void)hipGetLastError();
+        server_drop_all(s);
+        *n_admit = 0;
+        *n_done = 0;
+        t_err = keep;
+        return rc;
+    }
+    *n_admit = take;
     return GMACOP_OK;
 }
 
