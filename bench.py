@@ -3,17 +3,20 @@
 
 One step = one gmacop_route_batch call over the whole workload: every
 iteration's cost table, ant walks, best-route reduction, deposit,
-evaporation and load update.  Default workload: 32x32 grid city (1024
-intersections, 3770 roads), 256 vehicles x 128 ants x 100 iterations,
-shared pheromone and loads.  Queries and result buffers are resident in
-device memory before the timed region starts.
+evaporation and load update.  Default workload: 64 packed planar cities
+(843,944 intersections, 2,124,622 roads), 10,466 vehicles x 32 ants x 30
+iterations, shared pheromone and loads per city.  Queries and result
+buffers are resident in device memory before the timed region starts.
 
 Prints one JSON line: ant edge-selections per second (every roulette choice
-an ant makes), the walk kernel's position against HBM bandwidth, per-step
-latency percentiles, and the CPU oracle timed on a bounded sample of the same
-workload.
+an ant makes), the dominant walk kernel's position against HBM bandwidth,
+the routed fraction, the plain per-query form against the batched one, the
+continuous-batching router on the 1M-node city (p50/p99 latency and
+sustained queries/s at several offered rates), and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the walk kernel (what one lane must read or write):
+# Algorithmic bytes of a walk kernel (what one lane must read or write):
 #   per selection: row_ptr[u], row_ptr[u+1] (8 B) + path entry written (4 B)
 #   per candidate road examined: col, tau, cost (12 B) + head x, y (8 B)
 #   per road an arriving ant deposits on: path entry re-read (4 B) + 64-bit atomic add (8 B)
@@ -31,29 +34,30 @@ BYTES_PER_SELECTION = 12
 BYTES_PER_CANDIDATE = 20
 BYTES_PER_DEPOSIT_ROAD = 12
 
-
-PMC_PROFILE = os.path.join(ROOT, "profiles", "k_walk_ldsr_grid32x32_256veh_128ants_100it.md")
-# the walker kernels of each workload's walk phase
-WALK_KERNEL = {"grid8": "k_walk_ldsr", "grid32": "k_walk_ldsr", "planar100k": "k_walk_glb",
-               "multicity": "k_walk_ldsr + k_walk_lds + k_walk_glb"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_14244_amd", "csrc", "gmacop.hip")
+# walker kinds of the library's statistics: (stats kernel key, stats walker key, kernel names)
+WALKER_KINDS = {"lds": ("walk_lds", "lds", "k_walk_ldsr / k_walk_lds"), "glb": ("walk_glb", "glb", "k_walk_glb")}
 
 
-def measured_walk_traffic():
-    """HBM bytes per walk launch from the committed PMC profile (FETCH_SIZE and
-    WRITE_SIZE, each scaled by the copy-kernel calibration), or None when the
-    kernel source has changed since the counters were taken."""
-    import hashlib
+def source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed PMC
+    profile (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel
+    calibration), or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     try:
         vals = {}
-        with open(PMC_PROFILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and line.split(":")[0].strip().startswith(("pmc_", "source_sha256")):
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
-        with open(KERNEL_SOURCE, "rb") as f:
-            cur = hashlib.sha256(f.read()).hexdigest()[:16]
-        if vals.get("source_sha256_prefix") != cur:
+        if vals.get("source_sha256_prefix") != source_hash():
             return None
         return (float(vals["pmc_walk_fetch_kib"]) * float(vals["pmc_fetch_scale"]) +
                 float(vals["pmc_walk_write_kib"]) * float(vals["pmc_write_scale"])) * 1024.0
@@ -77,28 +81,50 @@ def make_workload(name):
     return table[name]()
 
 
-def cpu_baseline(w, iterations):
-    """The oracle, as is, on the same graph and vehicles with fewer iterations."""
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def cpu_baseline(w, vehicles):
+    """The oracle, as is, on the same graph and parameters for the first
+    `vehicles` vehicles and all iterations, one thread."""
     import oracle
+    from workloads import Vehicles
     oracle.build(force=False)
-    p = dict(w.params, iterations=iterations)
+    V = w.vehicles
+    k = min(vehicles, len(V))
+    sub = Vehicles(qid=V.qid[:k], src=V.src[:k], dst=V.dst[:k])
     t = time.perf_counter()
-    r = oracle.route(w.graph, w.vehicles, p, want_state=False)
+    r = oracle.route(w.graph, sub, w.params, want_state=False)
     dt = time.perf_counter() - t
+    model, ncpu, avail = host_cpu()
     return {"value": r["steps_total"] / dt, "unit": "edge-selections/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w.name} with {iterations} of {w.params['iterations']} iterations "
+            "host_cores": ncpu, "host_cores_available": avail, "cpu_model": model,
+            "sample": f"{w.name}: first {k} of {len(V)} vehicles, all {w.params['iterations']} iterations "
                       f"({r['steps_total']} selections in {dt:.1f} s, single thread)"}
 
 
-def measure_forms(gmacop, G, w, stream_obj, max_plain=None):
-    """Independent-mode routing of the workload's vehicles, two ways: the
-    plain per-query form (one gmacop_route_batch per vehicle, kernels
-    launched one by one) and the batched form (one call for all vehicles,
-    replayed as a HIP graph).  Per-vehicle results are identical; reports
-    edge-selections/s of both and their ratio."""
-    import numpy as np
+def measure_forms(gmacop, G, w, stream_obj, max_vehicles):
+    """Independent-mode routing of the first `max_vehicles` vehicles, two
+    ways: the plain per-query form (one gmacop_route_batch per vehicle,
+    kernels launched one by one) and the batched form (one call for all of
+    them, replayed as a HIP graph).  Per-vehicle results are identical;
+    reports edge-selections/s of both and their ratio."""
     V = w.vehicles
-    nv = len(V) if max_plain is None else min(len(V), max_plain)
+    nv = min(len(V), max_vehicles)
     p = dict(w.params, mode=gmacop.MODE_INDEPENDENT)
     stream = stream_obj.cuda_stream
     sub = type(V)(qid=V.qid[:nv], src=V.src[:nv], dst=V.dst[:nv])
@@ -129,58 +155,72 @@ def measure_forms(gmacop, G, w, stream_obj, max_plain=None):
     return {"mode": "independent", "vehicles": nv,
             "plain_per_query": {"value": sel_plain / t_plain, "ms": t_plain * 1e3, "launch": "eager, one call per vehicle"},
             "batched": {"value": rb["steps_total"] / t_batched, "ms": t_batched * 1e3, "launch": "hip_graph, one call"},
-            "batched_over_plain": t_plain / t_batched}
+            "batched_over_plain": t_plain / t_batched,
+            "routed_fraction": float((rb["path_len"] > 0).mean()) if nv else None}
 
 
-def bench_serve(args):
+def run_serving(args, log):
     """Continuous-batching router on the 1M-node city: Poisson arrivals at
-    each rate in --rates, 32 ants x 20 iterations per query."""
+    each rate in --rates, 32 ants x 20 iterations per query.  Latency is
+    arrival to result, queueing for a slot included."""
     import numpy as np
-    import torch
     import workloads
     from paper_2010_14244_amd import gmacop, serve
+    import torch
 
-    torch.cuda.set_device(0)
-    print("[bench] generating the serving city", file=sys.stderr, flush=True)
+    log("[bench] generating the serving city")
     w = workloads.serving_city(n=args.serve_nodes)
     g, p = w.graph, dict(w.params)
     G = gmacop.gmacop_graph_create(g)
     srv = gmacop.Server(G, p, max_slots=args.serve_slots)
     stream_obj = torch.cuda.Stream()
     stream = stream_obj.cuda_stream
-    print(f"[bench] {w.name}: n={g.n} m={g.m} slots={srv.slots} ({srv.bytes_per_slot / 2**20:.1f} MiB each)",
-          file=sys.stderr, flush=True)
+    log(f"[bench] {w.name}: n={g.n} m={g.m} slots={srv.slots} ({srv.bytes_per_slot / 2**20:.1f} MiB each)")
     rng = np.random.default_rng(7)
-    rates, qid0 = [float(r) for r in args.rates.split(",")], 0
-    runs = []
-    for rate in rates:
-        n = max(int(rate * args.serve_seconds), args.serve_warmup + 10)
+    qid0, runs = 0, []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        n = max(int(rate * args.serve_seconds), args.serve_min_queries + args.serve_warmup)
         od = workloads.query_stream(g, n, rng, qid0=qid0)
         qid0 += n
         arr = serve.poisson_arrivals(n, rate, rng)
         gmacop.gmacop_stats_get(G, reset=True)
-        r = serve.serve(srv, od, arr, warmup=args.serve_warmup, stream=stream,
-                        log=lambda m: print(m, file=sys.stderr, flush=True))
+        r = serve.serve(srv, od, arr, warmup=args.serve_warmup, stream=stream, log=log)
         st = gmacop.gmacop_stats_get(G)
-        run = {"offered_qps": rate, "queries": n, "sustained_qps": r["sustained_qps"], "p50_ms": r["p50_ms"],
-               "p99_ms": r["p99_ms"], "steps": r["steps"], "selections": st["selections"],
-               "edge_selections_per_s": st["selections"] / r["wall_s"],
-               "longest_walk_per_step": st["longest_walks"] / max(1, r["steps"])}
+        lat = r["latency_s"][args.serve_warmup:]
+        routed = np.array([len(r["results"][int(q)][0]) > 0 for q in od[args.serve_warmup:, 0]])
+        lat_routed = lat[routed]
+        run = {"offered_qps": rate, "queries": n, "measured_queries": int(lat.shape[0]),
+               "sustained_qps": r["sustained_qps"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+               "routed_fraction": float(routed.mean()),
+               "routed_qps": r["sustained_qps"] * float(routed.mean()),
+               "routed_p50_ms": float(np.percentile(lat_routed, 50) * 1e3) if lat_routed.size else None,
+               "routed_p99_ms": float(np.percentile(lat_routed, 99) * 1e3) if lat_routed.size else None,
+               "ant_arrival_rate": st["arrivals"] / max(1, n * p["ants"] * p["iterations"]),
+               "steps": r["steps"], "edge_selections_per_s": st["selections"] / r["wall_s"]}
         runs.append(run)
-        print(f"[bench] rate {rate:.0f}/s: sustained {r['sustained_qps']:.0f}/s p50 {r['p50_ms']:.1f} ms "
-              f"p99 {r['p99_ms']:.1f} ms, {r['steps']} steps", file=sys.stderr, flush=True)
-    best = max(runs, key=lambda x: x["sustained_qps"])
-    out = {"metric": "route queries/sec (continuous batching)", "value": best["sustained_qps"], "unit": "queries/s",
-           "n_gpus": 1, "steps": sum(x["steps"] for x in runs), "warmup": args.serve_warmup,
-           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
-           "data": "synthetic",
-           "config": {"workload": w.name, "nodes": g.n, "roads": g.m, "ants": p["ants"],
-                      "iterations": p["iterations"], "max_steps": p["max_steps"], "slots": srv.slots,
-                      "mode": "independent"},
-           "latency_ms": {"p50": best["p50_ms"], "p99": best["p99_ms"]}, "serving": runs}
+        log(f"[bench] serve {rate:.0f}/s: sustained {r['sustained_qps']:.0f}/s p50 {r['p50_ms']:.1f} ms "
+            f"p99 {r['p99_ms']:.1f} ms routed {run['routed_fraction']:.3f}, {r['steps']} steps")
     srv.release()
     gmacop.gmacop_release(G)
-    print(json.dumps(out), flush=True)
+    return {"workload": w.name, "nodes": g.n, "roads": g.m, "ants": p["ants"], "iterations": p["iterations"],
+            "max_steps": p["max_steps"], "slots": srv.slots, "mode": "independent", "runs": runs}
+
+
+def walker_roofline(st, kernel_ms_key, walker_key, workload, names):
+    """Effective bandwidth of one walker kind from its event times and
+    counters (algorithmic bytes / average launch time)."""
+    nl = st["launches"][kernel_ms_key]
+    if not nl or st["ms"][kernel_ms_key] <= 0:
+        return None
+    ms = st["ms"][kernel_ms_key] / nl
+    c = st["walkers"][walker_key]
+    byts = (BYTES_PER_SELECTION * c["selections"] + BYTES_PER_CANDIDATE * c["candidates"] +
+            BYTES_PER_DEPOSIT_ROAD * c["deposit_roads"]) / nl
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"kernel": names, "launches_timed": nl, "avg_launch_ms": round(ms, 5),
+            "algorithmic_bytes_per_launch": int(byts), "achieved": round(gbs, 2),
+            "selections_per_launch": c["selections"] / nl,
+            "mean_candidates_per_selection": c["candidates"] / max(1, c["selections"])}
 
 
 def main():
@@ -188,14 +228,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="grid32", choices=["grid8", "grid32", "planar100k", "multicity", "serve"])
-    ap.add_argument("--rates", default="2000,5000,10000,20000", help="serve: offered query rates")
-    ap.add_argument("--serve-seconds", type=float, default=3.0, help="serve: seconds of arrivals per rate")
-    ap.add_argument("--serve-warmup", type=int, default=200, help="serve: queries excluded from latency stats")
-    ap.add_argument("--serve-slots", type=int, default=4096, help="serve: slot limit (memory may allow fewer)")
-    ap.add_argument("--serve-nodes", type=int, default=1_000_000, help="serve: city size")
+    ap.add_argument("--workload", default="multicity", choices=["grid8", "grid32", "planar100k", "multicity"])
+    ap.add_argument("--no-serve", action="store_true", help="skip the continuous-batching router runs")
+    ap.add_argument("--rates", default="2000,5000,10000,20000", help="router: offered query rates")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="router: seconds of arrivals per rate")
+    ap.add_argument("--serve-min-queries", type=int, default=10000, help="router: measured queries per rate")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="router: queries excluded from latency stats")
+    ap.add_argument("--serve-slots", type=int, default=4096, help="router: slot limit (memory may allow fewer)")
+    ap.add_argument("--serve-nodes", type=int, default=1_000_000, help="router: city size")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iterations", type=int, default=10)
+    ap.add_argument("--cpu-vehicles", type=int, default=256, help="CPU oracle: the first this many vehicles")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed pass (roofline becomes null)")
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
@@ -204,20 +246,23 @@ def main():
                          "reference for hardware byte counters)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the plain-per-query vs batched comparison (independent mode)")
+    ap.add_argument("--forms-vehicles", type=int, default=512, help="plain vs batched: the first this many vehicles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "serve":
-        return bench_serve(args)
+    import numpy as np
     import torch
     from paper_2010_14244_amd import gmacop
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
+    log(f"[bench] generating workload {args.workload}")
     w = make_workload(args.workload)
     g, V, p = w.graph, w.vehicles, dict(w.params)
     G = gmacop.gmacop_graph_create(g)
@@ -226,7 +271,7 @@ def main():
     stream = stream_obj.cuda_stream
     p_run = dict(p, flags=p["flags"] | (0 if args.eager else gmacop.HIP_GRAPH))
 
-    print(f"[bench] {w.name}: n={g.n} m={g.m} vehicles={len(V)} warmup={args.warmup}", file=sys.stderr, flush=True)
+    log(f"[bench] {w.name}: n={g.n} m={g.m} vehicles={len(V)} warmup={args.warmup}")
     if args.copy_calibration_mib:
         src = torch.empty(args.copy_calibration_mib << 18, dtype=torch.int32, device="cuda").fill_(1)
         dst = torch.empty_like(src)
@@ -248,42 +293,49 @@ def main():
         gmacop.gmacop_route_batch_device(G, b, p_run, stream)
         stream_obj.synchronize()
         lat.append(time.perf_counter() - t0)
-        print(f"[bench] step {i}: {lat[-1] * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        log(f"[bench] step {i}: {lat[-1] * 1e3:.2f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     st = gmacop.gmacop_stats_get(G, reset=True)
     res = b.result()
     sel = st["selections"]
     assert sel == res["steps_total"] * args.steps, (sel, res["steps_total"])
+    routed = float((res["path_len"] > 0).mean()) if len(V) else None
+    arrival_rate = st["arrivals"] / max(1, args.steps * len(V) * p["ants"] * p["iterations"])
 
-    roofline = None
+    roofline, walkers = None, {}
     if not args.no_kernel_timing:
         # second timed pass: the same calls launched kernel by kernel, each
-        # bracketed by HIP events on the launch stream
+        # bracketed by HIP events on the stream it runs on
         for i in range(args.steps):
             gmacop.gmacop_route_batch_device(G, b, dict(p, flags=p["flags"] | gmacop.TIME_KERNELS), stream)
         stream_obj.synchronize()
         kt = gmacop.gmacop_stats_get(G)
-        nl = kt["launches"]["walk"]
-        walk_ms = kt["ms"]["walk"] / nl
-        ksel = kt["selections"]
-        bytes_per_launch = (BYTES_PER_SELECTION * ksel + BYTES_PER_CANDIDATE * kt["candidates"] +
-                            BYTES_PER_DEPOSIT_ROAD * kt["deposit_roads"]) / nl
-        achieved = bytes_per_launch / (walk_ms * 1e-3) / 1e9
-        traffic = measured_walk_traffic() if args.workload == "grid32" else None
-        roofline = {"bound": "hbm", "kernel": WALK_KERNEL[args.workload], "achieved": round(achieved, 2),
-                    "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                    "traffic": None if traffic is None else round(traffic),
-                    "avg_launch_ms": round(walk_ms, 5), "launches_timed": nl,
-                    "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                    "selections_per_launch": ksel / nl, "mean_candidates_per_selection": kt["candidates"] / ksel,
-                    "longest_walk_per_launch": kt["longest_walks"] / nl,
-                    "ns_per_road_on_longest_walk": walk_ms * 1e6 / max(1.0, kt["longest_walks"] / nl)}
-        tot = sum(kt["ms"].values())
-        print("[bench] event-timed pass, per call: " + ", ".join(
+        for kind, (mkey, wkey, names) in WALKER_KINDS.items():
+            r = walker_roofline(kt, mkey, wkey, w.name, names)
+            if r:
+                walkers[kind] = r
+        if walkers:
+            dom = max(walkers, key=lambda k: walkers[k]["avg_launch_ms"] * walkers[k]["launches_timed"])
+            d = walkers[dom]
+            kernel = "k_walk_glb" if dom == "glb" else "k_walk_ldsr"
+            traffic = measured_traffic(kernel, w.name)
+            roofline = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["achieved"], "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(d["achieved"] / HBM_PEAK_GBS, 5),
+                        "traffic": None if traffic is None else round(traffic),
+                        "achieved_kind": "effective: algorithmic bytes / average launch time",
+                        "measured_frac": None if traffic is None else
+                        round(traffic / (d["avg_launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                        "limiter": "dependent chain of the longest walks (latency), not bandwidth",
+                        "avg_launch_ms": d["avg_launch_ms"], "launches_timed": d["launches_timed"],
+                        "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+                        "selections_per_launch": d["selections_per_launch"],
+                        "mean_candidates_per_selection": d["mean_candidates_per_selection"],
+                        "longest_walk_per_iteration": kt["longest_walks"] / max(1, kt["launches"]["walk"])}
+        n_it = max(1, kt["launches"]["walk"])
+        log("[bench] event-timed pass, per call: " + ", ".join(
             f"{k} {kt['ms'][k] / args.steps:.3f} ms ({kt['launches'][k] // args.steps}x)" for k in kt["ms"]) +
-              f"; kernels {tot / args.steps:.3f} ms", file=sys.stderr, flush=True)
+            f"; walk phase {kt['ms']['walk'] / n_it:.3f} ms per iteration")
 
     out = {
         "metric": "ant edge-selections/sec",
@@ -298,23 +350,29 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": w.name, "nodes": g.n, "roads": g.m, "vehicles": len(V), "ants": p["ants"],
-                   "iterations": p["iterations"], "mode": "shared", "launch": "eager" if args.eager else "hip_graph",
-                   "selections_per_step": sel // args.steps,
-                   "arrivals_per_step": st["arrivals"] // args.steps},
-        "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3},
+        "config": {"workload": w.name, "nodes": g.n, "roads": g.m,
+                   "cities": 1 if g.inst_node_off is None else int(g.inst_node_off.shape[0] - 1),
+                   "vehicles": len(V), "ants": p["ants"], "iterations": p["iterations"], "mode": "shared",
+                   "launch": "eager" if args.eager else "hip_graph", "selections_per_step": sel // args.steps},
+        "routing": {"routed_fraction": routed, "ant_arrival_rate": arrival_rate},
+        "call_latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3},
         "roofline": roofline,
+        "walkers": walkers,
     }
     if not args.no_forms:
-        print("[bench] plain per-query vs batched (independent mode)", file=sys.stderr, flush=True)
-        out["forms"] = measure_forms(gmacop, G, w, stream_obj)
+        log("[bench] plain per-query vs batched (independent mode)")
+        out["forms"] = measure_forms(gmacop, G, w, stream_obj, args.forms_vehicles)
         f = out["forms"]
-        print(f"[bench] forms: plain {f['plain_per_query']['ms']:.1f} ms, batched {f['batched']['ms']:.1f} ms, "
-              f"ratio {f['batched_over_plain']:.1f}", file=sys.stderr, flush=True)
+        log(f"[bench] forms: plain {f['plain_per_query']['ms']:.1f} ms, batched {f['batched']['ms']:.1f} ms, "
+            f"ratio {f['batched_over_plain']:.1f}")
     gmacop.gmacop_release(G)
+    del b
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["serving"] = run_serving(args, log)
     if not args.no_cpu:
-        print(f"[bench] timing the CPU oracle on {args.cpu_iterations} iterations", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iterations)
+        log(f"[bench] timing the CPU oracle on the first {args.cpu_vehicles} vehicles")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_vehicles)
     print(json.dumps(out), flush=True)
 
 

@@ -154,18 +154,26 @@ int gmacop_state_get(gmacop_graph *g, uint32_t *tau_q16, uint32_t *load, void *h
 int gmacop_vehicle_tau_get(gmacop_graph *g, uint32_t vehicle, uint32_t *tau_q16, void *hip_stream);
 
 /* Work counters and kernel times accumulated over gmacop_route_batch calls
- * since the last reset.  Kernel index: 0 = walk (tour construction and
- * deposit), 1 = best-route reduction, 2 = pheromone/load update, 3 = signal
- * and cost table.  ms[] is filled only for calls made with
- * GMACOP_TIME_KERNELS (times from HIP events on the call's stream). */
+ * since the last reset.  Kernel index: 0 = walk phase (tour construction and
+ * deposit, all walkers of an iteration), 1 = best-route reduction, 2 =
+ * pheromone/load update, 3 = signal and cost table, 4 = the LDS walkers of an
+ * iteration (cities staged in on-chip memory), 5 = the global-memory walker
+ * of an iteration.  ms[] is filled only for calls made with
+ * GMACOP_TIME_KERNELS (times from HIP events on the stream each kernel runs
+ * on).  walker_*[k]: the same counters per walker kind, k = 0 LDS walkers,
+ * 1 global-memory walker, 2 first walker (graphs of 2^24 nodes or more). */
 typedef struct {
-    uint64_t launches[4];
-    double ms[4];
+    uint64_t launches[6];
+    double ms[6];
     uint64_t selections;     /* roulette selections (one per road an ant takes)       */
     uint64_t candidates;     /* out-roads examined at those selections                */
     uint64_t arrivals;       /* ants that reached their destination                   */
     uint64_t deposit_roads;  /* roads deposited on by arriving ants                   */
     uint64_t longest_walks;  /* sum over walk launches of the longest ant's road count   */
+    uint64_t walker_selections[3];
+    uint64_t walker_candidates[3];
+    uint64_t walker_arrivals[3];
+    uint64_t walker_deposit_roads[3];
 } gmacop_stats;
 
 /* Copy the counters into *s (synchronises hip_stream); reset them when reset

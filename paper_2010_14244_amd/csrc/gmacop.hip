@@ -72,6 +72,13 @@ constexpr int kLdsClasses = 6;       // LDS walker classes: 1..3 k_walk_ldsr, 4.
 constexpr bool is_road_class(uint32_t c) { return c >= 1 && c <= 3; }
 constexpr uint64_t kGlbWordsBudget = 4ull << 30;   // bytes of per-slot visited words of k_walk_glb
 constexpr uint32_t kLdsBitsetMaxNodes = 4096;   // 512 B of visited bits per ant in LDS
+// Work counters on the device: [0] selections, [1] candidates examined, [2] arrivals, [3] roads
+// deposited on, [4] sum over iterations of the longest walk; then four per walker kind (the same
+// first four quantities) at kWalkerCounters + 4 * kind.
+constexpr int kWalkerCounters = 5;
+constexpr int kCounters = kWalkerCounters + 4 * 3;
+constexpr int kKindLds = 0, kKindGlb = 1, kKindFirst = 2;
+constexpr int kTimedKernels = 6;   // walk phase, best route, update, cost table, LDS walkers, global walker
 
 // ---------------------------------------------------------------------------
 // device arithmetic
@@ -379,6 +386,19 @@ __global__ void k_cost(CostArgs a)
     }
 }
 
+// Add a walker's selections, candidates, arrivals and deposited roads to the
+// totals and to its kind's block.
+__device__ __forceinline__ void add_walk_counters(uint64_t *c, int kind, uint64_t sel, uint64_t cand, uint64_t arr,
+                                                  uint64_t dep)
+{
+    const uint64_t v[4] = {sel, cand, arr, dep};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        atomicAdd((unsigned long long *)&c[i], (unsigned long long)v[i]);
+        atomicAdd((unsigned long long *)&c[kWalkerCounters + 4 * kind + i], (unsigned long long)v[i]);
+    }
+}
+
 struct WalkArgs {
     const uint32_t *row_ptr, *col, *cost;
     PherView pher;
@@ -395,7 +415,7 @@ struct WalkArgs {
     uint32_t *gbits;       // [NA][nwords] visited bits when not in LDS
     uint64_t *iter_key;    // [nq]
     uint64_t *steps;       // [1] selections of this call
-    uint64_t *counters;    // [4] cumulative: selections, candidates examined, arrivals, roads deposited on
+    uint64_t *counters;    // [kCounters] cumulative work counters
     uint32_t *iter_max;    // longest walk of this iteration
 };
 
@@ -523,10 +543,7 @@ __global__ __launch_bounds__(kWave) void k_walk(WalkArgs a)
     }
     if (lane == 0 && cnt) {
         atomicAdd((unsigned long long *)a.steps, (unsigned long long)cnt);
-        atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)cnt);
-        atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)cand);
-        atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)arr);
-        atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)dh);
+        add_walk_counters(a.counters, kKindFirst, cnt, cand, arr, dh);
         atomicMax(a.iter_max, smax);
     }
 }
@@ -733,10 +750,7 @@ __device__ __forceinline__ void lds_block_finish(const LdsWalkArgs &a, uint64_t 
         if (s_blk[0] != ~0ull) atomicMin((unsigned long long *)&a.iter_key[v], (unsigned long long)s_blk[0]);
         if (s_blk[1]) {
             atomicAdd((unsigned long long *)a.steps, (unsigned long long)s_blk[1]);
-            atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)s_blk[1]);
-            atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)s_blk[2]);
-            atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)s_blk[3]);
-            atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)s_blk[4]);
+            add_walk_counters(a.counters, kKindLds, s_blk[1], s_blk[2], s_blk[3], s_blk[4]);
             atomicMax(a.iter_max, (uint32_t)s_blk[5]);
         }
     }
@@ -1444,10 +1458,7 @@ __global__ __launch_bounds__(256) void k_walk_glb(GlbWalkArgs a)
     if (lane == 0) {
         if (c_steps) {
             atomicAdd((unsigned long long *)a.steps, (unsigned long long)c_steps);
-            atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)c_steps);
-            atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)c_cand);
-            atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)c_arr);
-            atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)c_dh);
+            add_walk_counters(a.counters, kKindGlb, c_steps, c_cand, c_arr, c_dh);
             atomicMax(a.iter_max, c_max);
         }
         // the last wave out resets the ticket counters for the next launch
@@ -1849,10 +1860,10 @@ struct gmacop_graph {
     gmacop_od *od = nullptr;
     GlbWork glb;
     // statistics
-    uint64_t *counters = nullptr;         // device [5]
+    uint64_t *counters = nullptr;         // device [kCounters]
     uint32_t *iter_max = nullptr;         // device [1]
-    uint64_t launches[4] = {0, 0, 0, 0};
-    double ms[4] = {0, 0, 0, 0};
+    uint64_t launches[kTimedKernels] = {};
+    double ms[kTimedKernels] = {};
     struct Timed { hipEvent_t a, b; int kernel; };
     // a second stream for the global walker, run beside the LDS walkers of the same iteration
     hipStream_t side = nullptr;
@@ -2414,13 +2425,13 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
         (rc = upload(&g->base_load, d->base_load, m)) || (rc = upload(&g->rev_ptr, rev_ptr.data(), n + 1)) ||
         (rc = upload(&g->rev_edge, rev_edge.data(), m)) || (rc = dalloc(&g->t0, m)) || (rc = dalloc(&g->wf, m)) ||
         (rc = dalloc(&g->tau, m)) || (rc = dalloc(&g->load, m)) || (rc = dalloc(&g->cost, m)) ||
-        (rc = dalloc(&g->cnt, m)) || (rc = dalloc(&g->dep, m)) || (rc = dalloc(&g->counters, 5)) || (rc = dalloc(&g->iter_max, 1))) {
+        (rc = dalloc(&g->cnt, m)) || (rc = dalloc(&g->dep, m)) || (rc = dalloc(&g->counters, kCounters)) || (rc = dalloc(&g->iter_max, 1))) {
         std::string keep = t_err;
         delete g;
         t_err = keep;
         return rc;
     }
-    if (hipMemset(g->counters, 0, 5 * sizeof(uint64_t)) != hipSuccess ||
+    if (hipMemset(g->counters, 0, kCounters * sizeof(uint64_t)) != hipSuccess ||
         hipMemset(g->iter_max, 0, sizeof(uint32_t)) != hipSuccess) {
         delete g;
         return fail(GMACOP_E_DEVICE, "hipMemset of counters failed");
@@ -2589,7 +2600,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     auto enqueue = [&]() -> int {
         int erc = GMACOP_OK;
         KernelTimer kt{g, st, timing};
-        gmacop_graph::Timed tm{};
+        gmacop_graph::Timed tm{}, tl{};
         hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ia);
         if (indep && nq) hipLaunchKernelGGL(k_next_generation, dim3(1), dim3(64), 0, st, g->dev_gen);
         hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
@@ -2616,20 +2627,30 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
                           : md <= 8 ? launch_walk<8>(wt, lds, st)
                           : md <= 16 ? launch_walk<16>(wt, lds, st)
                                      : launch_walk<32>(wt, lds, st);
-                } else if (plan.glb && plan.any_lds()) {
-                    // both kinds of walker: the global one on the side stream, beside the LDS ones
-                    HIP_TRY(hipEventRecord(g->fork, st));
-                    HIP_TRY(hipStreamWaitEvent(g->side, g->fork, 0));
-                    hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, g->side, gla);
-                    erc = launch_walk_glb_any(gt, plan, g->side);
-                    if (!erc) erc = launch_walk_lds_classes(lt, plan, st);
-                    HIP_TRY(hipEventRecord(g->join, g->side));
-                    HIP_TRY(hipStreamWaitEvent(st, g->join, 0));
                 } else {
-                    erc = launch_walk_lds_classes(lt, plan, st);
-                    if (!erc && plan.glb) {
-                        hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, st, gla);
-                        erc = launch_walk_glb_any(gt, plan, st);
+                    // both kinds of walker: the global one on the side stream, beside the LDS ones
+                    const bool both = plan.glb && plan.any_lds();
+                    hipStream_t gst = both ? g->side : st;
+                    KernelTimer kg{g, gst, timing};
+                    gmacop_graph::Timed tg{};
+                    if (both) {
+                        HIP_TRY(hipEventRecord(g->fork, st));
+                        HIP_TRY(hipStreamWaitEvent(g->side, g->fork, 0));
+                    }
+                    if (plan.glb) {
+                        hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, gst, gla);
+                        if ((erc = kg.start(5, &tg)) || (erc = launch_walk_glb_any(gt, plan, gst)) ||
+                            (erc = kg.stop(&tg)))
+                            return erc;
+                    }
+                    if (plan.any_lds()) {
+                        if ((erc = kt.start(4, &tl)) || (erc = launch_walk_lds_classes(lt, plan, st)) ||
+                            (erc = kt.stop(&tl)))
+                            return erc;
+                    }
+                    if (both) {
+                        HIP_TRY(hipEventRecord(g->join, g->side));
+                        HIP_TRY(hipStreamWaitEvent(st, g->join, 0));
                     }
                 }
                 if (erc || (erc = kt.stop(&tm))) return erc;
@@ -2676,7 +2697,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
                 (void)hipGraphExecDestroy(g->gexec);
                 g->gexec = nullptr;
             }
-            uint64_t saved[4];
+            uint64_t saved[kTimedKernels];
             memcpy(saved, g->launches, sizeof(saved));
             HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             rc = enqueue();
@@ -2700,6 +2721,8 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         if (NA > 0) {
             g->launches[0] += p->iterations;
             g->launches[1] += p->iterations;
+            if (!plan.legacy && plan.any_lds()) g->launches[4] += p->iterations;
+            if (!plan.legacy && plan.glb) g->launches[5] += p->iterations;
         }
         g->launches[2] += p->iterations;
         if (update_loads) g->launches[3] += p->iterations;
@@ -2762,7 +2785,7 @@ extern "C" int gmacop_stats_get(gmacop_graph *g, gmacop_stats *s, int reset, voi
     if (!g || !s) return fail(GMACOP_E_INVAL, "graph or stats is NULL");
     HIP_TRY(hipSetDevice(g->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    uint64_t c[5];
+    uint64_t c[kCounters];
     HIP_TRY(hipMemcpyAsync(c, g->counters, sizeof(c), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (auto &t : g->pending) {
@@ -2774,7 +2797,7 @@ extern "C" int gmacop_stats_get(gmacop_graph *g, gmacop_stats *s, int reset, voi
         g->spare.push_back(t.b);
     }
     g->pending.clear();
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kTimedKernels; ++k) {
         s->launches[k] = g->launches[k];
         s->ms[k] = g->ms[k];
     }
@@ -2783,10 +2806,16 @@ extern "C" int gmacop_stats_get(gmacop_graph *g, gmacop_stats *s, int reset, voi
     s->arrivals = c[2];
     s->deposit_roads = c[3];
     s->longest_walks = c[4];
+    for (int k = 0; k < 3; ++k) {
+        s->walker_selections[k] = c[kWalkerCounters + 4 * k + 0];
+        s->walker_candidates[k] = c[kWalkerCounters + 4 * k + 1];
+        s->walker_arrivals[k] = c[kWalkerCounters + 4 * k + 2];
+        s->walker_deposit_roads[k] = c[kWalkerCounters + 4 * k + 3];
+    }
     if (reset) {
         HIP_TRY(hipMemsetAsync(g->counters, 0, sizeof(c), st));
         HIP_TRY(hipStreamSynchronize(st));
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kTimedKernels; ++k) {
             g->launches[k] = 0;
             g->ms[k] = 0;
         }
@@ -2928,7 +2957,7 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
         (rc = dalloc_zero(&s->touched_n, NS)) || (rc = dalloc(&s->touched, (size_t)NS * s->tcap)) ||
         (rc = dalloc(&s->path, (size_t)S * NA)) || (rc = dalloc(&s->ant_len, NA)) || (rc = dalloc(&s->ant_cost, NA)) ||
         (rc = dalloc_zero(&s->steps, 1)) ||
-        (rc = dalloc_zero(&s->counters, 5)) || (rc = dalloc_zero(&s->iter_max, 1)) || (rc = dalloc(&s->vclass, NS)) ||
+        (rc = dalloc_zero(&s->counters, kCounters)) || (rc = dalloc_zero(&s->iter_max, 1)) || (rc = dalloc(&s->vclass, NS)) ||
         (rc = dalloc(&s->t0, m)) || (rc = dalloc(&s->wf, m)) || (rc = dalloc(&s->load, m)) ||
         (rc = dalloc(&s->cost, m)) || (rc = dalloc(&s->cnt, m)) || (rc = dalloc(&s->tau, m)) ||
         (rc = dalloc(&s->dep_shared, m)) || (rc = dalloc(&s->adm_slots, NS)) || (rc = dalloc(&s->adm_gen, NS)) ||

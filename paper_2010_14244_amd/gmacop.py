@@ -34,7 +34,8 @@ HIP_GRAPH = 8
 EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_state_get", "gmacop_vehicle_tau_get",
             "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
             "gmacop_server_release", "gmacop_release", "gmacop_last_error")
-KERNELS = ("walk", "best", "edge", "cost")
+KERNELS = ("walk", "best", "edge", "cost", "walk_lds", "walk_glb")
+WALKERS = ("lds", "glb", "first")
 
 
 class GmacopError(RuntimeError):
@@ -69,9 +70,11 @@ class _Result(C.Structure):
 
 
 class _Stats(C.Structure):
-    _fields_ = [("launches", C.c_uint64 * 4), ("ms", C.c_double * 4), ("selections", C.c_uint64),
+    _fields_ = [("launches", C.c_uint64 * 6), ("ms", C.c_double * 6), ("selections", C.c_uint64),
                 ("candidates", C.c_uint64), ("arrivals", C.c_uint64), ("deposit_roads", C.c_uint64),
-                ("longest_walks", C.c_uint64)]
+                ("longest_walks", C.c_uint64), ("walker_selections", C.c_uint64 * 3),
+                ("walker_candidates", C.c_uint64 * 3), ("walker_arrivals", C.c_uint64 * 3),
+                ("walker_deposit_roads", C.c_uint64 * 3)]
 
 
 _lib = None
@@ -238,7 +241,10 @@ def gmacop_stats_get(g: Graph, reset: bool = False, stream: Optional[int] = None
     return dict(launches={k: int(st.launches[i]) for i, k in enumerate(KERNELS)},
                 ms={k: float(st.ms[i]) for i, k in enumerate(KERNELS)},
                 selections=int(st.selections), candidates=int(st.candidates), arrivals=int(st.arrivals),
-                deposit_roads=int(st.deposit_roads), longest_walks=int(st.longest_walks))
+                deposit_roads=int(st.deposit_roads), longest_walks=int(st.longest_walks),
+                walkers={w: dict(selections=int(st.walker_selections[i]), candidates=int(st.walker_candidates[i]),
+                                 arrivals=int(st.walker_arrivals[i]), deposit_roads=int(st.walker_deposit_roads[i]))
+                         for i, w in enumerate(WALKERS)})
 
 
 def gmacop_release(g: Graph) -> None:
