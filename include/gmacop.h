@@ -142,6 +142,35 @@ int gmacop_graph_create(const gmacop_graph_desc *desc, gmacop_graph **out);
 int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
                        gmacop_result *out, void *hip_stream);
 
+/* Bytes of device workspace gmacop_route_batch_noalloc may use: one static
+ * array of this size per GPU, held from the library's first use of that GPU
+ * until the process ends. */
+#define GMACOP_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call and the same results as gmacop_route_batch, with every per-call
+ * buffer (ant paths, per-vehicle keys and results, the walkers' work lists
+ * and visited words, independent-mode pheromone rows) carved out of the
+ * library's static per-GPU workspace of GMACOP_NOALLOC_SCRATCH_BYTES.  It
+ * calls no hipMalloc, hipFree or other allocating routine; the graph must
+ * have been created (and its state allocated) by gmacop_graph_create.
+ * Differences from gmacop_route_batch:
+ *  - GMACOP_HIP_GRAPH and GMACOP_TIME_KERNELS are rejected (GMACOP_E_INVAL);
+ *  - the walkers of one iteration run one after the other on hip_stream;
+ *  - a call whose workspace exceeds GMACOP_NOALLOC_SCRATCH_BYTES returns
+ *    GMACOP_E_NOMEM and changes nothing (the message gives the size needed);
+ *    graphs of 2^24 nodes or more return GMACOP_E_UNSUPPORTED;
+ *  - gmacop_vehicle_tau_get is not available after it (GMACOP_E_INVAL).
+ * Every call on one GPU, from any graph handle or thread, shares that GPU's
+ * workspace and finds the previous call's contents in it; calls that overlap
+ * on one GPU (on different streams or threads) race and must not be made.
+ * Without GMACOP_DEVICE_PTRS the call synchronises hip_stream before it
+ * returns; with it, the results are ready once hip_stream reaches them and
+ * the next call on the GPU may reuse the workspace only after that. */
+int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
+                               gmacop_result *out, void *hip_stream);
+
 /* Shared-mode state after the last gmacop_route_batch on this graph: the
  * pheromone and road load of every road (host arrays of n_edges entries,
  * either may be NULL).  Synchronises hip_stream. */

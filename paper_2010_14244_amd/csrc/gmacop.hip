@@ -30,6 +30,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1877,6 +1878,8 @@ struct gmacop_graph {
     uint32_t gen_count = 0;            // independent calls since the lazy array was cleared
     uint32_t last_mode = 0, last_nq = 0, last_iters = 0;
     gmacop_params last_p{};
+    const uint64_t *last_lazy = nullptr;   // independent mode: the last call's pheromone rows and generation
+    const uint32_t *last_gen = nullptr;
     // captured kernel sequence of the last GMACOP_HIP_GRAPH call and the key of its arguments
     hipGraphExec_t gexec = nullptr;
     std::vector<uint64_t> gkey;
@@ -2440,8 +2443,30 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
     return GMACOP_OK;
 }
 
-extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
-                                  gmacop_result *out, void *hip_stream)
+namespace {
+
+// Per-call workspace of a routing call: ant paths and results, the walkers'
+// work lists and visited words, and independent-mode pheromone rows.  The
+// allocating entry point takes it from buffers the graph grows on demand;
+// gmacop_route_batch_noalloc carves it out of the static scratch array.
+struct CallWork {
+    uint32_t *path = nullptr, *ant_len = nullptr, *ant_cost = nullptr, *gbits = nullptr;
+    uint64_t *iter_key = nullptr, *steps = nullptr;
+    uint32_t *best_path = nullptr, *best_len = nullptr, *best_cost = nullptr;
+    gmacop_od *od = nullptr;
+    uint8_t *vclass = nullptr;
+    GlbVeh *gveh = nullptr, *gvrec = nullptr;
+    uint32_t *gvlen = nullptr, *gctl = nullptr, *gepoch = nullptr;
+    uint64_t *gwords = nullptr;
+    uint64_t *lazy = nullptr, *dep_ind = nullptr;
+    uint32_t *touched = nullptr, *touched_n = nullptr, *dev_gen = nullptr;
+    bool side = false;          // the global walker may run on g->side beside the LDS walkers
+    bool allow_graph = false;   // GMACOP_HIP_GRAPH may capture and replay the call
+};
+
+// Checks shared by both routing entry points; on success *plan holds the walk schedule.
+int route_check(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p, const gmacop_result *out,
+                WalkPlan *plan)
 {
     if (!g) return fail(GMACOP_E_INVAL, "graph is NULL");
     if (!out || !out->path_edges || !out->path_len || !out->cost_ms || !out->steps_total)
@@ -2449,11 +2474,9 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     if (nq > 0 && !q) return fail(GMACOP_E_INVAL, "queries are NULL");
     int rc = validate_params(g, p, nq);
     if (rc) return rc;
-    const bool indep = p->mode == GMACOP_MODE_INDEPENDENT;
-    if (indep && p->iterations > kLazyIterMax)
+    if (p->mode == GMACOP_MODE_INDEPENDENT && p->iterations > kLazyIterMax)
         return fail(GMACOP_E_UNSUPPORTED, "independent mode supports at most %u iterations", kLazyIterMax);
-    const bool dev_ptrs = (p->flags & GMACOP_DEVICE_PTRS) != 0;
-    if (!dev_ptrs) {
+    if (!(p->flags & GMACOP_DEVICE_PTRS)) {
         for (uint32_t i = 0; i < nq; ++i) {
             if (q[i].qid == 0xFFFFFFFFu) return fail(GMACOP_E_INVAL, "query %u uses the reserved qid", i);
             if (q[i].src >= g->n || q[i].dst >= g->n) return fail(GMACOP_E_INVAL, "query %u: node out of range", i);
@@ -2463,15 +2486,21 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         }
     }
     HIP_TRY(hipSetDevice(g->device));
+    *plan = plan_walk(g, p, g->max_lds);
+    if (!plan->legacy && plan->glb && (rc = glb_grid(g->device, *plan, (uint64_t)nq * p->ants))) return rc;
+    return GMACOP_OK;
+}
+
+// Workspace of the allocating entry point: the graph's own buffers, grown to fit.
+int route_work_grow(gmacop_graph *g, uint32_t nq, const gmacop_params *p, const WalkPlan &plan, hipStream_t st,
+                    CallWork *w)
+{
+    int rc;
+    const bool indep = p->mode == GMACOP_MODE_INDEPENDENT;
     const uint32_t S = p->max_steps;
     const uint64_t NA = (uint64_t)nq * p->ants;
     const bool lds = g->n <= kLdsBitsetMaxNodes;
-    WalkPlan plan = plan_walk(g, p, g->max_lds);
-    if (!plan.legacy && plan.glb && (rc = glb_grid(g->device, plan, NA))) return rc;
-    hipStream_t st = (hipStream_t)hip_stream;
     const uint32_t nwords = (g->n + 31) / 32;
-
-    // workspace
     if ((rc = grow(&g->path, &g->cap_path, (size_t)S * NA, false))) return rc;
     {
         size_t c1 = g->cap_ants;
@@ -2490,10 +2519,6 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         HIP_TRY(hipEventCreateWithFlags(&g->join, hipEventDisableTiming));
     }
     if ((rc = grow(&g->vclass, &g->cap_vclass, std::max<size_t>(nq, 1), false))) return rc;
-    if (plan.city_class != g->city_class_dev) {   // per-city walker choice, uploaded when it changes
-        HIP_TRY(hipMemcpy(g->inst_fits, plan.city_class.data(), g->n_inst, hipMemcpyHostToDevice));
-        g->city_class_dev = plan.city_class;
-    }
     {
         size_t c1 = g->cap_veh, c2 = g->cap_veh, c3 = g->cap_veh, c4 = g->cap_veh;
         if ((rc = grow(&g->iter_key, &c1, nq, false)) || (rc = grow(&g->best_len, &c2, nq, false)) ||
@@ -2526,19 +2551,50 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         }
         g->gen_count++;
     }
+    w->path = g->path; w->ant_len = g->ant_len; w->ant_cost = g->ant_cost; w->gbits = g->gbits;
+    w->iter_key = g->iter_key; w->steps = g->steps;
+    w->best_path = g->best_path; w->best_len = g->best_len; w->best_cost = g->best_cost; w->od = g->od;
+    w->vclass = g->vclass;
+    w->gveh = g->glb.veh; w->gvrec = g->glb.vrec; w->gvlen = g->glb.vlen; w->gctl = g->glb.ctl;
+    w->gepoch = g->glb.epoch; w->gwords = g->glb.words;
+    w->lazy = g->lazy; w->dep_ind = g->dep_ind; w->touched = g->touched; w->touched_n = g->touched_n;
+    w->dev_gen = g->dev_gen;
+    w->side = true;
+    w->allow_graph = true;
+    return GMACOP_OK;
+}
+
+// The call itself, on workspace w: initial state and cost table, then per
+// iteration walk, best route, pheromone/load update, cost table; results to
+// the caller's buffers.
+int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p, gmacop_result *out,
+              hipStream_t st, const WalkPlan &plan, const CallWork &w)
+{
+    int rc;
+    const bool indep = p->mode == GMACOP_MODE_INDEPENDENT;
+    const bool dev_ptrs = (p->flags & GMACOP_DEVICE_PTRS) != 0;
+    const uint32_t S = p->max_steps;
+    const uint64_t NA = (uint64_t)nq * p->ants;
+    const bool lds = g->n <= kLdsBitsetMaxNodes;
+    const uint32_t nwords = (g->n + 31) / 32;
+    const uint32_t tcap = (uint32_t)std::min<uint64_t>(g->m, (uint64_t)p->ants * S);
+    if (plan.city_class != g->city_class_dev) {   // per-city walker choice, uploaded when it changes
+        HIP_TRY(hipMemcpy(g->inst_fits, plan.city_class.data(), g->n_inst, hipMemcpyHostToDevice));
+        g->city_class_dev = plan.city_class;
+    }
 
     const gmacop_od *od = q;
-    uint32_t *best_path = g->best_path, *best_len = g->best_len, *best_cost = g->best_cost;
-    uint64_t *steps = g->steps;
+    uint32_t *best_path = w.best_path, *best_len = w.best_len, *best_cost = w.best_cost;
+    uint64_t *steps = w.steps;
     if (dev_ptrs) {
         best_path = out->path_edges;
         best_len = out->path_len;
         best_cost = out->cost_ms;
         steps = out->steps_total;
     } else if (nq) {
-        HIP_TRY(hipMemcpyAsync(g->od, q, sizeof(gmacop_od) * nq, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(w.od, q, sizeof(gmacop_od) * nq, hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));   // the caller's queries are read before any later error returns
-        od = g->od;
+        od = w.od;
     }
 
     const bool load_update = !(p->flags & GMACOP_NO_LOAD_UPDATE);
@@ -2548,53 +2604,53 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost, mir};
     PherView pv{};
     pv.dense = indep ? nullptr : g->tau;
-    pv.lazy = g->lazy;
-    pv.gen = g->dev_gen;
+    pv.lazy = w.lazy;
+    pv.gen = w.dev_gen;
     pv.m = g->m; pv.tau0 = p->tau0_q16; pv.rho = p->rho_q16; pv.tau_min = p->tau_min_q16;
     DepView dv{};
-    dv.dep = indep ? g->dep_ind : g->dep;
-    dv.touched = g->touched; dv.touched_n = g->touched_n; dv.m = g->m; dv.cap = tcap; dv.indep = indep ? 1u : 0u;
+    dv.dep = indep ? w.dep_ind : g->dep;
+    dv.touched = w.touched; dv.touched_n = w.touched_n; dv.m = g->m; dv.cap = tcap; dv.indep = indep ? 1u : 0u;
     WalkArgs wa{};
     wa.row_ptr = g->row_ptr; wa.col = g->col; wa.cost = g->cost; wa.pher = pv; wa.depv = dv; wa.x = g->x; wa.y = g->y;
     wa.od = od; wa.n = g->n; wa.nq = nq; wa.ants = p->ants; wa.max_steps = S; wa.alpha = p->alpha; wa.beta = p->beta;
     wa.kgoal = p->vmax_kmh ? (uint32_t)((360ull << 16) / p->vmax_kmh) : 0;
     wa.nwords = nwords; wa.seed_lo = (uint32_t)p->seed; wa.seed_hi = (uint32_t)(p->seed >> 32);
-    wa.q_deposit = p->q_deposit; wa.path = g->path; wa.ant_len = g->ant_len; wa.ant_cost = g->ant_cost;
-    wa.gbits = g->gbits; wa.iter_key = g->iter_key; wa.steps = steps; wa.counters = g->counters;
+    wa.q_deposit = p->q_deposit; wa.path = w.path; wa.ant_len = w.ant_len; wa.ant_cost = w.ant_cost;
+    wa.gbits = w.gbits; wa.iter_key = w.iter_key; wa.steps = steps; wa.counters = g->counters;
     wa.iter_max = g->iter_max;
     LdsWalkArgs la{};
     la.row_ptr = g->row_ptr; la.col = g->col; la.cost = g->cost; la.pher = pv; la.depv = dv; la.x = g->x; la.y = g->y;
     la.rec = g->rec; la.tail = g->tail; la.rev_ptr = g->rev_ptr; la.rvs = g->rvs;
-    la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev; la.inst_eoff = g->inst_eoff_dev; la.vclass = g->vclass;
+    la.node_inst = g->node_inst; la.inst_off = g->inst_off_dev; la.inst_eoff = g->inst_eoff_dev; la.vclass = w.vclass;
     la.od = od; la.n = g->n; la.m = g->m; la.nq = nq; la.ants = p->ants; la.apb = plan.lds_apb; la.bpv = plan.lds_bpv;
     la.max_steps = S; la.alpha = p->alpha; la.beta = p->beta; la.kgoal = wa.kgoal; la.nwords = nwords;
-    la.seed_lo = wa.seed_lo; la.seed_hi = wa.seed_hi; la.q_deposit = p->q_deposit; la.path = g->path;
-    la.ant_len = g->ant_len; la.ant_cost = g->ant_cost; la.iter_key = g->iter_key;
+    la.seed_lo = wa.seed_lo; la.seed_hi = wa.seed_hi; la.q_deposit = p->q_deposit; la.path = w.path;
+    la.ant_len = w.ant_len; la.ant_cost = w.ant_cost; la.iter_key = w.iter_key;
     la.steps = steps; la.counters = g->counters; la.iter_max = g->iter_max;
     const bool update_loads = load_update && !indep;
-    BestArgs ba{nq, p->ants, S, update_loads ? 1u : 0u, g->iter_max, g->counters, g->path, g->ant_len, g->iter_key,
+    BestArgs ba{nq, p->ants, S, update_loads ? 1u : 0u, g->iter_max, g->counters, w.path, w.ant_len, w.iter_key,
                 best_path, best_len, best_cost, g->cnt};
     EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, update_loads ? 1u : 0u,
                 g->tau, g->load, g->cnt, g->base_load, g->dep, mir};
-    ApplyArgs aa{g->m, tcap, 0, p->tau0_q16, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, g->load, g->dev_gen,
-                 nullptr, nullptr, g->lazy, g->dep_ind, g->touched, g->touched_n};
+    ApplyArgs aa{g->m, tcap, 0, p->tau0_q16, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, g->load, w.dev_gen,
+                 nullptr, nullptr, w.lazy, w.dep_ind, w.touched, w.touched_n};
     GlbWalkArgs ga{};
     ga.rec32 = g->rec32; ga.pher = pv; ga.depv = dv;
-    ga.veh = g->glb.veh; ga.glb_n = g->glb.ctl; ga.tickets = g->glb.ctl + 1; ga.gwords = g->glb.words;
-    ga.vlen = g->glb.vlen;
-    ga.slot_epoch = g->glb.epoch; ga.m = g->m; ga.nq = nq;
+    ga.veh = w.gveh; ga.glb_n = w.gctl; ga.tickets = w.gctl ? w.gctl + 1 : nullptr; ga.gwords = w.gwords;
+    ga.vlen = w.gvlen;
+    ga.slot_epoch = w.gepoch; ga.m = g->m; ga.nq = nq;
     ga.ants = p->ants; ga.apb = plan.glb_apb; ga.max_steps = S; ga.alpha = p->alpha; ga.beta = p->beta;
     ga.kgoal = wa.kgoal; ga.nw2 = plan.glb_nwords; ga.bloom_log2 = plan.bloom_log2; ga.seed_lo = wa.seed_lo;
-    ga.seed_hi = wa.seed_hi; ga.q_deposit = p->q_deposit; ga.path = g->path; ga.ant_len = g->ant_len;
-    ga.ant_cost = g->ant_cost; ga.iter_key = g->iter_key; ga.steps = steps;
+    ga.seed_hi = wa.seed_hi; ga.q_deposit = p->q_deposit; ga.path = w.path; ga.ant_len = w.ant_len;
+    ga.ant_cost = w.ant_cost; ga.iter_key = w.iter_key; ga.steps = steps;
     ga.counters = g->counters; ga.iter_max = g->iter_max;
-    const GlbListArgs gla{od, g->vclass, g->row_ptr, g->node_lo, g->x, g->y, nq, p->ants, wa.kgoal,
-                          g->glb.vrec, g->glb.veh, g->glb.ctl, g->glb.vlen, g->ant_len, g->ant_cost};
+    const GlbListArgs gla{od, w.vclass, g->row_ptr, g->node_lo, g->x, g->y, nq, p->ants, wa.kgoal,
+                          w.gvrec, w.gveh, w.gctl, w.gvlen, w.ant_len, w.ant_cost};
     const bool any_lds = !plan.legacy && plan.any_lds();
     if (any_lds && (rc = setup_walk_lds(la, plan, st))) return rc;
 
     const bool timing = (p->flags & GMACOP_TIME_KERNELS) != 0;
-    const bool use_graph = (p->flags & GMACOP_HIP_GRAPH) && !timing && st != nullptr;
+    const bool use_graph = w.allow_graph && (p->flags & GMACOP_HIP_GRAPH) && !timing && st != nullptr;
     // The whole call as one kernel sequence on `st`: initial state and cost
     // table, then per iteration walk, best route, pheromone/load, cost table.
     auto enqueue = [&]() -> int {
@@ -2602,13 +2658,13 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         KernelTimer kt{g, st, timing};
         gmacop_graph::Timed tm{}, tl{};
         hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ia);
-        if (indep && nq) hipLaunchKernelGGL(k_next_generation, dim3(1), dim3(64), 0, st, g->dev_gen);
+        if (indep && nq) hipLaunchKernelGGL(k_next_generation, dim3(1), dim3(64), 0, st, w.dev_gen);
         hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
-                           best_len, best_cost, g->iter_key, steps);
+                           best_len, best_cost, w.iter_key, steps);
         hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
         if (nq && !plan.legacy) {
             hipLaunchKernelGGL(k_classify, dim3(blocks_for(nq, 256)), dim3(256), 0, st, od, nq, g->n,
-                               (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, g->vclass);
+                               (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, w.vclass);
             if (plan.glb) hipLaunchKernelGGL(k_glb_prep, dim3(blocks_for(nq, 256)), dim3(256), 0, st, gla);
         }
         HIP_TRY(hipGetLastError());
@@ -2629,7 +2685,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
                                      : launch_walk<32>(wt, lds, st);
                 } else {
                     // both kinds of walker: the global one on the side stream, beside the LDS ones
-                    const bool both = plan.glb && plan.any_lds();
+                    const bool both = w.side && plan.glb && plan.any_lds();
                     hipStream_t gst = both ? g->side : st;
                     KernelTimer kg{g, gst, timing};
                     gmacop_graph::Timed tg{};
@@ -2679,19 +2735,20 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
         // key: every value the captured launches depend on
         std::vector<uint64_t> key = {
             (uint64_t)(uintptr_t)od, (uint64_t)(uintptr_t)best_path, (uint64_t)(uintptr_t)best_len,
-            (uint64_t)(uintptr_t)best_cost, (uint64_t)(uintptr_t)steps, (uint64_t)(uintptr_t)g->path,
-            (uint64_t)(uintptr_t)g->ant_len, (uint64_t)(uintptr_t)g->ant_cost, (uint64_t)(uintptr_t)g->gbits,
-            (uint64_t)(uintptr_t)g->iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
+            (uint64_t)(uintptr_t)best_cost, (uint64_t)(uintptr_t)steps, (uint64_t)(uintptr_t)w.path,
+            (uint64_t)(uintptr_t)w.ant_len, (uint64_t)(uintptr_t)w.ant_cost, (uint64_t)(uintptr_t)w.gbits,
+            (uint64_t)(uintptr_t)w.iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
             p->rho_q16, p->tau0_q16, p->tau_min_q16, p->tau_max_q16, p->q_deposit, p->theta, p->th_max,
             p->t_max_ms, p->vmax_kmh, p->mode, p->flags & GMACOP_NO_LOAD_UPDATE, p->seed, p->iter_offset,
             plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.road_maxd,
             (uint64_t)plan.lds_bytes[1], (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3],
-            (uint64_t)plan.lds_bytes[4], (uint64_t)plan.lds_bytes[5], (uint64_t)plan.lds_bytes[6], plan.glb, plan.glb_lanes, plan.glb_apb,
-            plan.bloom_log2, plan.glb_nwords, plan.glb_blocks, (uint64_t)(uintptr_t)g->glb.veh, (uint64_t)(uintptr_t)g->glb.vrec, (uint64_t)(uintptr_t)g->glb.vlen,
-            (uint64_t)(uintptr_t)g->glb.ctl, (uint64_t)(uintptr_t)g->glb.words, (uint64_t)(uintptr_t)g->glb.epoch,
-            (uint64_t)lds, (uint64_t)(uintptr_t)g->vclass,
-            (uint64_t)(uintptr_t)g->lazy, (uint64_t)(uintptr_t)g->dep_ind, (uint64_t)(uintptr_t)g->touched,
-            (uint64_t)(uintptr_t)g->touched_n, (uint64_t)(uintptr_t)g->dev_gen, tcap};
+            (uint64_t)plan.lds_bytes[4], (uint64_t)plan.lds_bytes[5], (uint64_t)plan.lds_bytes[6], plan.glb,
+            plan.glb_lanes, plan.glb_apb, plan.bloom_log2, plan.glb_nwords, plan.glb_blocks,
+            (uint64_t)(uintptr_t)w.gveh, (uint64_t)(uintptr_t)w.gvrec, (uint64_t)(uintptr_t)w.gvlen,
+            (uint64_t)(uintptr_t)w.gctl, (uint64_t)(uintptr_t)w.gwords, (uint64_t)(uintptr_t)w.gepoch,
+            (uint64_t)lds, (uint64_t)(uintptr_t)w.vclass,
+            (uint64_t)(uintptr_t)w.lazy, (uint64_t)(uintptr_t)w.dep_ind, (uint64_t)(uintptr_t)w.touched,
+            (uint64_t)(uintptr_t)w.touched_n, (uint64_t)(uintptr_t)w.dev_gen, tcap, (uint64_t)w.side};
         if (!g->gexec || key != g->gkey) {
             if (g->gexec) {
                 (void)hipGraphExecDestroy(g->gexec);
@@ -2745,13 +2802,192 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     g->last_nq = nq;
     g->last_iters = p->iterations;
     g->last_p = *p;
+    g->last_lazy = indep ? w.lazy : nullptr;
+    g->last_gen = indep ? w.dev_gen : nullptr;
     return GMACOP_OK;
+}
+
+// ---- the allocation-free variant: workspace in a static device array ----
+
+// Per-call workspace of gmacop_route_batch_noalloc.  One copy per GPU, held
+// from the library's first use of that GPU until the process ends.  Host code
+// never passes this name to a kernel: its device address comes from
+// hipGetSymbolAddress, taken once per device.
+}  // namespace
+static __device__ __align__(256) uint64_t scratch[GMACOP_NOALLOC_SCRATCH_BYTES / sizeof(uint64_t)];
+namespace {
+
+// What the host remembers about each device's scratch: its device address,
+// and the layout and generation count of the regions whose contents carry
+// over from one call to the next (visited words and epochs of the global
+// walker, independent-mode pheromone rows).
+struct ScratchDevice {
+    void *ptr = nullptr;
+    std::vector<uint64_t> layout;
+    uint32_t gen_count = 0;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+ScratchDevice g_scratch[kMaxDevices];
+
+__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int fill_u32(void *p, size_t words, hipStream_t st)
+{
+    if (!words) return GMACOP_OK;
+    const unsigned grid = (unsigned)std::min<uint64_t>(blocks_for(words, 256), 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, (uint32_t *)p, words, 0u);
+    HIP_TRY(hipGetLastError());
+    return GMACOP_OK;
+}
+
+// Consecutive 256-byte aligned pieces of one buffer (base NULL: sizes only).
+struct Carver {
+    uint8_t *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+};
+
+// The workspace layout of one call; the regions that keep state across calls come first.
+size_t carve_work(uint8_t *base, gmacop_graph *g, uint32_t nq, const gmacop_params *p, const WalkPlan &plan,
+                  CallWork *w)
+{
+    const bool indep = p->mode == GMACOP_MODE_INDEPENDENT;
+    const bool dev_ptrs = (p->flags & GMACOP_DEVICE_PTRS) != 0;
+    const uint32_t S = p->max_steps;
+    const uint64_t NA = (uint64_t)nq * p->ants;
+    const uint32_t tcap = (uint32_t)std::min<uint64_t>(g->m, (uint64_t)p->ants * S);
+    Carver c{base};
+    CallWork x{};
+    if (plan.glb) {
+        const uint64_t slots = (uint64_t)plan.glb_blocks * plan.glb_apb;
+        x.gctl = c.take<uint32_t>(3);
+        x.gepoch = c.take<uint32_t>(slots);
+        x.gwords = c.take<uint64_t>(slots * plan.glb_nwords);
+    }
+    if (indep && nq) {
+        x.dev_gen = c.take<uint32_t>(1);
+        x.lazy = c.take<uint64_t>((size_t)nq * g->m);
+        x.dep_ind = c.take<uint64_t>((size_t)nq * g->m);
+        x.touched_n = c.take<uint32_t>(nq);
+        x.touched = c.take<uint32_t>((size_t)nq * tcap);
+    }
+    x.path = c.take<uint32_t>((size_t)S * NA);
+    x.ant_len = c.take<uint32_t>(NA);
+    x.ant_cost = c.take<uint32_t>(NA);
+    x.iter_key = c.take<uint64_t>(nq);
+    x.vclass = c.take<uint8_t>(nq);
+    if (plan.glb) {
+        x.gveh = c.take<GlbVeh>(nq);
+        x.gvrec = c.take<GlbVeh>(nq);
+        x.gvlen = c.take<uint32_t>(nq);
+    }
+    if (!dev_ptrs) {
+        x.best_path = c.take<uint32_t>((size_t)nq * S);
+        x.best_len = c.take<uint32_t>(nq);
+        x.best_cost = c.take<uint32_t>(nq);
+        x.od = c.take<gmacop_od>(nq);
+        x.steps = c.take<uint64_t>(1);
+    }
+    if (w) *w = x;
+    return c.off;
+}
+
+}  // namespace
+
+extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
+                                  gmacop_result *out, void *hip_stream)
+{
+    WalkPlan plan;
+    int rc = route_check(g, q, nq, p, out, &plan);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    CallWork w;
+    if ((rc = route_work_grow(g, nq, p, plan, st, &w))) return rc;
+    return route_run(g, q, nq, p, out, st, plan, w);
+}
+
+extern "C" int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
+                                          gmacop_result *out, void *hip_stream)
+{
+    if (p && (p->flags & (GMACOP_HIP_GRAPH | GMACOP_TIME_KERNELS)))
+        return fail(GMACOP_E_INVAL, "gmacop_route_batch_noalloc takes neither GMACOP_HIP_GRAPH nor GMACOP_TIME_KERNELS");
+    WalkPlan plan;
+    int rc = route_check(g, q, nq, p, out, &plan);
+    if (rc) return rc;
+    if (plan.legacy)
+        return fail(GMACOP_E_UNSUPPORTED, "gmacop_route_batch_noalloc needs a graph under 2^24 nodes");
+    if (plan.glb) {
+        // a smaller resident grid of the global walker keeps its visited words within half the scratch
+        const uint64_t per_block = (uint64_t)plan.glb_apb * (std::max<uint32_t>(plan.glb_nwords, 1) * 8ull + 4);
+        const uint64_t cap = std::max<uint64_t>(1, (GMACOP_NOALLOC_SCRATCH_BYTES / 2) / per_block);
+        plan.glb_blocks = (uint32_t)std::min<uint64_t>(plan.glb_blocks, cap);
+    }
+    const size_t need = carve_work(nullptr, g, nq, p, plan, nullptr);
+    if (need > GMACOP_NOALLOC_SCRATCH_BYTES)
+        return fail(GMACOP_E_NOMEM, "call needs %zu bytes of workspace; gmacop_route_batch_noalloc has %llu", need,
+                    (unsigned long long)GMACOP_NOALLOC_SCRATCH_BYTES);
+    if (g->device < 0 || g->device >= kMaxDevices) return fail(GMACOP_E_UNSUPPORTED, "device %d", g->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchDevice &sd = g_scratch[g->device];
+    if (!sd.ptr) {   // first call on this device (it is current: route_check set it)
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(GMACOP_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        sd.ptr = ptr;
+    }
+    CallWork w;
+    carve_work((uint8_t *)sd.ptr, g, nq, p, plan, &w);
+    const bool indep = p->mode == GMACOP_MODE_INDEPENDENT && nq;
+    // regions that carry state from call to call start over when their place or size changes
+    const std::vector<uint64_t> layout = {
+        (uint64_t)(uintptr_t)w.gepoch, (uint64_t)(uintptr_t)w.gwords,
+        plan.glb ? (uint64_t)plan.glb_blocks * plan.glb_apb : 0, plan.glb ? plan.glb_nwords : 0,
+        (uint64_t)(uintptr_t)w.lazy, indep ? (uint64_t)nq * g->m : 0, (uint64_t)(uintptr_t)w.dev_gen};
+    if (layout != sd.layout || (indep && sd.gen_count >= kGenMask)) {
+        if (plan.glb) {
+            const uint64_t slots = (uint64_t)plan.glb_blocks * plan.glb_apb;
+            if ((rc = fill_u32(w.gepoch, slots, st)) || (rc = fill_u32(w.gwords, 2 * slots * plan.glb_nwords, st)))
+                return rc;
+        }
+        if (indep) {
+            const size_t rows = (size_t)nq * g->m;
+            if ((rc = fill_u32(w.dev_gen, 1, st)) || (rc = fill_u32(w.lazy, 2 * rows, st)) ||
+                (rc = fill_u32(w.dep_ind, 2 * rows, st)) || (rc = fill_u32(w.touched_n, nq, st)))
+                return rc;
+        }
+        sd.layout = layout;
+        sd.gen_count = 0;
+    }
+    if (plan.glb) {   // ticket counters, and the walk lengths that order the first list
+        if ((rc = fill_u32(w.gctl, 3, st)) || (rc = fill_u32(w.gvlen, std::max<uint32_t>(nq, 1), st))) return rc;
+    }
+    if (indep) sd.gen_count++;
+    w.side = false;
+    w.allow_graph = false;
+    rc = route_run(g, q, nq, p, out, st, plan, w);
+    g->last_lazy = nullptr;   // the rows live in the shared workspace: no gmacop_vehicle_tau_get after this call
+    g->last_gen = nullptr;
+    return rc;
 }
 
 extern "C" int gmacop_vehicle_tau_get(gmacop_graph *g, uint32_t vehicle, uint32_t *tau_q16, void *hip_stream)
 {
     if (!g || !tau_q16) return fail(GMACOP_E_INVAL, "graph or output is NULL");
-    if (g->last_mode != GMACOP_MODE_INDEPENDENT || vehicle >= g->last_nq)
+    if (g->last_mode != GMACOP_MODE_INDEPENDENT || vehicle >= g->last_nq || !g->last_lazy)
         return fail(GMACOP_E_INVAL, "no independent-mode vehicle %u in the last call", vehicle);
     HIP_TRY(hipSetDevice(g->device));
     hipStream_t st = (hipStream_t)hip_stream;
@@ -2759,8 +2995,8 @@ extern "C" int gmacop_vehicle_tau_get(gmacop_graph *g, uint32_t vehicle, uint32_
     int rc = dalloc(&tmp, g->m);
     if (rc) return rc;
     const gmacop_params &p = g->last_p;
-    hipLaunchKernelGGL(k_materialize, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, g->lazy + (size_t)vehicle * g->m,
-                       (const uint32_t *)g->dev_gen, g->m, g->last_iters, p.tau0_q16, p.rho_q16, p.tau_min_q16, tmp);
+    hipLaunchKernelGGL(k_materialize, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, g->last_lazy + (size_t)vehicle * g->m,
+                       g->last_gen, g->m, g->last_iters, p.tau0_q16, p.rho_q16, p.tau_min_q16, tmp);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(tau_q16, tmp, sizeof(uint32_t) * g->m, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

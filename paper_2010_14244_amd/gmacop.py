@@ -31,7 +31,7 @@ DEVICE_PTRS = 2
 TIME_KERNELS = 4
 HIP_GRAPH = 8
 
-EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_state_get", "gmacop_vehicle_tau_get",
+EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_route_batch_noalloc", "gmacop_state_get", "gmacop_vehicle_tau_get",
             "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
             "gmacop_server_release", "gmacop_release", "gmacop_last_error")
 KERNELS = ("walk", "best", "edge", "cost", "walk_lds", "walk_glb")
@@ -96,6 +96,8 @@ def lib():
         L.gmacop_graph_create.restype = C.c_int
         L.gmacop_route_batch.argtypes = [vp, vp, C.c_uint32, C.POINTER(_Params), C.POINTER(_Result), vp]
         L.gmacop_route_batch.restype = C.c_int
+        L.gmacop_route_batch_noalloc.argtypes = [vp, vp, C.c_uint32, C.POINTER(_Params), C.POINTER(_Result), vp]
+        L.gmacop_route_batch_noalloc.restype = C.c_int
         L.gmacop_state_get.argtypes = [vp, vp, vp, vp]
         L.gmacop_state_get.restype = C.c_int
         L.gmacop_vehicle_tau_get.argtypes = [vp, C.c_uint32, vp, vp]
@@ -174,6 +176,16 @@ def _od_array(veh) -> np.ndarray:
 def gmacop_route_batch(g: Graph, veh, p: dict, stream: Optional[int] = None) -> dict:
     """Route the vehicles with host buffers (synchronous).  Returns dict with
     path_edges [V, max_steps], path_len [V], cost_ms [V], steps_total."""
+    return _route_host(lib().gmacop_route_batch, g, veh, p, stream)
+
+
+def gmacop_route_batch_noalloc(g: Graph, veh, p: dict, stream: Optional[int] = None) -> dict:
+    """gmacop_route_batch on the library's static per-GPU workspace (no
+    device allocation); host buffers, synchronous."""
+    return _route_host(lib().gmacop_route_batch_noalloc, g, veh, p, stream)
+
+
+def _route_host(fn, g: Graph, veh, p: dict, stream: Optional[int]) -> dict:
     od = _od_array(veh)
     V, S = od.shape[0], int(p["max_steps"])
     path = np.zeros((V, max(S, 1)), np.uint32)
@@ -182,7 +194,7 @@ def gmacop_route_batch(g: Graph, veh, p: dict, stream: Optional[int] = None) -> 
     steps = np.zeros(1, np.uint64)
     res = _Result(path.ctypes.data, plen.ctypes.data, cost.ctypes.data, steps.ctypes.data)
     pp = _params(dict(p, flags=int(p.get("flags", 0)) & ~DEVICE_PTRS))
-    _check(lib().gmacop_route_batch(g.handle, od.ctypes.data if V else None, V, C.byref(pp), C.byref(res), stream))
+    _check(fn(g.handle, od.ctypes.data if V else None, V, C.byref(pp), C.byref(res), stream))
     return dict(path_edges=path, path_len=plen, cost_ms=cost, steps_total=int(steps[0]))
 
 
@@ -207,15 +219,17 @@ class DeviceBatch:
                     cost_ms=self.cost.cpu().numpy().view(np.uint32), steps_total=int(self.steps.cpu().item()))
 
 
-def gmacop_route_batch_device(g: Graph, b: DeviceBatch, p: dict, stream: Optional[int] = None) -> None:
-    """Enqueue a routing call on ``stream`` with device buffers (no sync)."""
+def gmacop_route_batch_device(g: Graph, b: DeviceBatch, p: dict, stream: Optional[int] = None,
+                              noalloc: bool = False) -> None:
+    """Enqueue a routing call on ``stream`` with device buffers (no sync);
+    ``noalloc`` calls gmacop_route_batch_noalloc."""
     import torch
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     res = _Result(b.path.data_ptr(), b.path_len.data_ptr(), b.cost.data_ptr(), b.steps.data_ptr())
     pp = _params(dict(p, flags=int(p.get("flags", 0)) | DEVICE_PTRS))
-    _check(lib().gmacop_route_batch(g.handle, b.od.data_ptr() if b.V else None, b.V, C.byref(pp), C.byref(res),
-                                    stream))
+    fn = lib().gmacop_route_batch_noalloc if noalloc else lib().gmacop_route_batch
+    _check(fn(g.handle, b.od.data_ptr() if b.V else None, b.V, C.byref(pp), C.byref(res), stream))
 
 
 def gmacop_state_get(g: Graph, stream: Optional[int] = None):
