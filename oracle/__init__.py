@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "libgmacop_oracle.so")
 MODE_SHARED = 0
 MODE_INDEPENDENT = 1
 FLAG_NO_LOAD_UPDATE = 1
+FLAG_GOAL_EXACT = 16
 
 E_INVAL = -1
 E_RANGE = -2
@@ -78,6 +79,7 @@ def lib():
         L.orc_cost_table.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.orc_goal.argtypes = [vp, vp, u32, u32]
         L.orc_goal.restype = u64
+        L.orc_goal_exact.argtypes = [vp, vp, u32, vp]
         L.orc_eta.argtypes = [C.c_int64]
         L.orc_eta.restype = u32
         L.orc_roulette.argtypes = [vp, u32, u64]
@@ -158,6 +160,15 @@ def cost_table(g, p: dict, load: np.ndarray):
 def goal(g, p: dict, node: int, dst: int) -> int:
     gr, pp = _GraphRef(g), _params(p)
     return int(lib().orc_goal(C.byref(gr.s), C.byref(pp), node, dst))
+
+
+def goal_exact(g, p: dict, dst: int) -> np.ndarray:
+    """Exact goal row for destination dst: uint32 [n] shortest free-flow
+    time to dst (0xFFFFFFFF where dst cannot be reached)."""
+    gr, pp = _GraphRef(g), _params(p)
+    h = np.zeros(gr.n, np.uint32)
+    lib().orc_goal_exact(C.byref(gr.s), C.byref(pp), int(dst), _ptr(h))
+    return h
 
 
 def eta(delta: int) -> int:

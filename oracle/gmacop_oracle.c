@@ -152,6 +152,93 @@ uint64_t orc_goal(const orc_graph *g, const orc_params *p, uint32_t node, uint32
     return orc_isqrt(d2) * k >> 16;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Exact goal term (Section 4.2, Alg. 2 step 1: Calc_Dist computes the      */
+/* distance from any node to the destination over the road network).  Here  */
+/* the distance is the shortest free-flow travel time to dst, each road     */
+/* weighted by its free-flow time t0 (the static part of its cost, so the   */
+/* term never exceeds the true remaining cost).  Dijkstra from dst over the */
+/* reversed roads, with a binary heap; sums are exact in 64 bits and        */
+/* reported as min(sum, 0xFFFFFFFE); a node from which dst cannot be        */
+/* reached gets 0xFFFFFFFF.                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint64_t d; uint32_t v; } heap_item;
+
+static void heap_push(heap_item *h, uint32_t *n, heap_item x)
+{
+    uint32_t i = (*n)++;
+    h[i] = x;
+    while (i > 0) {
+        const uint32_t up = (i - 1) / 2;
+        if (h[up].d <= h[i].d) break;
+        const heap_item t = h[up]; h[up] = h[i]; h[i] = t;
+        i = up;
+    }
+}
+
+static heap_item heap_pop(heap_item *h, uint32_t *n)
+{
+    const heap_item top = h[0];
+    h[0] = h[--(*n)];
+    uint32_t i = 0;
+    for (;;) {
+        const uint32_t a = 2 * i + 1, b = 2 * i + 2;
+        uint32_t s = i;
+        if (a < *n && h[a].d < h[s].d) s = a;
+        if (b < *n && h[b].d < h[s].d) s = b;
+        if (s == i) break;
+        const heap_item t = h[s]; h[s] = h[i]; h[i] = t;
+        i = s;
+    }
+    return top;
+}
+
+void orc_goal_exact(const orc_graph *g, const orc_params *p, uint32_t dst, uint32_t *h)
+{
+    const uint32_t n = g->n, m = g->m;
+    uint32_t *t0 = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *wf = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    orc_edge_static(g, p, t0, wf);
+    /* reversed roads: for each node x, the roads u -> x, as (u, t0) */
+    uint32_t *rp = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
+    uint32_t *ru = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *rw = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    for (uint32_t e = 0; e < m; ++e) rp[g->col[e] + 1]++;
+    for (uint32_t x = 0; x < n; ++x) rp[x + 1] += rp[x];
+    uint32_t *fill = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+    memcpy(fill, rp, sizeof(uint32_t) * n);
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e) {
+            const uint32_t x = g->col[e];
+            ru[fill[x]] = u;
+            rw[fill[x]] = t0[e];
+            fill[x]++;
+        }
+    uint64_t *dist = (uint64_t *)malloc(sizeof(uint64_t) * n);
+    uint8_t *done = (uint8_t *)calloc(n, 1);
+    heap_item *heap = (heap_item *)malloc(sizeof(heap_item) * (m + 2));
+    uint32_t hn = 0;
+    for (uint32_t v = 0; v < n; ++v) dist[v] = UINT64_MAX;
+    dist[dst] = 0;
+    heap_push(heap, &hn, (heap_item){0, dst});
+    while (hn) {
+        const heap_item it = heap_pop(heap, &hn);
+        if (done[it.v]) continue;
+        done[it.v] = 1;
+        for (uint32_t i = rp[it.v]; i < rp[it.v + 1]; ++i) {
+            const uint32_t u = ru[i];
+            const uint64_t nd = it.d + rw[i];
+            if (!done[u] && nd < dist[u]) {
+                dist[u] = nd;
+                heap_push(heap, &hn, (heap_item){nd, u});
+            }
+        }
+    }
+    for (uint32_t v = 0; v < n; ++v)
+        h[v] = dist[v] == UINT64_MAX ? U32_MAX : (dist[v] > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)dist[v]);
+    free(t0); free(wf); free(rp); free(ru); free(rw); free(fill); free(dist); free(done); free(heap);
+}
+
 /* Desirability of a road from its reduced cost delta = cost + h(head) - h(tail):
  * eta = floor(2^26 / max(delta, 1)), clamped to [1, 65535]. */
 uint32_t orc_eta(int64_t delta)
@@ -210,8 +297,15 @@ uint32_t orc_apply_tau(const orc_params *p, uint32_t tau, uint64_t deposit, uint
 static uint8_t *g_visited;          /* scratch, n bytes, all zero between walks */
 static uint32_t g_visited_n;
 
+/* Goal term of node x: the exact row when the call uses one, else the
+ * straight-line estimate. */
+static int64_t goal_of(const orc_graph *g, const orc_params *p, const uint32_t *hrow, uint32_t x, uint32_t dst)
+{
+    return hrow ? (int64_t)hrow[x] : (int64_t)orc_goal(g, p, x, dst);
+}
+
 static int walk_impl(const orc_graph *g, const orc_params *p, const uint32_t *tau, const uint32_t *cost,
-                     uint32_t qid, uint32_t src, uint32_t dst, uint32_t ant, uint32_t iter,
+                     const uint32_t *hrow, uint32_t qid, uint32_t src, uint32_t dst, uint32_t ant, uint32_t iter,
                      uint32_t *path, uint32_t *len, uint32_t *cost_sum, uint64_t *selections,
                      uint64_t *wbuf)
 {
@@ -219,7 +313,7 @@ static int walk_impl(const orc_graph *g, const orc_params *p, const uint32_t *ta
     uint32_t u = src, s = 0, cs = 0;
     int ok = 0;
     visited[u] = 1;
-    int64_t hu = (int64_t)orc_goal(g, p, u, dst);
+    int64_t hu = goal_of(g, p, hrow, u, dst);
     for (;;) {
         if (s == p->max_steps) break;
         const uint32_t rs = g->row_ptr[u], d = g->row_ptr[u + 1] - rs;
@@ -227,7 +321,7 @@ static int walk_impl(const orc_graph *g, const orc_params *p, const uint32_t *ta
         for (uint32_t j = 0; j < d; ++j) {
             const uint32_t e = rs + j, x = g->col[e];
             if (visited[x]) { wbuf[j] = 0; continue; }
-            const int64_t delta = (int64_t)cost[e] + (int64_t)orc_goal(g, p, x, dst) - hu;
+            const int64_t delta = (int64_t)cost[e] + goal_of(g, p, hrow, x, dst) - hu;
             wbuf[j] = ipow(tau[e], p->alpha) * ipow(orc_eta(delta), p->beta);
             T += wbuf[j];
         }
@@ -240,7 +334,7 @@ static int walk_impl(const orc_graph *g, const orc_params *p, const uint32_t *ta
         cs = c > PATH_COST_CAP ? PATH_COST_CAP : (uint32_t)c;
         u = g->col[e];
         visited[u] = 1;
-        hu = (int64_t)orc_goal(g, p, u, dst);
+        hu = goal_of(g, p, hrow, u, dst);
         if (u == dst) { ok = 1; break; }
     }
     /* clear the visited marks of this walk */
@@ -276,8 +370,14 @@ int orc_walk(const orc_graph *g, const orc_params *p, const uint32_t *tau, const
 {
     ensure_visited(g->n);
     uint64_t *wbuf = (uint64_t *)malloc(sizeof(uint64_t) * (max_out_degree(g) + 1));
-    const int ok = walk_impl(g, p, tau, cost, qid, src, dst, ant, iter, path, len, cost_sum, selections, wbuf);
+    uint32_t *hrow = NULL;
+    if (p->flags & ORC_FLAG_GOAL_EXACT) {
+        hrow = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
+        orc_goal_exact(g, p, dst, hrow);
+    }
+    const int ok = walk_impl(g, p, tau, cost, hrow, qid, src, dst, ant, iter, path, len, cost_sum, selections, wbuf);
     free(wbuf);
+    free(hrow);
     return ok;
 }
 
@@ -323,7 +423,7 @@ typedef struct {
 } route_ctx;
 
 static void vehicle_iteration(route_ctx *c, uint32_t qid, uint32_t src, uint32_t dst, uint32_t t,
-                              const uint32_t *tau, const uint32_t *cost, uint64_t *dep,
+                              const uint32_t *tau, const uint32_t *cost, const uint32_t *hrow, uint64_t *dep,
                               uint32_t *best_path, uint32_t *best_len, uint32_t *best_cost)
 {
     const orc_params *p = c->p;
@@ -331,7 +431,7 @@ static void vehicle_iteration(route_ctx *c, uint32_t qid, uint32_t src, uint32_t
     uint32_t iter_len = 0;
     for (uint32_t k = 0; k < p->ants; ++k) {
         uint32_t len, cs;
-        if (!walk_impl(c->g, p, tau, cost, qid, src, dst, k, t, c->ant_path, &len, &cs, &c->steps, c->wbuf))
+        if (!walk_impl(c->g, p, tau, cost, hrow, qid, src, dst, k, t, c->ant_path, &len, &cs, &c->steps, c->wbuf))
             continue;
         const uint64_t key = ((uint64_t)cs << 32) | k;
         if (key < iter_key) {
@@ -380,6 +480,14 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
     const uint32_t n_tau = shared ? 1 : nv;
     uint32_t *tau = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)n_tau * m + 1));
 
+    /* Calc_Dist (Alg. 2 step 1), once per call: the exact goal row of each vehicle */
+    uint32_t *hrows = NULL;
+    if (p->flags & ORC_FLAG_GOAL_EXACT) {
+        hrows = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)nv * g->n + 1));
+        for (uint32_t v = 0; v < nv; ++v) orc_goal_exact(g, p, dst[v], hrows + (size_t)v * g->n);
+    }
+#define HROW(v) (hrows ? hrows + (size_t)(v) * g->n : NULL)
+
     orc_edge_static(g, p, t0, wf);
     for (uint32_t e = 0; e < m; ++e) load[e] = g->base_load[e];
     for (size_t i = 0; i < (size_t)n_tau * m; ++i) tau[i] = p->tau0_q16;
@@ -390,7 +498,7 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
             orc_cost_table(g, p, load, t0, wf, cost, NULL);
             memset(dep, 0, sizeof(uint64_t) * m);
             for (uint32_t v = 0; v < nv; ++v) {
-                vehicle_iteration(&c, qid[v], src[v], dst[v], t, tau, cost, dep,
+                vehicle_iteration(&c, qid[v], src[v], dst[v], t, tau, cost, HROW(v), dep,
                                   path_edges + (size_t)v * S, &path_len[v], &cost_ms[v]);
                 if (best_hist) best_hist[(size_t)t * nv + v] = cost_ms[v];
             }
@@ -407,7 +515,7 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
             uint32_t *tv = tau + (size_t)v * m;
             for (uint32_t t = 0; t < p->iterations; ++t) {
                 memset(dep, 0, sizeof(uint64_t) * m);
-                vehicle_iteration(&c, qid[v], src[v], dst[v], t, tv, cost, dep,
+                vehicle_iteration(&c, qid[v], src[v], dst[v], t, tv, cost, HROW(v), dep,
                                   path_edges + (size_t)v * S, &path_len[v], &cost_ms[v]);
                 if (best_hist) best_hist[(size_t)t * nv + v] = cost_ms[v];
                 for (uint32_t e = 0; e < m; ++e) tv[e] = orc_apply_tau(p, tv[e], dep[e], load[e]);
@@ -419,6 +527,7 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
     if (tau_out) memcpy(tau_out, tau, sizeof(uint32_t) * (size_t)n_tau * m);
     if (load_out) memcpy(load_out, load, sizeof(uint32_t) * m);
     free(c.wbuf); free(c.ant_path); free(c.iter_path);
-    free(t0); free(wf); free(cost); free(load); free(dep); free(tau);
+    free(t0); free(wf); free(cost); free(load); free(dep); free(tau); free(hrows);
+#undef HROW
     return 0;
 }

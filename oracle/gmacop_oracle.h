@@ -44,7 +44,8 @@ typedef struct {
     uint64_t q_deposit;
     uint32_t theta, th_max, t_max_ms, vmax_kmh;
     uint32_t mode;          /* 0 = shared pheromone/load, 1 = independent per vehicle */
-    uint32_t flags;         /* bit 0: loads frozen at base_load */
+    uint32_t flags;         /* ORC_FLAG_NO_LOAD_UPDATE: loads frozen at base_load;
+                               ORC_FLAG_GOAL_EXACT: exact goal term instead of the straight line */
     uint64_t seed;
     uint32_t iter_offset;
 } orc_params;
@@ -52,6 +53,7 @@ typedef struct {
 #define ORC_MODE_SHARED      0u
 #define ORC_MODE_INDEPENDENT 1u
 #define ORC_FLAG_NO_LOAD_UPDATE 1u
+#define ORC_FLAG_GOAL_EXACT 16u   /* goal term = exact shortest free-flow time to dst */
 
 /* Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -66,6 +68,9 @@ void orc_cost_table(const orc_graph *g, const orc_params *p, const uint32_t *loa
                     uint8_t *preempted /* may be NULL */);
 /* Goal term h(node) for destination dst (time-to-go lower bound, ms). */
 uint64_t orc_goal(const orc_graph *g, const orc_params *p, uint32_t node, uint32_t dst);
+/* Exact goal row for destination dst: shortest free-flow time (sum of t0)
+ * from every node to dst, min(.., 0xFFFFFFFE); 0xFFFFFFFF = cannot reach dst. */
+void orc_goal_exact(const orc_graph *g, const orc_params *p, uint32_t dst, uint32_t *h);
 /* Heuristic desirability of a road from its reduced cost. */
 uint32_t orc_eta(int64_t delta);
 /* Roulette: index chosen among d weights by a 64-bit random word. */

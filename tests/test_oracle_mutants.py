@@ -32,6 +32,25 @@ MUTANTS = {
     "counter_swap": ("const uint32_t ctr[4] = {qid, ant, p->iter_offset + iter, step};",
                      "const uint32_t ctr[4] = {ant, qid, p->iter_offset + iter, step};"),
     "word_order": ("return ((uint64_t)x[1] << 32) | x[0];", "return ((uint64_t)x[0] << 32) | x[1];"),
+    "goal_exact_weight": ("rw[fill[x]] = t0[e];", "rw[fill[x]] = t0[e] + wf[e];"),
+    "goal_exact_cap": ("(dist[v] > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)dist[v])", "((uint32_t)dist[v])"),
+    "goal_exact_unreachable": ("h[v] = dist[v] == UINT64_MAX ? U32_MAX :", "h[v] = dist[v] == UINT64_MAX ? 0u :"),
+    "goal_exact_row_ignored": ("return hrow ? (int64_t)hrow[x] :", "return hrow ? (int64_t)hrow[dst] :"),
+    "goal_exact_forward_roads": (
+        """    for (uint32_t e = 0; e < m; ++e) rp[g->col[e] + 1]++;
+    for (uint32_t x = 0; x < n; ++x) rp[x + 1] += rp[x];
+    uint32_t *fill = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+    memcpy(fill, rp, sizeof(uint32_t) * n);
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e) {
+            const uint32_t x = g->col[e];
+            ru[fill[x]] = u;
+            rw[fill[x]] = t0[e];
+            fill[x]++;
+        }""",
+        """    for (uint32_t u = 0; u <= n; ++u) rp[u] = g->row_ptr[u];
+    uint32_t *fill = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+    for (uint32_t e = 0; e < m; ++e) { ru[e] = g->col[e]; rw[e] = t0[e]; }"""),
     "apply_after_load_update": (
         """            for (uint32_t e = 0; e < m; ++e) tau[e] = orc_apply_tau(p, tau[e], dep[e], load[e]);
             if (!(p->flags & ORC_FLAG_NO_LOAD_UPDATE)) {

@@ -701,3 +701,149 @@ def test_pheromone_is_penalised_by_the_load_the_ants_saw(orc):
     assert two["cost_ms"][0] == 14400 and two["path_len"][0] == 2
     assert two["tau"].tolist() == [1669953, 16384, 1912679, 16384]
     assert two["load"].tolist() == [5, 0, 1, 0]
+
+
+# ---------------------------------------------------------------------------
+# exact goal term (Calc_Dist as the shortest free-flow time to the destination)
+# ---------------------------------------------------------------------------
+
+def _reverse_dijkstra(g, t0, dst):
+    """Shortest free-flow time from every node to dst by scipy, as the
+    oracle reports it: min(d, 2^32 - 2), and 2^32 - 1 where dst is out of reach."""
+    tails = g.tail().astype(np.int64)
+    heads = g.col.astype(np.int64)
+    best = {}
+    for u, x, w in zip(tails.tolist(), heads.tolist(), t0.tolist()):   # parallel roads: the faster one
+        best[(u, x)] = min(w, best.get((u, x), w))
+    keys = np.array(list(best.keys()), dtype=np.int64).reshape(-1, 2)
+    A = sp.csr_matrix((np.array(list(best.values()), dtype=np.float64), (keys[:, 0], keys[:, 1])),
+                      shape=(g.n, g.n))
+    d = dijkstra(A.T.tocsr(), indices=int(dst))
+    out = np.full(g.n, 0xFFFFFFFF, np.uint64)
+    fin = np.isfinite(d)
+    out[fin] = np.minimum(d[fin], 0xFFFFFFFE).astype(np.uint64)
+    return out.astype(np.uint32)
+
+
+def _one_way_graph(rng, n=70, m=260):
+    """Random directed roads (some one-way, some parallel), with nodes that
+    cannot reach others; signals on half the nodes."""
+    tails = rng.integers(0, n, size=m)
+    heads = rng.integers(0, n - 1, size=m)
+    heads = np.where(heads >= tails, heads + 1, heads)
+    tails[:5] = n - 1                # node n-1 only leaves: nothing reaches it
+    return from_edges(n, tails, heads, len_dm=rng.integers(100, 9000, size=m),
+                      speed_kmh=rng.choice([30, 50, 70], size=m), green_pm=rng.integers(200, 800, size=m),
+                      cycle_ms=np.where(rng.random(n) < 0.5, 90000, 0))
+
+
+def test_exact_goal_matches_scipy_dijkstra(orc):
+    rng = np.random.default_rng(21)
+    p = default_params(flags=orc.FLAG_GOAL_EXACT)
+    cases = [(_one_way_graph(rng), None), (planar_graph(900, rng), None)]
+    for g, _ in cases:
+        t0, _ = orc.edge_static(g, p)
+        for dst in rng.integers(0, g.n, size=8).tolist() + [g.n - 1]:
+            want = _reverse_dijkstra(g, t0, dst)
+            got = orc.goal_exact(g, p, dst)
+            assert got.tolist() == want.tolist(), dst
+            assert got[dst] == 0
+    # the one-way graph has nodes that cannot reach some destinations
+    g = cases[0][0]
+    assert np.any(orc.goal_exact(g, p, g.n - 1) == 0xFFFFFFFF)
+
+
+def test_exact_goal_saturates_and_marks_unreachable(orc):
+    """Chain 0 -> 1 -> ... -> 5 of roads whose free-flow time is capped at
+    2^31 ms (6e6 dm at 1 km/h); node 6 is isolated.  By hand: h(5) = 0,
+    h(4) = 2^31, h(3..0) = 2^32 - 2 (saturated), h(6) = 2^32 - 1."""
+    g = from_edges(7, [0, 1, 2, 3, 4], [1, 2, 3, 4, 5], len_dm=6_000_000, speed_kmh=1)
+    p = default_params(flags=orc.FLAG_GOAL_EXACT)
+    t0, _ = orc.edge_static(g, p)
+    assert t0.tolist() == [2 ** 31] * 5
+    assert orc.goal_exact(g, p, 5).tolist() == [0xFFFFFFFE] * 4 + [2 ** 31, 0, 0xFFFFFFFF]
+
+
+def test_exact_goal_is_consistent_and_tight(orc):
+    """Bellman's equations of shortest distances: along every road the term
+    drops by at most the road's free-flow time, and from every node that
+    reaches dst some road drops it by exactly that."""
+    rng = np.random.default_rng(22)
+    g = planar_graph(1500, rng)
+    p = default_params(flags=orc.FLAG_GOAL_EXACT)
+    t0, _ = orc.edge_static(g, p)
+    tails = g.tail()
+    for dst in rng.integers(0, g.n, size=4).tolist():
+        h = orc.goal_exact(g, p, dst).astype(np.int64)
+        assert np.all(h < 0xFFFFFFFE)                       # strongly connected, short distances
+        slack = t0.astype(np.int64) + h[g.col] - h[tails]
+        assert slack.min() >= 0
+        tight = np.zeros(g.n, bool)
+        tight[tails[slack == 0]] = True
+        tight[dst] = True
+        assert tight.all()
+
+
+def diamond_with_signals():
+    """0 -> 1 -> 3 and 0 -> 2 -> 3, every road 65536 ms of free flow (8192 dm
+    at 45 km/h).  Node 1 and node 2 have 100 s signals; the approach 0 -> 1
+    has 500 per mille green (wait 50000^2 / 200000 = 12500 ms), 0 -> 2 none
+    (wait 100000^2 / 200000 = 50000, capped at T_max = 20000 ms); no loads."""
+    return from_edges(4, [0, 0, 1, 2], [1, 2, 3, 3], len_dm=8192, speed_kmh=45,
+                      green_pm=[500, 0, 1000, 1000], cycle_ms=[0, 100000, 100000, 0])
+
+
+def test_exact_goal_first_step_frequencies(orc):
+    """With the exact term h = (131072, 65536, 65536, 0) the reduced costs
+    of the two first roads are their signal waits alone, 12500 and 20000 ms,
+    so eta = floor(2^26 / delta) = 5368 and 3355 and (beta = 2) the first
+    road is taken with probability 5368^2 / (5368^2 + 3355^2).  The
+    straight-line term is 0 here (all coordinates equal), which would give
+    eta = 859 and 784 instead."""
+    g = diamond_with_signals()
+    p = default_params(max_steps=3, vmax_kmh=0, alpha=1, beta=2, flags=orc.FLAG_GOAL_EXACT)
+    cost, pre = orc.cost_table(g, p, g.base_load)
+    assert cost.tolist() == [65536 + 12500, 65536 + 20000, 65536, 65536] and not pre.any()
+    assert orc.goal_exact(g, p, 3).tolist() == [131072, 65536, 65536, 0]
+    tau = np.full(g.m, 0x10000, np.uint32)
+    N = 12000
+    first = np.zeros(2)
+    for q in range(N):
+        ok, path, cs, sel = orc.walk(g, p, tau, cost, q, 0, 3, 0, 0)
+        assert ok and len(path) == 2
+        first[int(path[0])] += 1
+    p1 = 5368 ** 2 / (5368 ** 2 + 3355 ** 2)
+    assert chisquare(first, np.array([p1, 1 - p1]) * N).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_exact_goal_routes_are_valid_and_bounded(orc, mode):
+    """Whole runs with the exact term: simple connected routes whose cost is
+    the cost-table sum of the path and never below the optimum; the tiny
+    grid's optimum is reached."""
+    w = grid32(vehicles=16, ants=16, iterations=6)
+    g, V = w.graph, w.vehicles
+    p = dict(w.params, mode=mode, flags=orc.FLAG_NO_LOAD_UPDATE | orc.FLAG_GOAL_EXACT)
+    res = orc.route(g, V, p)
+    _check_paths(g, V, res, p["max_steps"])
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    A = sp.csr_matrix((cost.astype(np.float64), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
+                      shape=(g.n, g.n))
+    opt = dijkstra(A, indices=V.src.astype(np.int64))
+    for v in range(len(V)):
+        L = int(res["path_len"][v])
+        assert L > 0
+        assert res["cost_ms"][v] == int(cost[res["path_edges"][v, :L].astype(np.int64)].astype(np.int64).sum())
+        assert res["cost_ms"][v] >= opt[v, V.dst[v]] - 1e-6
+    rng = np.random.default_rng(4)
+    gt = grid_graph(3, 4, rng)
+    Vt = veh([0, 11, 3], [11, 0, 8])
+    pt = default_params(ants=64, iterations=20, max_steps=11, mode=mode,
+                        flags=orc.FLAG_NO_LOAD_UPDATE | orc.FLAG_GOAL_EXACT)
+    rt = orc.route(gt, Vt, pt)
+    ct, _ = orc.cost_table(gt, pt, gt.base_load)
+    At = sp.csr_matrix((ct.astype(np.float64), gt.col.astype(np.int64), gt.row_ptr.astype(np.int64)),
+                       shape=(gt.n, gt.n))
+    ot = dijkstra(At, indices=Vt.src.astype(np.int64))
+    for v in range(3):
+        assert rt["cost_ms"][v] == int(ot[v, Vt.dst[v]])
