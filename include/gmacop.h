@@ -51,6 +51,16 @@ extern "C" {
                                        captured once and replayed while the call's
                                        arguments stay the same; needs a non-null
                                        stream; ignored with GMACOP_TIME_KERNELS        */
+#define GMACOP_GOAL_EXACT     16u   /* goal term (Section 4.2, Alg. 2 step 1, Calc_Dist)
+                                       = exact shortest free-flow time to the
+                                       vehicle's destination (sum of each road's
+                                       floor(len * 360 / speed) ms over the best road
+                                       sequence; min(d, 2^32 - 2), 2^32 - 1 where the
+                                       destination cannot be reached), computed on the
+                                       device once per call (per admitted query in a
+                                       router) instead of the straight-line term;
+                                       vmax_kmh is then ignored.  Graphs under 2^24
+                                       nodes (GMACOP_E_UNSUPPORTED otherwise)          */
 
 /* Opaque handle: the graph, its static per-road data and the pheromone / load
  * state on the device.  Owns all of its device memory. */
@@ -182,6 +192,27 @@ int gmacop_state_get(gmacop_graph *g, uint32_t *tau_q16, uint32_t *load, void *h
  * in independent mode or had no such vehicle.  Synchronises hip_stream. */
 int gmacop_vehicle_tau_get(gmacop_graph *g, uint32_t vehicle, uint32_t *tau_q16, void *hip_stream);
 
+/* Calc_Dist (Section 4.2, Alg. 2 step 1) on its own: the exact goal term of
+ * GMACOP_GOAL_EXACT for nd destinations.  h (host, nd * n_nodes entries) row
+ * i gets, for every node, the shortest free-flow time to dst[i] in ms (each
+ * road weighted t0 = max(1, min(2^31, floor(len * 360 / speed)))),
+ * min(d, 2^32 - 2), and 0xFFFFFFFF for nodes that cannot reach dst[i],
+ * including every node of another city.  Synchronous on hip_stream; uses
+ * temporary device memory.  GMACOP_E_INVAL for a destination out of range. */
+int gmacop_goal_rows(gmacop_graph *g, const uint32_t *dst, uint32_t nd, uint32_t *h, void *hip_stream);
+
+/* The shortest free-flow route of each query (the Dijkstra baseline the paper
+ * compares against in Table 1): at every node the first out-road in road
+ * order that lies on a shortest route to q[i].dst.  out (host buffers, as in
+ * gmacop_route_batch with max_steps entries per row): path_len[i] roads
+ * (0 when the destination cannot be reached, its free-flow time reaches
+ * 2^32 - 2, or the route has more than max_steps roads), cost_ms[i] its
+ * free-flow time (0xFFFFFFFF when path_len is 0), steps_total the sum of
+ * path_len.  Errors as gmacop_route_batch's query checks.  Synchronous; uses
+ * temporary device memory. */
+int gmacop_shortest_routes(gmacop_graph *g, const gmacop_od *q, uint32_t nq, uint32_t max_steps,
+                           gmacop_result *out, void *hip_stream);
+
 /* Work counters and kernel times accumulated over gmacop_route_batch calls
  * since the last reset.  Kernel index: 0 = walk phase (tour construction and
  * deposit, all walkers of an iteration), 1 = best-route reduction, 2 =
@@ -225,6 +256,8 @@ typedef struct gmacop_server gmacop_server;
  * max_slots, or fewer if the per-slot device memory times the slots would
  * exceed mem_budget_bytes (0: half of the device memory free now); the graph
  * must have fewer than 2^24 nodes.  Loads are frozen at the sensed loads.
+ * Of params->flags only GMACOP_TIME_KERNELS and GMACOP_GOAL_EXACT are used
+ * (with the latter, each query's goal row is computed when it is admitted).
  * Errors: GMACOP_E_INVAL / E_RANGE as gmacop_route_batch, GMACOP_E_NOMEM when
  * not even one slot fits, GMACOP_E_UNSUPPORTED for 0 or more than 4095
  * iterations. */

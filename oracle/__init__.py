@@ -80,6 +80,8 @@ def lib():
         L.orc_goal.argtypes = [vp, vp, u32, u32]
         L.orc_goal.restype = u64
         L.orc_goal_exact.argtypes = [vp, vp, u32, vp]
+        L.orc_shortest_route.argtypes = [vp, vp, u32, u32, u32, vp]
+        L.orc_shortest_route.restype = u32
         L.orc_eta.argtypes = [C.c_int64]
         L.orc_eta.restype = u32
         L.orc_roulette.argtypes = [vp, u32, u64]
@@ -169,6 +171,15 @@ def goal_exact(g, p: dict, dst: int) -> np.ndarray:
     h = np.zeros(gr.n, np.uint32)
     lib().orc_goal_exact(C.byref(gr.s), C.byref(pp), int(dst), _ptr(h))
     return h
+
+
+def shortest_route(g, p: dict, src: int, dst: int, max_len: int) -> np.ndarray:
+    """Shortest free-flow route (road ids) from src to dst; empty when dst is
+    out of reach, the time is capped, or the route exceeds max_len roads."""
+    gr, pp = _GraphRef(g), _params(p)
+    path = np.zeros(max(1, max_len), np.uint32)
+    n = lib().orc_shortest_route(C.byref(gr.s), C.byref(pp), int(src), int(dst), int(max_len), _ptr(path))
+    return path[:n].copy()
 
 
 def eta(delta: int) -> int:

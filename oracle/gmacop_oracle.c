@@ -239,6 +239,35 @@ void orc_goal_exact(const orc_graph *g, const orc_params *p, uint32_t dst, uint3
     free(t0); free(wf); free(rp); free(ru); free(rw); free(fill); free(dist); free(done); free(heap);
 }
 
+/* Shortest free-flow route from src to dst (the Dijkstra baseline of the    */
+/* paper's Table 1): from each node, the first out-road in road order that   */
+/* lies on a shortest route, i.e. whose free-flow time equals the drop of   */
+/* the exact goal term along it.  Returns the number of roads; 0 when dst    */
+/* cannot be reached, when its free-flow time reaches the 2^32-2 cap (the    */
+/* drops can no longer be told apart), or when the route has more than      */
+/* max_len roads.                                                            */
+uint32_t orc_shortest_route(const orc_graph *g, const orc_params *p, uint32_t src, uint32_t dst,
+                            uint32_t max_len, uint32_t *path)
+{
+    uint32_t *h = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
+    uint32_t *t0 = (uint32_t *)malloc(sizeof(uint32_t) * (g->m + 1));
+    uint32_t *wf = (uint32_t *)malloc(sizeof(uint32_t) * (g->m + 1));
+    orc_goal_exact(g, p, dst, h);
+    orc_edge_static(g, p, t0, wf);
+    uint32_t len = 0, u = src;
+    const int followable = h[src] < 0xFFFFFFFEu;
+    while (followable && u != dst) {
+        uint32_t next = U32_MAX;
+        for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e)
+            if ((uint64_t)t0[e] + h[g->col[e]] == h[u]) { next = e; break; }
+        if (len == max_len) { len = 0; break; }
+        path[len++] = next;      /* a node with a finite term always has such a road */
+        u = g->col[next];
+    }
+    free(h); free(t0); free(wf);
+    return len;
+}
+
 /* Desirability of a road from its reduced cost delta = cost + h(head) - h(tail):
  * eta = floor(2^26 / max(delta, 1)), clamped to [1, 65535]. */
 uint32_t orc_eta(int64_t delta)

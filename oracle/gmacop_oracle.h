@@ -71,6 +71,11 @@ uint64_t orc_goal(const orc_graph *g, const orc_params *p, uint32_t node, uint32
 /* Exact goal row for destination dst: shortest free-flow time (sum of t0)
  * from every node to dst, min(.., 0xFFFFFFFE); 0xFFFFFFFF = cannot reach dst. */
 void orc_goal_exact(const orc_graph *g, const orc_params *p, uint32_t dst, uint32_t *h);
+/* Shortest free-flow route src -> dst: first road (road order) on a shortest
+ * route at every node; returns its road count, 0 if out of reach, capped or
+ * longer than max_len. */
+uint32_t orc_shortest_route(const orc_graph *g, const orc_params *p, uint32_t src, uint32_t dst,
+                            uint32_t max_len, uint32_t *path);
 /* Heuristic desirability of a road from its reduced cost. */
 uint32_t orc_eta(int64_t delta);
 /* Roulette: index chosen among d weights by a 64-bit random word. */

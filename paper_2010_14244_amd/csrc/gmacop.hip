@@ -633,6 +633,8 @@ struct LdsWalkArgs {
     uint32_t *path, *ant_len, *ant_cost;
     uint64_t *iter_key, *steps, *counters;
     uint32_t *iter_max;    // longest walk of this iteration
+    const uint32_t *goal;  // exact goal rows [nq][goal_stride] (city-local node ids), or NULL: straight line
+    uint32_t goal_stride;
 };
 
 // Per-group scratch at the end of an LDS walker's dynamic LDS: the deposit
@@ -875,7 +877,8 @@ __global__ __launch_bounds__(512) void k_walk_lds(LdsWalkArgs a)
     {
         const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
         for (uint32_t i = tid; i < n_cnt; i += nthr)
-            s_aux[i] = (uint32_t)goal_ms(a.x[n_lo + i], a.y[n_lo + i], dx, dy, a.kgoal);
+            s_aux[i] = a.goal ? a.goal[(size_t)v * a.goal_stride + i]
+                              : (uint32_t)goal_ms(a.x[n_lo + i], a.y[n_lo + i], dx, dy, a.kgoal);
     }
     __syncthreads();
     {
@@ -1092,7 +1095,8 @@ __global__ __launch_bounds__(512) void k_walk_ldsr(LdsWalkArgs a)
         load_batch(tid);
         const int32_t dx = a.x[q.dst], dy = a.y[q.dst];
         for (uint32_t i = tid; i < n_cnt; i += nthr)
-            s_aux[i] = (uint32_t)goal_ms(a.x[n_lo + i], a.y[n_lo + i], dx, dy, a.kgoal);
+            s_aux[i] = a.goal ? a.goal[(size_t)v * a.goal_stride + i]
+                              : (uint32_t)goal_ms(a.x[n_lo + i], a.y[n_lo + i], dx, dy, a.kgoal);
         __syncthreads();
         stage_batch(tid);
         for (uint32_t b0 = tid + 8 * nthr; b0 < e_cnt; b0 += 8 * nthr) {
@@ -1167,6 +1171,8 @@ struct GlbWalkArgs {
     uint32_t *path, *ant_len, *ant_cost;
     uint64_t *iter_key, *steps, *counters;
     uint32_t *iter_max;
+    const uint32_t *goal;      // exact goal rows [nq][goal_stride] (city-local node ids), or NULL: straight line
+    uint32_t goal_stride;
 };
 
 constexpr uint8_t kWalkerNone = 0, kWalkerGlobal = 8;   // 1..6: LDS walker classes
@@ -1187,6 +1193,7 @@ struct GlbWalk {
     uint64_t cs;
     uint32_t hist[4];          // the last four nodes entered
     uint32_t *path;            // this ant's path column
+    const uint32_t *grow;      // the vehicle's exact goal row (when the call uses one)
     uint64_t *pw;              // visited word of the node entered last (group lane 0; nullptr: none)
     uint64_t pval;             // its value, loaded when the node was entered
     uint32_t pbit;
@@ -1250,7 +1257,8 @@ __device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, GlbWalk &w, uint3
         }
         hx[c] = 0;
         if (live) {
-            hx[c] = goal_ms((int32_t)rec[c].z, (int32_t)rec[c].w, w.dx, w.dy, a.kgoal);
+            hx[c] = a.goal ? (int64_t)w.grow[xh - w.n_lo]
+                           : goal_ms((int32_t)rec[c].z, (int32_t)rec[c].w, w.dx, w.dy, a.kgoal);
             const uint32_t eta = eta_of((int64_t)cst[c] + hx[c] - w.hu);
             const uint32_t t = (uint32_t)wt[c];
             wt[c] = (a.alpha == 1 && a.beta == 2) ? (uint64_t)t * (eta * eta)
@@ -1385,6 +1393,7 @@ __global__ __launch_bounds__(256) void k_walk_glb(GlbWalkArgs a)
                     w.s = 0; w.ncand = 0; w.cs = 0; w.ok = false;
                     w.hist[0] = w.u; w.hist[1] = w.hist[2] = w.hist[3] = 0xFFFFFFFFu;
                     w.path = a.path + (size_t)w.v * a.ants + w.k;
+                    w.grow = a.goal ? a.goal + (size_t)w.v * a.goal_stride : nullptr;
                     if (++epoch == 0) {   // epochs would repeat: clear the slot's words once
                         for (uint32_t i = j; i < a.nw2; i += L) gw[i] = 0;
                         epoch = 1;
@@ -1482,6 +1491,8 @@ struct GlbListArgs {
     uint32_t *glb_n;
     uint32_t *vlen;            // [nq] longest walk of each vehicle in the previous launch; reset by k_glb_list
     uint32_t *ant_len, *ant_cost;
+    const uint32_t *goal;      // exact goal rows [nq][goal_stride], or NULL: straight line
+    uint32_t goal_stride;
 };
 
 // Once per call: the start data of every vehicle served by k_walk_glb; ants
@@ -1497,7 +1508,8 @@ __global__ void k_glb_prep(GlbListArgs a)
         r.v = v; r.qid = q.qid; r.src = q.src; r.dst = q.dst;
         r.rs = a.row_ptr[q.src]; r.d = a.row_ptr[q.src + 1] - r.rs; r.n_lo = a.node_lo[q.src]; r.pad = 0;
         r.dx = a.x[q.dst]; r.dy = a.y[q.dst];
-        const uint64_t hu = (uint64_t)goal_ms(a.x[q.src], a.y[q.src], r.dx, r.dy, a.kgoal);
+        const uint64_t hu = a.goal ? (uint64_t)a.goal[(size_t)v * a.goal_stride + (q.src - r.n_lo)]
+                                   : (uint64_t)goal_ms(a.x[q.src], a.y[q.src], r.dx, r.dy, a.kgoal);
         r.hu_lo = (uint32_t)hu; r.hu_hi = (uint32_t)(hu >> 32);
         a.vrec[v] = r;
     } else if (cls == kWalkerNone) {
@@ -1705,6 +1717,189 @@ __global__ void k_classify(const gmacop_od *od, uint32_t nq, uint32_t n, const u
     vclass[v] = c;
 }
 
+// ---- exact goal term: shortest free-flow time to each vehicle's destination ----
+
+// The in-roads of every node as (tail, free-flow time), in reverse-CSR order.
+__global__ void k_rev_weights(uint32_t m, const uint32_t *rev_edge, const uint32_t *tail, const uint32_t *t0,
+                              uint2 *rev_tw)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t e = rev_edge[i];
+    rev_tw[i] = make_uint2(tail[e], t0[e]);
+}
+
+// Free-flow time of every road, t0 = floor(len * 360 / speed) ms in [1, 2^31]
+// (the same quantity k_init_edges derives).
+__global__ void k_free_flow(uint32_t m, const uint32_t *len_dm, const uint16_t *speed, uint32_t *t0)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    uint64_t x = (uint64_t)len_dm[e] * 360u / speed[e];
+    x = x < 1 ? 1 : (x > kRoadCostCap ? kRoadCostCap : x);
+    t0[e] = (uint32_t)x;
+}
+
+struct GoalArgs {
+    const gmacop_od *od;       // queries; the destination of task v is od[v].dst
+    const uint32_t *list;      // task i is vehicle list[i] (router: admitted slots), or NULL: vehicle i
+    const uint32_t *dsts;      // or, when not NULL: task i is the destination dsts[i], row i
+    uint32_t ntask, n, stride, qcap;
+    const uint32_t *node_inst, *inst_off, *rev_ptr;
+    const uint2 *rev_tw;       // [m] (tail, free-flow time) of the in-roads of each node
+    uint32_t *goal;            // [vehicles][stride] rows, city-local node ids
+    uint32_t *work;            // per block: stamp [stride], two queues [qcap]
+    uint32_t *ctl;             // [0] next task, [1] blocks done (the last block out resets both)
+};
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Calc_Dist (Alg. 2 step 1) as an exact term: for each task's vehicle, the
+// shortest free-flow time from every node of its city to its destination,
+// min(d, 2^32 - 2), and 2^32 - 1 where the destination is out of reach.  A
+// persistent grid; a block takes one destination at a time and relaxes the
+// reversed roads from a frontier (label correcting: a node whose term drops
+// is queued for the next round, at most once per round by its round stamp),
+// until no term drops.  The result is the unique shortest-distance vector,
+// whatever order the relaxations run in.  When a round's frontier would
+// overflow its queue the next round scans the stamps of the whole city.
+__global__ __launch_bounds__(256) void k_goal_sssp(GoalArgs a)
+{
+    __shared__ uint32_t s_task, s_next, s_ovf;
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    uint32_t *stamp = a.work + (size_t)blockIdx.x * (a.stride + 2 * (size_t)a.qcap);
+    uint32_t *qa = stamp + a.stride, *qb = qa + a.qcap;
+    for (;;) {
+        if (tid == 0) s_task = atomicAdd(&a.ctl[0], 1u);
+        __syncthreads();
+        const uint32_t ti = s_task;
+        __syncthreads();
+        if (ti >= a.ntask) break;
+        const uint32_t v = a.list ? a.list[ti] : ti;
+        gmacop_od q;
+        if (a.dsts) {
+            q.dst = a.dsts[ti];
+            q.src = q.dst ^ 1u;   // only its validity is looked at
+            if (q.dst >= a.n) continue;
+        } else {
+            q = a.od[v];
+            if (q.src >= a.n || q.dst >= a.n || q.src == q.dst) continue;   // no walk for this vehicle
+        }
+        const uint32_t city = a.node_inst[q.dst];
+        const uint32_t n_lo = a.inst_off[city], nc = a.inst_off[city + 1] - n_lo;
+        uint32_t *row = a.goal + (size_t)v * a.stride;
+        const uint32_t dl = q.dst - n_lo;
+        for (uint32_t i = tid; i < nc; i += nthr) {
+            row[i] = i == dl ? 0u : 0xFFFFFFFFu;
+            stamp[i] = 0;
+        }
+        if (tid == 0) qa[0] = dl;
+        uint32_t F = 1;
+        bool scan = false;       // this round's frontier is every node stamped with the previous round
+        uint32_t *cur = qa, *nxt = qb;
+        __syncthreads();
+        for (uint32_t r = 1;; ++r) {
+            if (tid == 0) {
+                s_next = 0;
+                s_ovf = 0;
+            }
+            __syncthreads();
+            const uint32_t lim = scan ? nc : F;
+            for (uint32_t i = tid; i < lim; i += nthr) {
+                uint32_t x;
+                if (scan) {
+                    if (ld_agent(&stamp[i]) != r - 1) continue;
+                    x = i;
+                } else {
+                    x = ld_agent(&cur[i]);
+                }
+                const uint64_t d = ld_agent(&row[x]);
+                const uint32_t jb = a.rev_ptr[n_lo + x], je = a.rev_ptr[n_lo + x + 1];
+                for (uint32_t jj = jb; jj < je; ++jj) {
+                    const uint2 tw = a.rev_tw[jj];
+                    const uint32_t ul = tw.x - n_lo;
+                    const uint64_t s = d + tw.y;
+                    const uint32_t nd = s > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)s;
+                    if (nd < ld_agent(&row[ul])) {
+                        const uint32_t old = atomicMin(&row[ul], nd);
+                        if (nd < old && atomicExch(&stamp[ul], r) != r) {
+                            const uint32_t pos = atomicAdd(&s_next, 1u);
+                            if (pos < a.qcap)
+                                __hip_atomic_store(&nxt[pos], ul, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            else
+                                s_ovf = 1;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            F = s_next;
+            scan = s_ovf != 0;
+            uint32_t *tq = cur;
+            cur = nxt;
+            nxt = tq;
+            __syncthreads();   // every thread has read s_next and s_ovf before they are reset
+            if (F == 0) break;
+        }
+    }
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&a.ctl[1], 1u) == gridDim.x - 1) {
+            a.ctl[0] = 0;
+            a.ctl[1] = 0;
+        }
+    }
+}
+
+// The shortest free-flow route of each vehicle (the Dijkstra baseline of
+// Table 1), one lane per vehicle: from the source, repeatedly the first
+// out-road in road order whose free-flow time equals the drop of the exact
+// goal term along it, until the destination.  Length 0 when the destination
+// is out of reach, its time reaches the 2^32 - 2 cap, or the route has more
+// than max_steps roads.
+__global__ void k_shortest_route(const gmacop_od *od, uint32_t nq, uint32_t n, uint32_t max_steps,
+                                 const uint32_t *row_ptr, const uint32_t *col, const uint32_t *t0,
+                                 const uint32_t *node_lo, const uint32_t *goal, uint32_t stride, uint32_t *path,
+                                 uint32_t *len, uint32_t *cost, uint64_t *steps)
+{
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nq) return;
+    const gmacop_od q = od[v];
+    uint32_t L = 0, c = kNoCost;
+    if (q.src < n && q.dst < n && q.src != q.dst) {
+        const uint32_t n_lo = node_lo[q.dst];
+        const uint32_t *h = goal + (size_t)v * stride;
+        const uint32_t hs = h[q.src - n_lo];
+        if (hs < 0xFFFFFFFEu) {
+            uint32_t u = q.src;
+            bool fits = true;
+            while (u != q.dst) {
+                const uint32_t hu = h[u - n_lo];
+                uint32_t next = 0xFFFFFFFFu;
+                for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+                    if ((uint64_t)t0[e] + h[col[e] - n_lo] == hu) {
+                        next = e;
+                        break;
+                    }
+                if (next == 0xFFFFFFFFu || L == max_steps) {   // (the first cannot happen for a finite term)
+                    fits = false;
+                    break;
+                }
+                path[(size_t)v * max_steps + L++] = next;
+                u = col[next];
+            }
+            if (fits) c = hs;
+            else L = 0;
+        }
+    }
+    len[v] = L;
+    cost[v] = c;
+    if (L) atomicAdd((unsigned long long *)steps, (unsigned long long)L);
+}
+
 // ---- serving: slot admission, advance, result gather ----
 
 // Queries enter free slots: the slot's route starts empty at iteration 0
@@ -1860,6 +2055,11 @@ struct gmacop_graph {
     uint32_t *best_path = nullptr, *best_len = nullptr, *best_cost = nullptr;
     gmacop_od *od = nullptr;
     GlbWork glb;
+    // exact goal term: rows per vehicle, the search's per-block workspace and task counter,
+    // the in-roads as (tail, free-flow time)
+    size_t cap_goal = 0, cap_goal_work = 0;
+    uint32_t *goal = nullptr, *goal_work = nullptr, *goal_ctl = nullptr;
+    uint2 *rev_tw = nullptr;
     // statistics
     uint64_t *counters = nullptr;         // device [kCounters]
     uint32_t *iter_max = nullptr;         // device [1]
@@ -1894,6 +2094,7 @@ struct gmacop_graph {
         dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_key); dfree(steps);
         dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters); dfree(iter_max);
         dfree(lazy); dfree(dep_ind); dfree(touched); dfree(touched_n); dfree(dev_gen);
+        dfree(goal); dfree(goal_work); dfree(goal_ctl); dfree(rev_tw);
         glb.release();
         for (auto &t : pending) {
             (void)hipEventDestroy(t.a);
@@ -2054,7 +2255,8 @@ int validate_params(const gmacop_graph *g, const gmacop_params *p, uint32_t nq)
     if (p->tau_min_q16 > p->tau0_q16 || p->tau0_q16 > p->tau_max_q16)
         return fail(GMACOP_E_INVAL, "need tau_min <= tau0 <= tau_max");
     if (p->mode > GMACOP_MODE_INDEPENDENT) return fail(GMACOP_E_INVAL, "unknown mode %u", p->mode);
-    if (p->flags & ~(GMACOP_NO_LOAD_UPDATE | GMACOP_DEVICE_PTRS | GMACOP_TIME_KERNELS | GMACOP_HIP_GRAPH))
+    if (p->flags & ~(GMACOP_NO_LOAD_UPDATE | GMACOP_DEVICE_PTRS | GMACOP_TIME_KERNELS | GMACOP_HIP_GRAPH |
+                     GMACOP_GOAL_EXACT))
         return fail(GMACOP_E_INVAL, "unknown flags");
     const uint32_t lg = g->max_deg <= 1 ? 0 : bit_length(g->max_deg - 1);
     if ((uint64_t)p->alpha * bit_length(p->tau_max_q16) + 16ull * p->beta + lg > 64)
@@ -2273,7 +2475,9 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     // largest possible term (its bounding-box diagonal at this vmax) does not
     // fit goes to the global walker, which keeps 64
     const uint64_t kgoal = p->vmax_kmh ? (360ull << 16) / p->vmax_kmh : 0;
+    const bool exact_goal = (p->flags & GMACOP_GOAL_EXACT) != 0;
     auto goal_fits = [&](uint32_t i) {
+        if (exact_goal) return true;   // exact terms are 32-bit by definition
         const uint64_t x = g->inst_span2[i];
         uint64_t r = (uint64_t)std::sqrt((double)x);
         while (r * r < x) ++r;   // ceil(sqrt(x)) <= 2^31.5: no overflow
@@ -2439,6 +2643,21 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
         delete g;
         return fail(GMACOP_E_DEVICE, "hipMemset of counters failed");
     }
+    // static: free-flow times and the in-roads as (tail, free-flow time), for the exact goal term
+    if ((rc = dalloc(&g->rev_tw, m))) {
+        std::string keep = t_err;
+        delete g;
+        t_err = keep;
+        return rc;
+    }
+    hipLaunchKernelGGL(k_free_flow, dim3(blocks_for(m, 256)), dim3(256), 0, 0, m, (const uint32_t *)g->len_dm,
+                       (const uint16_t *)g->speed, g->t0);
+    hipLaunchKernelGGL(k_rev_weights, dim3(blocks_for(m, 256)), dim3(256), 0, 0, m, (const uint32_t *)g->rev_edge,
+                       (const uint32_t *)g->tail, (const uint32_t *)g->t0, g->rev_tw);
+    if (hipDeviceSynchronize() != hipSuccess) {
+        delete g;
+        return fail(GMACOP_E_DEVICE, "graph set-up kernels failed");
+    }
     *out = g;
     return GMACOP_OK;
 }
@@ -2460,9 +2679,41 @@ struct CallWork {
     uint64_t *gwords = nullptr;
     uint64_t *lazy = nullptr, *dep_ind = nullptr;
     uint32_t *touched = nullptr, *touched_n = nullptr, *dev_gen = nullptr;
+    uint32_t *goal = nullptr, *goal_work = nullptr, *goal_ctl = nullptr;   // exact goal term (GoalPlan)
     bool side = false;          // the global walker may run on g->side beside the LDS walkers
     bool allow_graph = false;   // GMACOP_HIP_GRAPH may capture and replay the call
 };
+
+// Shape of the exact-goal search: one row of `stride` terms per vehicle (the
+// largest city), and a persistent grid whose per-block workspace (stamps and
+// two frontier queues) stays within a budget.
+struct GoalPlan {
+    bool on = false;
+    uint32_t stride = 0, qcap = 0, blocks = 0;
+    size_t work_words() const { return (size_t)blocks * (stride + 2 * (size_t)qcap); }
+};
+
+constexpr uint64_t kGoalWorkBudget = 2ull << 30;   // bytes of the search's per-block workspace
+
+int goal_plan(const gmacop_graph *g, const gmacop_params *p, uint64_t tasks, uint64_t budget, GoalPlan *gp)
+{
+    *gp = GoalPlan{};
+    if (!(p->flags & GMACOP_GOAL_EXACT)) return GMACOP_OK;
+    gp->on = true;
+    gp->stride = std::max<uint32_t>(g->max_city_nodes, 1);
+    gp->qcap = std::min<uint32_t>(gp->stride, 65536);
+    if (const char *qc = getenv("GMACOP_GOAL_QCAP"))   // smaller frontier queues (exercises the scan rounds)
+        gp->qcap = std::max<uint32_t>(1, std::min<uint32_t>(gp->qcap, (uint32_t)strtoul(qc, nullptr, 10)));
+    int nb = 0, cus = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_goal_sssp, 256, 0));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+    uint64_t blocks = (uint64_t)std::max(nb, 1) * (uint64_t)std::max(cus, 1);
+    blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(tasks, 1));
+    const uint64_t per_block = 4ull * (gp->stride + 2ull * gp->qcap);
+    blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(1, budget / per_block));
+    gp->blocks = (uint32_t)blocks;
+    return GMACOP_OK;
+}
 
 // Checks shared by both routing entry points; on success *plan holds the walk schedule.
 int route_check(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p, const gmacop_result *out,
@@ -2487,13 +2738,15 @@ int route_check(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_p
     }
     HIP_TRY(hipSetDevice(g->device));
     *plan = plan_walk(g, p, g->max_lds);
+    if (plan->legacy && (p->flags & GMACOP_GOAL_EXACT))
+        return fail(GMACOP_E_UNSUPPORTED, "the exact goal term needs a graph under 2^24 nodes");
     if (!plan->legacy && plan->glb && (rc = glb_grid(g->device, *plan, (uint64_t)nq * p->ants))) return rc;
     return GMACOP_OK;
 }
 
 // Workspace of the allocating entry point: the graph's own buffers, grown to fit.
-int route_work_grow(gmacop_graph *g, uint32_t nq, const gmacop_params *p, const WalkPlan &plan, hipStream_t st,
-                    CallWork *w)
+int route_work_grow(gmacop_graph *g, uint32_t nq, const gmacop_params *p, const WalkPlan &plan, const GoalPlan &gp,
+                    hipStream_t st, CallWork *w)
 {
     int rc;
     const bool indep = p->mode == GMACOP_MODE_INDEPENDENT;
@@ -2559,6 +2812,17 @@ int route_work_grow(gmacop_graph *g, uint32_t nq, const gmacop_params *p, const 
     w->gepoch = g->glb.epoch; w->gwords = g->glb.words;
     w->lazy = g->lazy; w->dep_ind = g->dep_ind; w->touched = g->touched; w->touched_n = g->touched_n;
     w->dev_gen = g->dev_gen;
+    if (gp.on) {
+        if ((rc = grow(&g->goal, &g->cap_goal, std::max<size_t>((size_t)nq * gp.stride, 1), false)) ||
+            (rc = grow(&g->goal_work, &g->cap_goal_work, std::max<size_t>(gp.work_words(), 1), false)))
+            return rc;
+        if (!g->goal_ctl) {
+            if ((rc = dalloc(&g->goal_ctl, 2))) return rc;
+            HIP_TRY(hipMemset(g->goal_ctl, 0, 2 * sizeof(uint32_t)));
+            HIP_TRY(hipDeviceSynchronize());
+        }
+        w->goal = g->goal; w->goal_work = g->goal_work; w->goal_ctl = g->goal_ctl;
+    }
     w->side = true;
     w->allow_graph = true;
     return GMACOP_OK;
@@ -2568,7 +2832,7 @@ int route_work_grow(gmacop_graph *g, uint32_t nq, const gmacop_params *p, const 
 // iteration walk, best route, pheromone/load update, cost table; results to
 // the caller's buffers.
 int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p, gmacop_result *out,
-              hipStream_t st, const WalkPlan &plan, const CallWork &w)
+              hipStream_t st, const WalkPlan &plan, const GoalPlan &gp, const CallWork &w)
 {
     int rc;
     const bool indep = p->mode == GMACOP_MODE_INDEPENDENT;
@@ -2627,6 +2891,7 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
     la.seed_lo = wa.seed_lo; la.seed_hi = wa.seed_hi; la.q_deposit = p->q_deposit; la.path = w.path;
     la.ant_len = w.ant_len; la.ant_cost = w.ant_cost; la.iter_key = w.iter_key;
     la.steps = steps; la.counters = g->counters; la.iter_max = g->iter_max;
+    la.goal = gp.on ? w.goal : nullptr; la.goal_stride = gp.stride;
     const bool update_loads = load_update && !indep;
     BestArgs ba{nq, p->ants, S, update_loads ? 1u : 0u, g->iter_max, g->counters, w.path, w.ant_len, w.iter_key,
                 best_path, best_len, best_cost, g->cnt};
@@ -2644,8 +2909,13 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
     ga.seed_hi = wa.seed_hi; ga.q_deposit = p->q_deposit; ga.path = w.path; ga.ant_len = w.ant_len;
     ga.ant_cost = w.ant_cost; ga.iter_key = w.iter_key; ga.steps = steps;
     ga.counters = g->counters; ga.iter_max = g->iter_max;
+    ga.goal = la.goal; ga.goal_stride = gp.stride;
     const GlbListArgs gla{od, w.vclass, g->row_ptr, g->node_lo, g->x, g->y, nq, p->ants, wa.kgoal,
-                          w.gvrec, w.gveh, w.gctl, w.gvlen, w.ant_len, w.ant_cost};
+                          w.gvrec, w.gveh, w.gctl, w.gvlen, w.ant_len, w.ant_cost, la.goal, gp.stride};
+    GoalArgs goa{};
+    goa.od = od; goa.list = nullptr; goa.ntask = nq; goa.n = g->n; goa.stride = gp.stride; goa.qcap = gp.qcap;
+    goa.node_inst = g->node_inst; goa.inst_off = g->inst_off_dev; goa.rev_ptr = g->rev_ptr; goa.rev_tw = g->rev_tw;
+    goa.goal = w.goal; goa.work = w.goal_work; goa.ctl = w.goal_ctl;
     const bool any_lds = !plan.legacy && plan.any_lds();
     if (any_lds && (rc = setup_walk_lds(la, plan, st))) return rc;
 
@@ -2658,6 +2928,8 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
         KernelTimer kt{g, st, timing};
         gmacop_graph::Timed tm{}, tl{};
         hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ia);
+        if (gp.on && nq)   // Calc_Dist: the exact goal row of every vehicle, once per call
+            hipLaunchKernelGGL(k_goal_sssp, dim3(gp.blocks), dim3(256), 0, st, goa);
         if (indep && nq) hipLaunchKernelGGL(k_next_generation, dim3(1), dim3(64), 0, st, w.dev_gen);
         hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
                            best_len, best_cost, w.iter_key, steps);
@@ -2748,7 +3020,9 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
             (uint64_t)(uintptr_t)w.gctl, (uint64_t)(uintptr_t)w.gwords, (uint64_t)(uintptr_t)w.gepoch,
             (uint64_t)lds, (uint64_t)(uintptr_t)w.vclass,
             (uint64_t)(uintptr_t)w.lazy, (uint64_t)(uintptr_t)w.dep_ind, (uint64_t)(uintptr_t)w.touched,
-            (uint64_t)(uintptr_t)w.touched_n, (uint64_t)(uintptr_t)w.dev_gen, tcap, (uint64_t)w.side};
+            (uint64_t)(uintptr_t)w.touched_n, (uint64_t)(uintptr_t)w.dev_gen, tcap, (uint64_t)w.side,
+            (uint64_t)gp.on, gp.stride, gp.qcap, gp.blocks, (uint64_t)(uintptr_t)w.goal,
+            (uint64_t)(uintptr_t)w.goal_work, (uint64_t)(uintptr_t)w.goal_ctl};
         if (!g->gexec || key != g->gkey) {
             if (g->gexec) {
                 (void)hipGraphExecDestroy(g->gexec);
@@ -2861,7 +3135,7 @@ struct Carver {
 
 // The workspace layout of one call; the regions that keep state across calls come first.
 size_t carve_work(uint8_t *base, gmacop_graph *g, uint32_t nq, const gmacop_params *p, const WalkPlan &plan,
-                  CallWork *w)
+                  const GoalPlan &gp, CallWork *w)
 {
     const bool indep = p->mode == GMACOP_MODE_INDEPENDENT;
     const bool dev_ptrs = (p->flags & GMACOP_DEVICE_PTRS) != 0;
@@ -2870,6 +3144,11 @@ size_t carve_work(uint8_t *base, gmacop_graph *g, uint32_t nq, const gmacop_para
     const uint32_t tcap = (uint32_t)std::min<uint64_t>(g->m, (uint64_t)p->ants * S);
     Carver c{base};
     CallWork x{};
+    if (gp.on) {
+        x.goal_ctl = c.take<uint32_t>(2);
+        x.goal_work = c.take<uint32_t>(gp.work_words());
+        x.goal = c.take<uint32_t>((size_t)nq * gp.stride);
+    }
     if (plan.glb) {
         const uint64_t slots = (uint64_t)plan.glb_blocks * plan.glb_apb;
         x.gctl = c.take<uint32_t>(3);
@@ -2913,9 +3192,11 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     int rc = route_check(g, q, nq, p, out, &plan);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
+    GoalPlan gp;
+    if ((rc = goal_plan(g, p, nq, kGoalWorkBudget, &gp))) return rc;
     CallWork w;
-    if ((rc = route_work_grow(g, nq, p, plan, st, &w))) return rc;
-    return route_run(g, q, nq, p, out, st, plan, w);
+    if ((rc = route_work_grow(g, nq, p, plan, gp, st, &w))) return rc;
+    return route_run(g, q, nq, p, out, st, plan, gp, w);
 }
 
 extern "C" int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
@@ -2934,7 +3215,9 @@ extern "C" int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, u
         const uint64_t cap = std::max<uint64_t>(1, (GMACOP_NOALLOC_SCRATCH_BYTES / 2) / per_block);
         plan.glb_blocks = (uint32_t)std::min<uint64_t>(plan.glb_blocks, cap);
     }
-    const size_t need = carve_work(nullptr, g, nq, p, plan, nullptr);
+    GoalPlan gp;   // the search's workspace: at most a quarter of the scratch
+    if ((rc = goal_plan(g, p, nq, GMACOP_NOALLOC_SCRATCH_BYTES / 4, &gp))) return rc;
+    const size_t need = carve_work(nullptr, g, nq, p, plan, gp, nullptr);
     if (need > GMACOP_NOALLOC_SCRATCH_BYTES)
         return fail(GMACOP_E_NOMEM, "call needs %zu bytes of workspace; gmacop_route_batch_noalloc has %llu", need,
                     (unsigned long long)GMACOP_NOALLOC_SCRATCH_BYTES);
@@ -2950,7 +3233,7 @@ extern "C" int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, u
         sd.ptr = ptr;
     }
     CallWork w;
-    carve_work((uint8_t *)sd.ptr, g, nq, p, plan, &w);
+    carve_work((uint8_t *)sd.ptr, g, nq, p, plan, gp, &w);
     const bool indep = p->mode == GMACOP_MODE_INDEPENDENT && nq;
     // regions that carry state from call to call start over when their place or size changes
     const std::vector<uint64_t> layout = {
@@ -2975,10 +3258,11 @@ extern "C" int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, u
     if (plan.glb) {   // ticket counters, and the walk lengths that order the first list
         if ((rc = fill_u32(w.gctl, 3, st)) || (rc = fill_u32(w.gvlen, std::max<uint32_t>(nq, 1), st))) return rc;
     }
+    if (gp.on && (rc = fill_u32(w.goal_ctl, 2, st))) return rc;   // the search's task counter
     if (indep) sd.gen_count++;
     w.side = false;
     w.allow_graph = false;
-    rc = route_run(g, q, nq, p, out, st, plan, w);
+    rc = route_run(g, q, nq, p, out, st, plan, gp, w);
     g->last_lazy = nullptr;   // the rows live in the shared workspace: no gmacop_vehicle_tau_get after this call
     g->last_gen = nullptr;
     return rc;
@@ -3013,6 +3297,131 @@ extern "C" int gmacop_state_get(gmacop_graph *g, uint32_t *tau_q16, uint32_t *lo
     if (tau_q16) HIP_TRY(hipMemcpyAsync(tau_q16, g->tau, sizeof(uint32_t) * g->m, hipMemcpyDeviceToHost, st));
     if (load) HIP_TRY(hipMemcpyAsync(load, g->load, sizeof(uint32_t) * g->m, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return GMACOP_OK;
+}
+
+namespace {
+
+// Exact goal rows on temporary device buffers: `tasks` destinations (dsts) or
+// vehicles (od); rows [tasks][stride] city-local.
+struct GoalRun {
+    GoalPlan gp;
+    uint32_t *rows = nullptr, *work = nullptr, *ctl = nullptr;
+    ~GoalRun()
+    {
+        dfree(rows); dfree(work); dfree(ctl);
+    }
+};
+
+int goal_run(gmacop_graph *g, const gmacop_od *od_dev, const uint32_t *dsts_dev, uint32_t tasks, hipStream_t st,
+             GoalRun *r)
+{
+    gmacop_params gpar{};
+    gpar.flags = GMACOP_GOAL_EXACT;
+    int rc;
+    if ((rc = goal_plan(g, &gpar, tasks, kGoalWorkBudget, &r->gp)) ||
+        (rc = dalloc(&r->rows, std::max<size_t>((size_t)tasks * r->gp.stride, 1))) ||
+        (rc = dalloc(&r->work, std::max<size_t>(r->gp.work_words(), 1))) || (rc = dalloc(&r->ctl, 2)))
+        return rc;
+    HIP_TRY(hipMemsetAsync(r->ctl, 0, 2 * sizeof(uint32_t), st));
+    GoalArgs goa{};
+    goa.od = od_dev; goa.dsts = dsts_dev; goa.ntask = tasks; goa.n = g->n; goa.stride = r->gp.stride;
+    goa.qcap = r->gp.qcap; goa.node_inst = g->node_inst; goa.inst_off = g->inst_off_dev; goa.rev_ptr = g->rev_ptr;
+    goa.rev_tw = g->rev_tw; goa.goal = r->rows; goa.work = r->work; goa.ctl = r->ctl;
+    if (tasks) hipLaunchKernelGGL(k_goal_sssp, dim3(r->gp.blocks), dim3(256), 0, st, goa);
+    HIP_TRY(hipGetLastError());
+    return GMACOP_OK;
+}
+
+}  // namespace
+
+extern "C" int gmacop_goal_rows(gmacop_graph *g, const uint32_t *dst, uint32_t nd, uint32_t *h, void *hip_stream)
+{
+    if (!g || (nd && (!dst || !h))) return fail(GMACOP_E_INVAL, "graph, destinations or output is NULL");
+    for (uint32_t i = 0; i < nd; ++i)
+        if (dst[i] >= g->n) return fail(GMACOP_E_INVAL, "destination %u out of range", i);
+    if (!nd) return GMACOP_OK;
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint32_t *ddst = nullptr;
+    int rc = dalloc(&ddst, nd);
+    if (rc) return rc;
+    std::vector<uint32_t> rows;
+    uint32_t stride = 0;
+    hipError_t e = hipSuccess;
+    {
+        GoalRun r;
+        e = hipMemcpyAsync(ddst, dst, sizeof(uint32_t) * nd, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess && (rc = goal_run(g, nullptr, ddst, nd, st, &r)) == GMACOP_OK) {
+            stride = r.gp.stride;
+            rows.resize((size_t)nd * stride);
+            e = hipMemcpyAsync(rows.data(), r.rows, sizeof(uint32_t) * rows.size(), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+        }
+        (void)hipStreamSynchronize(st);   // nothing may still use the buffers freed below
+    }
+    dfree(ddst);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(GMACOP_E_DEVICE, "gmacop_goal_rows: %s", hipGetErrorString(e));
+    for (uint32_t i = 0; i < nd; ++i) {   // city-local rows to whole-graph rows
+        const uint32_t c = instance_of(g, dst[i]), lo = g->inst_off[c], hi = g->inst_off[c + 1];
+        uint32_t *out = h + (size_t)i * g->n;
+        std::fill(out, out + g->n, 0xFFFFFFFFu);
+        std::copy(rows.begin() + (size_t)i * stride, rows.begin() + (size_t)i * stride + (hi - lo), out + lo);
+    }
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_shortest_routes(gmacop_graph *g, const gmacop_od *q, uint32_t nq, uint32_t max_steps,
+                                      gmacop_result *out, void *hip_stream)
+{
+    if (!g) return fail(GMACOP_E_INVAL, "graph is NULL");
+    if (!out || !out->path_edges || !out->path_len || !out->cost_ms || !out->steps_total)
+        return fail(GMACOP_E_INVAL, "result buffers missing");
+    if (nq && !q) return fail(GMACOP_E_INVAL, "queries are NULL");
+    if (max_steps == 0) return fail(GMACOP_E_INVAL, "max_steps must be >= 1");
+    for (uint32_t i = 0; i < nq; ++i) {
+        if (q[i].src >= g->n || q[i].dst >= g->n) return fail(GMACOP_E_INVAL, "query %u: node out of range", i);
+        if (q[i].src == q[i].dst) return fail(GMACOP_E_INVAL, "query %u: src == dst", i);
+        if (instance_of(g, q[i].src) != instance_of(g, q[i].dst))
+            return fail(GMACOP_E_INVAL, "query %u: src and dst in different cities", i);
+    }
+    *out->steps_total = 0;
+    if (!nq) return GMACOP_OK;
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    gmacop_od *dq = nullptr;
+    uint32_t *dpath = nullptr, *dlen = nullptr, *dcost = nullptr;
+    uint64_t *dsteps = nullptr;
+    int rc;
+    hipError_t e = hipSuccess;
+    {
+        GoalRun r;
+        if (!(rc = dalloc(&dq, nq)) && !(rc = dalloc(&dpath, (size_t)nq * max_steps)) && !(rc = dalloc(&dlen, nq)) &&
+            !(rc = dalloc(&dcost, nq)) && !(rc = dalloc(&dsteps, 1))) {
+            e = hipMemcpyAsync(dq, q, sizeof(gmacop_od) * nq, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipMemsetAsync(dsteps, 0, sizeof(uint64_t), st);
+            if (e == hipSuccess && !(rc = goal_run(g, dq, nullptr, nq, st, &r))) {
+                hipLaunchKernelGGL(k_shortest_route, dim3(blocks_for(nq, 64)), dim3(64), 0, st, (const gmacop_od *)dq,
+                                   nq, g->n, max_steps, (const uint32_t *)g->row_ptr, (const uint32_t *)g->col,
+                                   (const uint32_t *)g->t0, (const uint32_t *)g->node_lo, (const uint32_t *)r.rows,
+                                   r.gp.stride, dpath, dlen, dcost, dsteps);
+                e = hipGetLastError();
+                if (e == hipSuccess) e = hipMemcpyAsync(out->path_len, dlen, 4ull * nq, hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipMemcpyAsync(out->cost_ms, dcost, 4ull * nq, hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(out->path_edges, dpath, sizeof(uint32_t) * (size_t)nq * max_steps,
+                                       hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipMemcpyAsync(out->steps_total, dsteps, 8, hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+            }
+        }
+        (void)hipStreamSynchronize(st);   // nothing may still use the buffers freed below
+    }
+    dfree(dq); dfree(dpath); dfree(dlen); dfree(dcost); dfree(dsteps);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(GMACOP_E_DEVICE, "gmacop_shortest_routes: %s", hipGetErrorString(e));
     return GMACOP_OK;
 }
 
@@ -3088,6 +3497,9 @@ struct gmacop_server {
     uint4 *rec32 = nullptr;   // global-walker road records with this router's costs
     GlbWork glb;
     uint8_t *vclass = nullptr;
+    // exact goal term: a row per slot, computed at admission
+    GoalPlan gp;
+    uint32_t *goal = nullptr, *goal_work = nullptr, *goal_ctl = nullptr;
     // device, per road: this router's frozen-load cost table
     uint32_t *t0 = nullptr, *wf = nullptr, *load = nullptr, *cost = nullptr, *cnt = nullptr, *tau = nullptr;
     uint64_t *dep_shared = nullptr;
@@ -3112,6 +3524,7 @@ struct gmacop_server {
         dfree(slot_od); dfree(slot_t); dfree(slot_gen); dfree(best_path); dfree(best_len); dfree(best_cost);
         dfree(iter_key); dfree(lazy); dfree(dep); dfree(steps); dfree(counters); dfree(touched); dfree(touched_n);
         dfree(path); dfree(ant_len); dfree(ant_cost); dfree(iter_max); dfree(vclass); dfree(rec32);
+        dfree(goal); dfree(goal_work); dfree(goal_ctl);
         glb.release();
         dfree(t0); dfree(wf); dfree(load); dfree(cost); dfree(cnt); dfree(tau); dfree(dep_shared);
         dfree(adm_slots); dfree(adm_gen); dfree(done_slots); dfree(done_path); dfree(done_len); dfree(done_cost);
@@ -3140,7 +3553,7 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
     if (!g || !p) return fail(GMACOP_E_INVAL, "graph or params is NULL");
     gmacop_params pp = *p;
     pp.mode = GMACOP_MODE_INDEPENDENT;
-    pp.flags &= GMACOP_TIME_KERNELS;
+    pp.flags &= GMACOP_TIME_KERNELS | GMACOP_GOAL_EXACT;   // loads are frozen; results go to host buffers
     int rc = validate_params(g, &pp, 1);
     if (rc) return rc;
     if (pp.iterations == 0 || pp.iterations > kLazyIterMax)
@@ -3156,8 +3569,12 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
     }
     const uint32_t A = pp.ants, S = pp.max_steps, m = g->m;
     s->tcap = (uint32_t)std::min<uint64_t>(m, (uint64_t)A * S);
+    if ((rc = goal_plan(g, &pp, 0xFFFFFFFFull, kGoalWorkBudget, &s->gp))) {
+        delete s;
+        return rc;
+    }
     s->per_slot = (size_t)m * 16 + (size_t)s->tcap * 4 + (size_t)A * S * 4 + (size_t)A * 8 +
-                  (size_t)S * 8 + sizeof(GlbVeh) + 64;
+                  (size_t)S * 8 + sizeof(GlbVeh) + 64 + (s->gp.on ? (size_t)s->gp.stride * 4 : 0);
     size_t budget = mem_budget_bytes;
     if (!budget) {
         size_t fr = 0, tot = 0;
@@ -3165,7 +3582,7 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
         budget = fr / 2;
     }
     // the global walker's visited words: a fixed amount, at most that of its full resident grid
-    size_t fixed = 0;
+    size_t fixed = s->gp.on ? s->gp.work_words() * 4 : 0;
     if (s->plan.glb) {
         WalkPlan full = s->plan;
         if ((rc = glb_grid(g->device, full, 0xFFFFFFFFull))) {
@@ -3201,7 +3618,10 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
         (rc = dalloc(&s->done_path, (size_t)NS * S)) || (rc = dalloc(&s->done_len, NS)) ||
         (rc = dalloc(&s->done_cost, NS)) || (s->plan.glb && (rc = glb_grid(g->device, s->plan, NA))) ||
         (s->plan.glb &&
-         (rc = glb_prepare(s->glb, NS, (uint64_t)s->plan.glb_blocks * s->plan.glb_apb, s->plan.glb_nwords)))) {
+         (rc = glb_prepare(s->glb, NS, (uint64_t)s->plan.glb_blocks * s->plan.glb_apb, s->plan.glb_nwords))) ||
+        (s->gp.on && ((rc = dalloc(&s->goal, (size_t)NS * s->gp.stride)) ||
+                      (rc = dalloc(&s->goal_work, std::max<size_t>(s->gp.work_words(), 1))) ||
+                      (rc = dalloc_zero(&s->goal_ctl, 2))))) {
         std::string keep = t_err;
         delete s;
         t_err = keep;
@@ -3317,6 +3737,15 @@ int server_step_impl(gmacop_server *s, const gmacop_od *admit, uint32_t take, ui
                            (const gmacop_od *)s->adm_od, (const uint32_t *)s->adm_gen, take, NS, s->slot_od, s->slot_t,
                            s->slot_gen, s->best_len, s->best_cost, s->iter_key);
         HIP_TRY(hipGetLastError());
+        if (s->gp.on) {   // Calc_Dist of the admitted queries: their exact goal rows
+            GoalArgs goa{};
+            goa.od = s->slot_od; goa.list = s->adm_slots; goa.ntask = take; goa.n = g->n; goa.stride = s->gp.stride;
+            goa.qcap = s->gp.qcap; goa.node_inst = g->node_inst; goa.inst_off = g->inst_off_dev;
+            goa.rev_ptr = g->rev_ptr; goa.rev_tw = g->rev_tw; goa.goal = s->goal; goa.work = s->goal_work;
+            goa.ctl = s->goal_ctl;
+            hipLaunchKernelGGL(k_goal_sssp, dim3(std::min(s->gp.blocks, take)), dim3(256), 0, st, goa);
+            HIP_TRY(hipGetLastError());
+        }
         s->admitted += take;
     }
 
@@ -3334,7 +3763,8 @@ int server_step_impl(gmacop_server *s, const gmacop_od *admit, uint32_t take, ui
                        g->n, (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, s->vclass);
     if (plan.glb) {
         const GlbListArgs gla{s->slot_od, s->vclass, g->row_ptr, g->node_lo, g->x, g->y, NS, A, kgoal,
-                              s->glb.vrec, s->glb.veh, s->glb.ctl, s->glb.vlen, s->ant_len, s->ant_cost};
+                              s->glb.vrec, s->glb.veh, s->glb.ctl, s->glb.vlen, s->ant_len, s->ant_cost,
+                              s->gp.on ? s->goal : nullptr, s->gp.stride};
         hipLaunchKernelGGL(k_glb_prep, dim3(blocks_for(NS, 256)), dim3(256), 0, st, gla);
         hipLaunchKernelGGL(k_glb_list, dim3(1), dim3(1024), 0, st, gla);
     }
@@ -3351,6 +3781,7 @@ int server_step_impl(gmacop_server *s, const gmacop_od *admit, uint32_t take, ui
         la.seed_hi = (uint32_t)(p.seed >> 32); la.iter = p.iter_offset; la.t_local = 0; la.q_deposit = p.q_deposit;
         la.path = s->path; la.ant_len = s->ant_len; la.ant_cost = s->ant_cost; la.iter_key = s->iter_key;
         la.steps = s->steps; la.counters = g->counters; la.iter_max = g->iter_max;
+        la.goal = s->gp.on ? s->goal : nullptr; la.goal_stride = s->gp.stride;
         if (plan.any_lds() && ((rc = setup_walk_lds(la, plan, st)) || (rc = launch_walk_lds_classes(la, plan, st))))
             return rc;
         if (plan.glb) {
@@ -3364,6 +3795,7 @@ int server_step_impl(gmacop_server *s, const gmacop_od *admit, uint32_t take, ui
             ga.t_local = 0; ga.q_deposit = p.q_deposit; ga.path = s->path; ga.ant_len = s->ant_len;
             ga.ant_cost = s->ant_cost; ga.iter_key = s->iter_key; ga.steps = s->steps;
             ga.counters = g->counters; ga.iter_max = g->iter_max;
+            ga.goal = la.goal; ga.goal_stride = s->gp.stride;
             if ((rc = launch_walk_glb_any(ga, plan, st))) return rc;
         }
     }

@@ -30,9 +30,10 @@ DEVICE_PTRS = 2
 
 TIME_KERNELS = 4
 HIP_GRAPH = 8
+GOAL_EXACT = 16
 
 EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_route_batch_noalloc", "gmacop_state_get", "gmacop_vehicle_tau_get",
-            "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
+            "gmacop_goal_rows", "gmacop_shortest_routes", "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
             "gmacop_server_release", "gmacop_release", "gmacop_last_error")
 KERNELS = ("walk", "best", "edge", "cost", "walk_lds", "walk_glb")
 WALKERS = ("lds", "glb", "first")
@@ -102,6 +103,10 @@ def lib():
         L.gmacop_state_get.restype = C.c_int
         L.gmacop_vehicle_tau_get.argtypes = [vp, C.c_uint32, vp, vp]
         L.gmacop_vehicle_tau_get.restype = C.c_int
+        L.gmacop_goal_rows.argtypes = [vp, vp, C.c_uint32, vp, vp]
+        L.gmacop_goal_rows.restype = C.c_int
+        L.gmacop_shortest_routes.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(_Result), vp]
+        L.gmacop_shortest_routes.restype = C.c_int
         L.gmacop_stats_get.argtypes = [vp, C.POINTER(_Stats), C.c_int, vp]
         L.gmacop_stats_get.restype = C.c_int
         u32p = C.POINTER(C.c_uint32)
@@ -246,6 +251,29 @@ def gmacop_vehicle_tau_get(g: Graph, vehicle: int, stream: Optional[int] = None)
     tau = np.zeros(g.m, np.uint32)
     _check(lib().gmacop_vehicle_tau_get(g.handle, int(vehicle), tau.ctypes.data, stream))
     return tau
+
+
+def gmacop_goal_rows(g: Graph, dst, stream: Optional[int] = None) -> np.ndarray:
+    """Exact goal term rows: uint32 [len(dst), n], shortest free-flow time of
+    every node to each destination (0xFFFFFFFF: out of reach)."""
+    d = np.ascontiguousarray(dst, np.uint32).reshape(-1)
+    h = np.zeros((d.shape[0], g.n), np.uint32)
+    _check(lib().gmacop_goal_rows(g.handle, d.ctypes.data if d.shape[0] else None, d.shape[0],
+                                  h.ctypes.data if d.shape[0] else None, stream))
+    return h
+
+
+def gmacop_shortest_routes(g: Graph, veh, max_steps: int, stream: Optional[int] = None) -> dict:
+    """Shortest free-flow route per vehicle (road ids), as gmacop_route_batch's result dict."""
+    od = _od_array(veh)
+    V, S = od.shape[0], int(max_steps)
+    path = np.zeros((V, max(S, 1)), np.uint32)
+    plen = np.zeros(V, np.uint32)
+    cost = np.zeros(V, np.uint32)
+    steps = np.zeros(1, np.uint64)
+    res = _Result(path.ctypes.data, plen.ctypes.data, cost.ctypes.data, steps.ctypes.data)
+    _check(lib().gmacop_shortest_routes(g.handle, od.ctypes.data if V else None, V, S, C.byref(res), stream))
+    return dict(path_edges=path, path_len=plen, cost_ms=cost, steps_total=int(steps[0]))
 
 
 def gmacop_stats_get(g: Graph, reset: bool = False, stream: Optional[int] = None) -> dict:

@@ -51,6 +51,8 @@ MUTANTS = {
         """    for (uint32_t u = 0; u <= n; ++u) rp[u] = g->row_ptr[u];
     uint32_t *fill = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
     for (uint32_t e = 0; e < m; ++e) { ru[e] = g->col[e]; rw[e] = t0[e]; }"""),
+    "shortest_route_last_tight": ("if ((uint64_t)t0[e] + h[g->col[e]] == h[u]) { next = e; break; }",
+                                  "if ((uint64_t)t0[e] + h[g->col[e]] == h[u]) { next = e; }"),
     "apply_after_load_update": (
         """            for (uint32_t e = 0; e < m; ++e) tau[e] = orc_apply_tau(p, tau[e], dep[e], load[e]);
             if (!(p->flags & ORC_FLAG_NO_LOAD_UPDATE)) {

@@ -847,3 +847,37 @@ def test_exact_goal_routes_are_valid_and_bounded(orc, mode):
     ot = dijkstra(At, indices=Vt.src.astype(np.int64))
     for v in range(3):
         assert rt["cost_ms"][v] == int(ot[v, Vt.dst[v]])
+
+
+def test_shortest_route_is_a_shortest_path(orc):
+    """The Dijkstra baseline: a simple connected src -> dst route whose
+    free-flow time equals scipy's shortest distance, every road tight."""
+    rng = np.random.default_rng(23)
+    g = planar_graph(1200, rng)
+    p = default_params()
+    t0, _ = orc.edge_static(g, p)
+    A = sp.csr_matrix((t0.astype(np.float64), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
+                      shape=(g.n, g.n))
+    V = random_od(g.n, 12, rng)
+    d = dijkstra(A, indices=V.src.astype(np.int64))
+    tails = g.tail()
+    for v in range(len(V)):
+        path = orc.shortest_route(g, p, int(V.src[v]), int(V.dst[v]), 4096)
+        assert path.shape[0] > 0
+        assert tails[path[0]] == V.src[v] and g.col[path[-1]] == V.dst[v]
+        assert np.all(tails[path[1:]] == g.col[path[:-1]])
+        nodes = np.concatenate([[V.src[v]], g.col[path]])
+        assert np.unique(nodes).shape[0] == nodes.shape[0]
+        assert int(t0[path.astype(np.int64)].astype(np.int64).sum()) == int(d[v, V.dst[v]])
+
+
+def test_shortest_route_ties_and_limits(orc):
+    """Two equal routes 0 -> 1 -> 3 and 0 -> 2 -> 3: the first road in road
+    order (0 -> 1, road 0) is taken.  Out of reach, or longer than the
+    limit: empty."""
+    g = from_edges(5, [0, 0, 1, 2], [1, 2, 3, 3], len_dm=1000, speed_kmh=50)
+    p = default_params()
+    assert orc.shortest_route(g, p, 0, 3, 8).tolist() == [0, 2]
+    assert orc.shortest_route(g, p, 0, 4, 8).tolist() == []
+    assert orc.shortest_route(g, p, 0, 3, 1).tolist() == []
+    assert orc.shortest_route(g, p, 0, 1, 1).tolist() == [0]
