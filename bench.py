@@ -159,10 +159,44 @@ def measure_forms(gmacop, G, w, stream_obj, max_vehicles):
             "routed_fraction": float((rb["path_len"] > 0).mean()) if nv else None}
 
 
-def run_serving(args, log):
+def measure_goal_exact(gmacop, G, w, b, stream_obj, steps, log):
+    """The same batched workload with the exact goal term (the shortest
+    free-flow time to each vehicle's destination, searched on the device once
+    per call): selections/s over `steps` whole calls, routed fraction, ant
+    arrival rate, and the search's and walks' event-timed share of a call."""
+    p = dict(w.params, flags=w.params["flags"] | gmacop.GOAL_EXACT)
+    stream = stream_obj.cuda_stream
+    pg = dict(p, flags=p["flags"] | gmacop.HIP_GRAPH)
+    gmacop.gmacop_route_batch_device(G, b, pg, stream)          # warm-up + capture
+    stream_obj.synchronize()
+    gmacop.gmacop_stats_get(G, reset=True)
+    t = time.perf_counter()
+    for _ in range(steps):
+        gmacop.gmacop_route_batch_device(G, b, pg, stream)
+    stream_obj.synchronize()
+    dt = time.perf_counter() - t
+    st = gmacop.gmacop_stats_get(G, reset=True)
+    res = b.result()
+    gmacop.gmacop_route_batch_device(G, b, dict(p, flags=p["flags"] | gmacop.TIME_KERNELS), stream)
+    stream_obj.synchronize()
+    kt = gmacop.gmacop_stats_get(G, reset=True)
+    V = len(w.vehicles)
+    out = {"value": st["selections"] / dt, "unit": "edge-selections/s", "ms_per_step": dt / steps * 1e3,
+           "steps": steps, "routed_fraction": float((res["path_len"] > 0).mean()) if V else None,
+           "ant_arrival_rate": st["arrivals"] / max(1, steps * V * p["ants"] * p["iterations"]),
+           "goal_search_ms": kt["ms"]["goal"], "walk_phase_ms": kt["ms"]["walk"],
+           "selections_per_step": st["selections"] // max(1, steps)}
+    log(f"[bench] exact goal: {out['value'] / 1e9:.2f} G selections/s, {out['ms_per_step']:.1f} ms/call "
+        f"(search {out['goal_search_ms']:.2f} ms), routed {out['routed_fraction']:.3f}, "
+        f"arrivals {out['ant_arrival_rate']:.3f}")
+    return out
+
+
+def run_serving(args, log, exact=False):
     """Continuous-batching router on the 1M-node city: Poisson arrivals at
     each rate in --rates, 32 ants x 20 iterations per query.  Latency is
-    arrival to result, queueing for a slot included."""
+    arrival to result, queueing for a slot included.  exact: the goal term is
+    the exact shortest free-flow time, searched when a query is admitted."""
     import numpy as np
     import workloads
     from paper_2010_14244_amd import gmacop, serve
@@ -171,6 +205,8 @@ def run_serving(args, log):
     log("[bench] generating the serving city")
     w = workloads.serving_city(n=args.serve_nodes)
     g, p = w.graph, dict(w.params)
+    if exact:
+        p["flags"] |= gmacop.GOAL_EXACT
     G = gmacop.gmacop_graph_create(g)
     srv = gmacop.Server(G, p, max_slots=args.serve_slots)
     stream_obj = torch.cuda.Stream()
@@ -178,7 +214,7 @@ def run_serving(args, log):
     log(f"[bench] {w.name}: n={g.n} m={g.m} slots={srv.slots} ({srv.bytes_per_slot / 2**20:.1f} MiB each)")
     rng = np.random.default_rng(7)
     qid0, runs = 0, []
-    for rate in [float(r) for r in args.rates.split(",")]:
+    for rate in [float(r) for r in (args.exact_rates if exact else args.rates).split(",")]:
         n = max(int(rate * args.serve_seconds), args.serve_min_queries + args.serve_warmup)
         od = workloads.query_stream(g, n, rng, qid0=qid0)
         qid0 += n
@@ -197,13 +233,16 @@ def run_serving(args, log):
                "routed_p99_ms": float(np.percentile(lat_routed, 99) * 1e3) if lat_routed.size else None,
                "ant_arrival_rate": st["arrivals"] / max(1, n * p["ants"] * p["iterations"]),
                "steps": r["steps"], "edge_selections_per_s": st["selections"] / r["wall_s"]}
+        if exact:
+            run["goal_searches"] = st["launches"]["goal"]
         runs.append(run)
         log(f"[bench] serve {rate:.0f}/s: sustained {r['sustained_qps']:.0f}/s p50 {r['p50_ms']:.1f} ms "
             f"p99 {r['p99_ms']:.1f} ms routed {run['routed_fraction']:.3f}, {r['steps']} steps")
     srv.release()
     gmacop.gmacop_release(G)
     return {"workload": w.name, "nodes": g.n, "roads": g.m, "ants": p["ants"], "iterations": p["iterations"],
-            "max_steps": p["max_steps"], "slots": srv.slots, "mode": "independent", "runs": runs}
+            "max_steps": p["max_steps"], "slots": srv.slots, "mode": "independent",
+            "goal": "exact shortest free-flow time" if exact else "straight line at the top speed", "runs": runs}
 
 
 def walker_roofline(st, kernel_ms_key, walker_key, workload, names):
@@ -236,8 +275,10 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200, help="router: queries excluded from latency stats")
     ap.add_argument("--serve-slots", type=int, default=4096, help="router: slot limit (memory may allow fewer)")
     ap.add_argument("--serve-nodes", type=int, default=1_000_000, help="router: city size")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact-goal-term runs")
+    ap.add_argument("--exact-rates", default="2000,5000", help="router with the exact goal term: offered rates")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-vehicles", type=int, default=256, help="CPU oracle: the first this many vehicles")
+    ap.add_argument("--cpu-vehicles", type=int, default=640, help="CPU oracle: the first this many vehicles")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed pass (roofline becomes null)")
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
@@ -359,6 +400,8 @@ def main():
         "roofline": roofline,
         "walkers": walkers,
     }
+    if not args.no_exact:
+        out["goal_exact"] = measure_goal_exact(gmacop, G, w, b, stream_obj, args.steps, log)
     if not args.no_forms:
         log("[bench] plain per-query vs batched (independent mode)")
         out["forms"] = measure_forms(gmacop, G, w, stream_obj, args.forms_vehicles)
@@ -370,6 +413,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_serve:
         out["serving"] = run_serving(args, log)
+        if not args.no_exact:
+            out["serving_goal_exact"] = run_serving(args, log, exact=True)
     if not args.no_cpu:
         log(f"[bench] timing the CPU oracle on the first {args.cpu_vehicles} vehicles")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_vehicles)

@@ -218,13 +218,13 @@ int gmacop_shortest_routes(gmacop_graph *g, const gmacop_od *q, uint32_t nq, uin
  * deposit, all walkers of an iteration), 1 = best-route reduction, 2 =
  * pheromone/load update, 3 = signal and cost table, 4 = the LDS walkers of an
  * iteration (cities staged in on-chip memory), 5 = the global-memory walker
- * of an iteration.  ms[] is filled only for calls made with
+ * of an iteration, 6 = the exact goal search of a call (GMACOP_GOAL_EXACT).  ms[] is filled only for calls made with
  * GMACOP_TIME_KERNELS (times from HIP events on the stream each kernel runs
  * on).  walker_*[k]: the same counters per walker kind, k = 0 LDS walkers,
  * 1 global-memory walker, 2 first walker (graphs of 2^24 nodes or more). */
 typedef struct {
-    uint64_t launches[6];
-    double ms[6];
+    uint64_t launches[7];
+    double ms[7];
     uint64_t selections;     /* roulette selections (one per road an ant takes)       */
     uint64_t candidates;     /* out-roads examined at those selections                */
     uint64_t arrivals;       /* ants that reached their destination                   */

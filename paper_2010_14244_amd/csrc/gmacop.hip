@@ -79,7 +79,8 @@ constexpr uint32_t kLdsBitsetMaxNodes = 4096;   // 512 B of visited bits per ant
 constexpr int kWalkerCounters = 5;
 constexpr int kCounters = kWalkerCounters + 4 * 3;
 constexpr int kKindLds = 0, kKindGlb = 1, kKindFirst = 2;
-constexpr int kTimedKernels = 6;   // walk phase, best route, update, cost table, LDS walkers, global walker
+constexpr int kTimedKernels = 7;   // walk phase, best route, update, cost table, LDS walkers, global walker,
+                                   // exact goal search
 
 // ---------------------------------------------------------------------------
 // device arithmetic
@@ -1744,11 +1745,11 @@ struct GoalArgs {
     const gmacop_od *od;       // queries; the destination of task v is od[v].dst
     const uint32_t *list;      // task i is vehicle list[i] (router: admitted slots), or NULL: vehicle i
     const uint32_t *dsts;      // or, when not NULL: task i is the destination dsts[i], row i
-    uint32_t ntask, n, stride, qcap;
+    uint32_t ntask, n, stride, qcap, fcap, delta;
     const uint32_t *node_inst, *inst_off, *rev_ptr;
     const uint2 *rev_tw;       // [m] (tail, free-flow time) of the in-roads of each node
-    uint32_t *goal;            // [vehicles][stride] rows, city-local node ids
-    uint32_t *work;            // per block: stamp [stride], two queues [qcap]
+    uint32_t *goal;            // [vehicles][stride] rows, city-local node ids (the terms, lowered in place)
+    uint32_t *work;            // per block: done [stride], fmark [stride], near queues 2 x qcap, far queues 2 x fcap
     uint32_t *ctl;             // [0] next task, [1] blocks done (the last block out resets both)
 };
 
@@ -1757,21 +1758,40 @@ __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr uint32_t kGoalFar = 0xFFFFFFFFu;   // goal term of a node that cannot reach the destination
+constexpr uint32_t kGoalCap = 0xFFFFFFFEu;   // largest finite goal term
+
 // Calc_Dist (Alg. 2 step 1) as an exact term: for each task's vehicle, the
 // shortest free-flow time from every node of its city to its destination,
 // min(d, 2^32 - 2), and 2^32 - 1 where the destination is out of reach.  A
 // persistent grid; a block takes one destination at a time and relaxes the
-// reversed roads from a frontier (label correcting: a node whose term drops
-// is queued for the next round, at most once per round by its round stamp),
-// until no term drops.  The result is the unique shortest-distance vector,
-// whatever order the relaxations run in.  When a round's frontier would
-// overflow its queue the next round scans the stamps of the whole city.
-__global__ __launch_bounds__(256) void k_goal_sssp(GoalArgs a)
+// reversed roads (label correcting).  The result is the unique
+// shortest-distance vector, whatever order the relaxations run in; the order
+// only decides the work.
+//
+// Order (near-far): terms below a moving split are relaxed first, in rounds
+// from a near queue; a term lowered to or above the split goes to a far
+// queue (once per phase, by a phase mark).  When the near queue runs dry the
+// split moves up by delta and the far queue is sorted again into near and
+// far.  A node is pending while its term is below done[x], the term it was
+// last relaxed with; queues only point at candidates, so a stale or repeated
+// entry is skipped.  If a queue would overflow, the task switches to scan
+// rounds: every pending node of the city below the split, with the split
+// moved to the smallest pending term when none is left.  The block size is
+// chosen per call, so the kernel takes it from blockDim.
+__global__ __launch_bounds__(1024) void k_goal_sssp(GoalArgs a)
 {
-    __shared__ uint32_t s_task, s_next, s_ovf;
+    __shared__ uint32_t s_task, s_nn, s_fn, s_ovf, s_work, s_min;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
-    uint32_t *stamp = a.work + (size_t)blockIdx.x * (a.stride + 2 * (size_t)a.qcap);
-    uint32_t *qa = stamp + a.stride, *qb = qa + a.qcap;
+    uint32_t *done = a.work + (size_t)blockIdx.x * (2 * (size_t)a.stride + 2 * (size_t)a.qcap + 2 * (size_t)a.fcap);
+    uint32_t *fmark = done + a.stride;
+    uint32_t *nq[2] = {fmark + a.stride, fmark + a.stride + a.qcap};
+    uint32_t *fq[2] = {nq[1] + a.qcap, nq[1] + a.qcap + a.fcap};
     for (;;) {
         if (tid == 0) s_task = atomicAdd(&a.ctl[0], 1u);
         __syncthreads();
@@ -1790,60 +1810,134 @@ __global__ __launch_bounds__(256) void k_goal_sssp(GoalArgs a)
         }
         const uint32_t city = a.node_inst[q.dst];
         const uint32_t n_lo = a.inst_off[city], nc = a.inst_off[city + 1] - n_lo;
-        uint32_t *row = a.goal + (size_t)v * a.stride;
         const uint32_t dl = q.dst - n_lo;
+        uint32_t *dist = a.goal + (size_t)v * a.stride;
         for (uint32_t i = tid; i < nc; i += nthr) {
-            row[i] = i == dl ? 0u : 0xFFFFFFFFu;
-            stamp[i] = 0;
+            dist[i] = i == dl ? 0u : kGoalFar;
+            done[i] = kGoalFar;
+            fmark[i] = 0;
         }
-        if (tid == 0) qa[0] = dl;
-        uint32_t F = 1;
-        bool scan = false;       // this round's frontier is every node stamped with the previous round
-        uint32_t *cur = qa, *nxt = qb;
+        if (tid == 0) nq[0][0] = dl;
+        uint32_t nn = 1, nf = 0, ncur = 0, fcur = 0, phase = 1;
+        uint64_t split = a.delta;
+        bool scan = false;       // sticky: a queue overflowed, rounds scan the city
         __syncthreads();
-        for (uint32_t r = 1;; ++r) {
-            if (tid == 0) {
-                s_next = 0;
-                s_ovf = 0;
-            }
-            __syncthreads();
-            const uint32_t lim = scan ? nc : F;
-            for (uint32_t i = tid; i < lim; i += nthr) {
-                uint32_t x;
-                if (scan) {
-                    if (ld_agent(&stamp[i]) != r - 1) continue;
-                    x = i;
-                } else {
-                    x = ld_agent(&cur[i]);
+        for (;;) {
+            // ---- near rounds: relax pending nodes below the split until none is left ----
+            for (;;) {
+                if (tid == 0) {
+                    s_nn = 0;
+                    s_ovf = 0;
+                    s_work = 0;
+                    s_fn = nf;
                 }
-                const uint64_t d = ld_agent(&row[x]);
-                const uint32_t jb = a.rev_ptr[n_lo + x], je = a.rev_ptr[n_lo + x + 1];
-                for (uint32_t jj = jb; jj < je; ++jj) {
-                    const uint2 tw = a.rev_tw[jj];
-                    const uint32_t ul = tw.x - n_lo;
-                    const uint64_t s = d + tw.y;
-                    const uint32_t nd = s > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)s;
-                    if (nd < ld_agent(&row[ul])) {
-                        const uint32_t old = atomicMin(&row[ul], nd);
-                        if (nd < old && atomicExch(&stamp[ul], r) != r) {
-                            const uint32_t pos = atomicAdd(&s_next, 1u);
-                            if (pos < a.qcap)
-                                __hip_atomic_store(&nxt[pos], ul, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            else
-                                s_ovf = 1;
+                __syncthreads();
+                const uint32_t lim = scan ? nc : nn;
+                const uint32_t *src = nq[ncur];
+                uint32_t *dstq = nq[ncur ^ 1], *far = fq[fcur];
+                for (uint32_t i = tid; i < lim; i += nthr) {
+                    const uint32_t x = scan ? i : ld_agent(&src[i]);
+                    const uint32_t d = ld_agent(&dist[x]);
+                    if (d >= ld_agent(&done[x]) || d >= split) continue;   // relaxed already, or not near yet
+                    atomicMin(&done[x], d);   // (a smaller term relaxed by another thread keeps its mark)
+                    if (scan) s_work = 1;
+                    const uint32_t jb = a.rev_ptr[n_lo + x], je = a.rev_ptr[n_lo + x + 1];
+                    for (uint32_t j0 = jb; j0 < je; j0 += 8) {   // up to eight in-roads with their atomics in flight
+                        uint32_t ul[8], nd[8], old[8];
+#pragma unroll
+                        for (uint32_t u = 0; u < 8; ++u) {
+                            ul[u] = 0;
+                            nd[u] = kGoalFar;
+                            if (j0 + u < je) {
+                                const uint2 tw = a.rev_tw[j0 + u];
+                                const uint64_t s = (uint64_t)d + tw.y;
+                                ul[u] = tw.x - n_lo;
+                                nd[u] = s > kGoalCap ? kGoalCap : (uint32_t)s;
+                            }
+                        }
+#pragma unroll
+                        for (uint32_t u = 0; u < 8; ++u) old[u] = j0 + u < je ? atomicMin(&dist[ul[u]], nd[u]) : 0u;
+#pragma unroll
+                        for (uint32_t u = 0; u < 8; ++u) {
+                            if (!(j0 + u < je && nd[u] < old[u]) || scan) continue;
+                            if (nd[u] < split) {
+                                const uint32_t pos = atomicAdd(&s_nn, 1u);
+                                if (pos < a.qcap) st_agent(&dstq[pos], ul[u]);
+                                else s_ovf = 1;
+                            } else if (atomicExch(&fmark[ul[u]], phase) != phase) {
+                                const uint32_t pos = atomicAdd(&s_fn, 1u);
+                                if (pos < a.fcap) st_agent(&far[pos], ul[u]);
+                                else s_ovf = 1;
+                            }
                         }
                     }
                 }
+                __syncthreads();
+                const bool more = scan ? s_work != 0 : s_nn != 0;
+                const bool ovf = s_ovf != 0;
+                nn = s_nn;
+                nf = s_fn;
+                if (ovf) scan = true;
+                ncur ^= 1;
+                __syncthreads();   // every thread has read the counters before they are reset
+                if (!more && !ovf) break;
             }
-            __syncthreads();
-            F = s_next;
-            scan = s_ovf != 0;
-            uint32_t *tq = cur;
-            cur = nxt;
-            nxt = tq;
-            __syncthreads();   // every thread has read s_next and s_ovf before they are reset
-            if (F == 0) break;
+            // ---- move the split up ----
+            if (scan) {   // the smallest pending term of the city, if any
+                if (tid == 0) s_min = kGoalFar;
+                __syncthreads();
+                for (uint32_t i = tid; i < nc; i += nthr) {
+                    const uint32_t d = ld_agent(&dist[i]);
+                    if (d < ld_agent(&done[i])) atomicMin(&s_min, d);
+                }
+                __syncthreads();
+                const uint32_t mn = s_min;
+                __syncthreads();
+                if (mn == kGoalFar) break;
+                split = ((uint64_t)mn / a.delta + 1) * a.delta;
+                continue;
+            }
+            if (nf == 0) break;
+            split += a.delta;
+            for (;;) {   // sort the far queue into near (below the new split) and the next far queue
+                ++phase;
+                if (tid == 0) {
+                    s_nn = 0;
+                    s_fn = 0;
+                    s_ovf = 0;
+                    s_min = kGoalFar;
+                }
+                __syncthreads();
+                const uint32_t *fsrc = fq[fcur];
+                uint32_t *fdst = fq[fcur ^ 1], *near = nq[ncur];
+                for (uint32_t i = tid; i < nf; i += nthr) {
+                    const uint32_t y = ld_agent(&fsrc[i]);
+                    const uint32_t d = ld_agent(&dist[y]);
+                    if (d >= ld_agent(&done[y])) continue;   // relaxed since it was queued
+                    if (d < split) {
+                        const uint32_t pos = atomicAdd(&s_nn, 1u);
+                        if (pos < a.qcap) st_agent(&near[pos], y);
+                        else s_ovf = 1;
+                    } else if (atomicExch(&fmark[y], phase) != phase) {
+                        atomicMin(&s_min, d);
+                        const uint32_t pos = atomicAdd(&s_fn, 1u);
+                        if (pos < a.fcap) st_agent(&fdst[pos], y);
+                        else s_ovf = 1;
+                    }
+                }
+                __syncthreads();
+                nn = s_nn;
+                nf = s_fn;
+                const uint32_t mn = s_min;
+                if (s_ovf) scan = true;
+                fcur ^= 1;
+                __syncthreads();
+                if (scan || nn > 0 || nf == 0) break;
+                split = ((uint64_t)mn / a.delta + 1) * a.delta;   // skip empty bands
+            }
+            if (!scan && nn == 0 && nf == 0) break;
         }
+        __syncthreads();   // the workspace is rewritten by the next task
     }
     if (tid == 0) {
         __threadfence();
@@ -2059,6 +2153,7 @@ struct gmacop_graph {
     // the in-roads as (tail, free-flow time)
     size_t cap_goal = 0, cap_goal_work = 0;
     uint32_t *goal = nullptr, *goal_work = nullptr, *goal_ctl = nullptr;
+    uint32_t mean_t0 = 1;              // mean free-flow road time (ms), the scale of the search's bands
     uint2 *rev_tw = nullptr;
     // statistics
     uint64_t *counters = nullptr;         // device [kCounters]
@@ -2643,6 +2738,14 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
         delete g;
         return fail(GMACOP_E_DEVICE, "hipMemset of counters failed");
     }
+    {   // the mean free-flow road time, the band width scale of the exact goal search
+        long double sum = 0;
+        for (uint32_t e = 0; e < m; ++e) {
+            uint64_t x = (uint64_t)d->len_dm[e] * 360u / d->speed_kmh[e];
+            sum += (long double)(x < 1 ? 1 : (x > kRoadCostCap ? kRoadCostCap : x));
+        }
+        g->mean_t0 = (uint32_t)std::max<long double>(1.0L, sum / m);
+    }
     // static: free-flow times and the in-roads as (tail, free-flow time), for the exact goal term
     if ((rc = dalloc(&g->rev_tw, m))) {
         std::string keep = t_err;
@@ -2689,27 +2792,47 @@ struct CallWork {
 // two frontier queues) stays within a budget.
 struct GoalPlan {
     bool on = false;
-    uint32_t stride = 0, qcap = 0, blocks = 0;
-    size_t work_words() const { return (size_t)blocks * (stride + 2 * (size_t)qcap); }
+    uint32_t stride = 0, qcap = 0, fcap = 0, delta = 1, blocks = 0, threads = 0;
+    // u32 words of the per-block workspace: relaxed-at terms, phase marks, two near and two far queues
+    size_t work_words() const { return (size_t)blocks * (2 * (size_t)stride + 2 * (size_t)qcap + 2 * (size_t)fcap); }
 };
 
-constexpr uint64_t kGoalWorkBudget = 2ull << 30;   // bytes of the search's per-block workspace
+constexpr uint64_t kGoalWorkBudget = 8ull << 30;   // bytes of the search's per-block workspace
 
-int goal_plan(const gmacop_graph *g, const gmacop_params *p, uint64_t tasks, uint64_t budget, GoalPlan *gp)
+// tasks: destinations searched by one launch; threads 0 = choose so that the
+// resident blocks together hold about as many threads as the device can
+// keep (one wave per destination when there are many, up to 1024 when few).
+// The band of the near-far order is a few mean free-flow road times.
+int goal_plan(const gmacop_graph *g, const gmacop_params *p, uint64_t tasks, uint64_t budget, uint32_t threads,
+              GoalPlan *gp)
 {
     *gp = GoalPlan{};
     if (!(p->flags & GMACOP_GOAL_EXACT)) return GMACOP_OK;
     gp->on = true;
     gp->stride = std::max<uint32_t>(g->max_city_nodes, 1);
-    gp->qcap = std::min<uint32_t>(gp->stride, 65536);
-    if (const char *qc = getenv("GMACOP_GOAL_QCAP"))   // smaller frontier queues (exercises the scan rounds)
-        gp->qcap = std::max<uint32_t>(1, std::min<uint32_t>(gp->qcap, (uint32_t)strtoul(qc, nullptr, 10)));
-    int nb = 0, cus = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_goal_sssp, 256, 0));
+    gp->qcap = std::min<uint32_t>(gp->stride, 16384);
+    gp->fcap = std::min<uint32_t>(gp->stride, 32768);
+    if (const char *qc = getenv("GMACOP_GOAL_QCAP")) {   // smaller queues (exercises the scan rounds)
+        const uint32_t c = std::max<uint32_t>(1, (uint32_t)strtoul(qc, nullptr, 10));
+        gp->qcap = std::min(gp->qcap, c);
+        gp->fcap = std::min(gp->fcap, c);
+    }
+    const uint32_t mult = std::max<uint32_t>(1, env_u32("GMACOP_GOAL_DELTA", 4));
+    gp->delta = (uint32_t)std::min<uint64_t>(0x7FFFFFFFull, std::max<uint64_t>(1, (uint64_t)g->mean_t0 * mult));
+    int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
-    uint64_t blocks = (uint64_t)std::max(nb, 1) * (uint64_t)std::max(cus, 1);
+    cus = std::max(cus, 1);
+    if (!threads) {
+        const uint64_t per_task = 2048ull * (uint64_t)cus / std::max<uint64_t>(tasks, 1);
+        threads = 64;
+        while (threads < 1024 && threads * 2 <= per_task) threads *= 2;
+    }
+    gp->threads = threads;
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_goal_sssp, (int)threads, 0));
+    uint64_t blocks = (uint64_t)std::max(nb, 1) * (uint64_t)cus;
     blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(tasks, 1));
-    const uint64_t per_block = 4ull * (gp->stride + 2ull * gp->qcap);
+    const uint64_t per_block = 4ull * (2ull * gp->stride + 2ull * gp->qcap + 2ull * gp->fcap);
     blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(1, budget / per_block));
     gp->blocks = (uint32_t)blocks;
     return GMACOP_OK;
@@ -2913,7 +3036,8 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
     const GlbListArgs gla{od, w.vclass, g->row_ptr, g->node_lo, g->x, g->y, nq, p->ants, wa.kgoal,
                           w.gvrec, w.gveh, w.gctl, w.gvlen, w.ant_len, w.ant_cost, la.goal, gp.stride};
     GoalArgs goa{};
-    goa.od = od; goa.list = nullptr; goa.ntask = nq; goa.n = g->n; goa.stride = gp.stride; goa.qcap = gp.qcap;
+    goa.od = od; goa.list = nullptr; goa.ntask = nq; goa.n = g->n; goa.stride = gp.stride; goa.qcap = gp.qcap; goa.fcap = gp.fcap;
+    goa.delta = gp.delta;
     goa.node_inst = g->node_inst; goa.inst_off = g->inst_off_dev; goa.rev_ptr = g->rev_ptr; goa.rev_tw = g->rev_tw;
     goa.goal = w.goal; goa.work = w.goal_work; goa.ctl = w.goal_ctl;
     const bool any_lds = !plan.legacy && plan.any_lds();
@@ -2928,8 +3052,12 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
         KernelTimer kt{g, st, timing};
         gmacop_graph::Timed tm{}, tl{};
         hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(g->m, 256)), dim3(256), 0, st, ia);
-        if (gp.on && nq)   // Calc_Dist: the exact goal row of every vehicle, once per call
-            hipLaunchKernelGGL(k_goal_sssp, dim3(gp.blocks), dim3(256), 0, st, goa);
+        if (gp.on && nq) {   // Calc_Dist: the exact goal row of every vehicle, once per call
+            gmacop_graph::Timed tq{};
+            if ((erc = kt.start(6, &tq))) return erc;
+            hipLaunchKernelGGL(k_goal_sssp, dim3(gp.blocks), dim3(gp.threads), 0, st, goa);
+            if ((erc = kt.stop(&tq))) return erc;
+        }
         if (indep && nq) hipLaunchKernelGGL(k_next_generation, dim3(1), dim3(64), 0, st, w.dev_gen);
         hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
                            best_len, best_cost, w.iter_key, steps);
@@ -3021,7 +3149,7 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
             (uint64_t)lds, (uint64_t)(uintptr_t)w.vclass,
             (uint64_t)(uintptr_t)w.lazy, (uint64_t)(uintptr_t)w.dep_ind, (uint64_t)(uintptr_t)w.touched,
             (uint64_t)(uintptr_t)w.touched_n, (uint64_t)(uintptr_t)w.dev_gen, tcap, (uint64_t)w.side,
-            (uint64_t)gp.on, gp.stride, gp.qcap, gp.blocks, (uint64_t)(uintptr_t)w.goal,
+            (uint64_t)gp.on, gp.stride, gp.qcap, gp.fcap, gp.delta, gp.blocks, gp.threads, (uint64_t)(uintptr_t)w.goal,
             (uint64_t)(uintptr_t)w.goal_work, (uint64_t)(uintptr_t)w.goal_ctl};
         if (!g->gexec || key != g->gkey) {
             if (g->gexec) {
@@ -3057,6 +3185,7 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
         }
         g->launches[2] += p->iterations;
         if (update_loads) g->launches[3] += p->iterations;
+        if (gp.on && nq) g->launches[6] += 1;
         HIP_TRY(hipGraphLaunch(g->gexec, st));
     } else if ((rc = enqueue())) {
         return rc;
@@ -3193,7 +3322,7 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     GoalPlan gp;
-    if ((rc = goal_plan(g, p, nq, kGoalWorkBudget, &gp))) return rc;
+    if ((rc = goal_plan(g, p, nq, kGoalWorkBudget, 0, &gp))) return rc;
     CallWork w;
     if ((rc = route_work_grow(g, nq, p, plan, gp, st, &w))) return rc;
     return route_run(g, q, nq, p, out, st, plan, gp, w);
@@ -3216,7 +3345,7 @@ extern "C" int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, u
         plan.glb_blocks = (uint32_t)std::min<uint64_t>(plan.glb_blocks, cap);
     }
     GoalPlan gp;   // the search's workspace: at most a quarter of the scratch
-    if ((rc = goal_plan(g, p, nq, GMACOP_NOALLOC_SCRATCH_BYTES / 4, &gp))) return rc;
+    if ((rc = goal_plan(g, p, nq, GMACOP_NOALLOC_SCRATCH_BYTES / 4, 0, &gp))) return rc;
     const size_t need = carve_work(nullptr, g, nq, p, plan, gp, nullptr);
     if (need > GMACOP_NOALLOC_SCRATCH_BYTES)
         return fail(GMACOP_E_NOMEM, "call needs %zu bytes of workspace; gmacop_route_batch_noalloc has %llu", need,
@@ -3319,16 +3448,16 @@ int goal_run(gmacop_graph *g, const gmacop_od *od_dev, const uint32_t *dsts_dev,
     gmacop_params gpar{};
     gpar.flags = GMACOP_GOAL_EXACT;
     int rc;
-    if ((rc = goal_plan(g, &gpar, tasks, kGoalWorkBudget, &r->gp)) ||
+    if ((rc = goal_plan(g, &gpar, tasks, kGoalWorkBudget, 0, &r->gp)) ||
         (rc = dalloc(&r->rows, std::max<size_t>((size_t)tasks * r->gp.stride, 1))) ||
         (rc = dalloc(&r->work, std::max<size_t>(r->gp.work_words(), 1))) || (rc = dalloc(&r->ctl, 2)))
         return rc;
     HIP_TRY(hipMemsetAsync(r->ctl, 0, 2 * sizeof(uint32_t), st));
     GoalArgs goa{};
     goa.od = od_dev; goa.dsts = dsts_dev; goa.ntask = tasks; goa.n = g->n; goa.stride = r->gp.stride;
-    goa.qcap = r->gp.qcap; goa.node_inst = g->node_inst; goa.inst_off = g->inst_off_dev; goa.rev_ptr = g->rev_ptr;
+    goa.qcap = r->gp.qcap; goa.fcap = r->gp.fcap; goa.delta = r->gp.delta; goa.node_inst = g->node_inst; goa.inst_off = g->inst_off_dev; goa.rev_ptr = g->rev_ptr;
     goa.rev_tw = g->rev_tw; goa.goal = r->rows; goa.work = r->work; goa.ctl = r->ctl;
-    if (tasks) hipLaunchKernelGGL(k_goal_sssp, dim3(r->gp.blocks), dim3(256), 0, st, goa);
+    if (tasks) hipLaunchKernelGGL(k_goal_sssp, dim3(r->gp.blocks), dim3(r->gp.threads), 0, st, goa);
     HIP_TRY(hipGetLastError());
     return GMACOP_OK;
 }
@@ -3569,7 +3698,8 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
     }
     const uint32_t A = pp.ants, S = pp.max_steps, m = g->m;
     s->tcap = (uint32_t)std::min<uint64_t>(m, (uint64_t)A * S);
-    if ((rc = goal_plan(g, &pp, 0xFFFFFFFFull, kGoalWorkBudget, &s->gp))) {
+    // queries are searched as they are admitted, a few at a time: large blocks keep each search short
+    if ((rc = goal_plan(g, &pp, 0xFFFFFFFFull, kGoalWorkBudget / 4, 1024, &s->gp))) {
         delete s;
         return rc;
     }
@@ -3740,11 +3870,15 @@ int server_step_impl(gmacop_server *s, const gmacop_od *admit, uint32_t take, ui
         if (s->gp.on) {   // Calc_Dist of the admitted queries: their exact goal rows
             GoalArgs goa{};
             goa.od = s->slot_od; goa.list = s->adm_slots; goa.ntask = take; goa.n = g->n; goa.stride = s->gp.stride;
-            goa.qcap = s->gp.qcap; goa.node_inst = g->node_inst; goa.inst_off = g->inst_off_dev;
+            goa.qcap = s->gp.qcap; goa.fcap = s->gp.fcap; goa.delta = s->gp.delta; goa.node_inst = g->node_inst; goa.inst_off = g->inst_off_dev;
             goa.rev_ptr = g->rev_ptr; goa.rev_tw = g->rev_tw; goa.goal = s->goal; goa.work = s->goal_work;
             goa.ctl = s->goal_ctl;
-            hipLaunchKernelGGL(k_goal_sssp, dim3(std::min(s->gp.blocks, take)), dim3(256), 0, st, goa);
+            KernelTimer kq{g, st, (p.flags & GMACOP_TIME_KERNELS) != 0};
+            gmacop_graph::Timed tq{};
+            if ((rc = kq.start(6, &tq))) return rc;
+            hipLaunchKernelGGL(k_goal_sssp, dim3(std::min(s->gp.blocks, take)), dim3(s->gp.threads), 0, st, goa);
             HIP_TRY(hipGetLastError());
+            if ((rc = kq.stop(&tq))) return rc;
         }
         s->admitted += take;
     }

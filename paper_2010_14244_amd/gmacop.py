@@ -35,7 +35,7 @@ GOAL_EXACT = 16
 EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_route_batch_noalloc", "gmacop_state_get", "gmacop_vehicle_tau_get",
             "gmacop_goal_rows", "gmacop_shortest_routes", "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
             "gmacop_server_release", "gmacop_release", "gmacop_last_error")
-KERNELS = ("walk", "best", "edge", "cost", "walk_lds", "walk_glb")
+KERNELS = ("walk", "best", "edge", "cost", "walk_lds", "walk_glb", "goal")
 WALKERS = ("lds", "glb", "first")
 
 
@@ -71,7 +71,7 @@ class _Result(C.Structure):
 
 
 class _Stats(C.Structure):
-    _fields_ = [("launches", C.c_uint64 * 6), ("ms", C.c_double * 6), ("selections", C.c_uint64),
+    _fields_ = [("launches", C.c_uint64 * 7), ("ms", C.c_double * 7), ("selections", C.c_uint64),
                 ("candidates", C.c_uint64), ("arrivals", C.c_uint64), ("deposit_roads", C.c_uint64),
                 ("longest_walks", C.c_uint64), ("walker_selections", C.c_uint64 * 3),
                 ("walker_candidates", C.c_uint64 * 3), ("walker_arrivals", C.c_uint64 * 3),
