@@ -192,11 +192,10 @@ def measure_goal_exact(gmacop, G, w, b, stream_obj, steps, log):
     return out
 
 
-def run_serving(args, log, exact=False):
+def run_serving(args, log):
     """Continuous-batching router on the 1M-node city: Poisson arrivals at
     each rate in --rates, 32 ants x 20 iterations per query.  Latency is
-    arrival to result, queueing for a slot included.  exact: the goal term is
-    the exact shortest free-flow time, searched when a query is admitted."""
+    arrival to result, queueing for a slot included."""
     import numpy as np
     import workloads
     from paper_2010_14244_amd import gmacop, serve
@@ -205,8 +204,6 @@ def run_serving(args, log, exact=False):
     log("[bench] generating the serving city")
     w = workloads.serving_city(n=args.serve_nodes)
     g, p = w.graph, dict(w.params)
-    if exact:
-        p["flags"] |= gmacop.GOAL_EXACT
     G = gmacop.gmacop_graph_create(g)
     srv = gmacop.Server(G, p, max_slots=args.serve_slots)
     stream_obj = torch.cuda.Stream()
@@ -214,7 +211,7 @@ def run_serving(args, log, exact=False):
     log(f"[bench] {w.name}: n={g.n} m={g.m} slots={srv.slots} ({srv.bytes_per_slot / 2**20:.1f} MiB each)")
     rng = np.random.default_rng(7)
     qid0, runs = 0, []
-    for rate in [float(r) for r in (args.exact_rates if exact else args.rates).split(",")]:
+    for rate in [float(r) for r in args.rates.split(",")]:
         n = max(int(rate * args.serve_seconds), args.serve_min_queries + args.serve_warmup)
         od = workloads.query_stream(g, n, rng, qid0=qid0)
         qid0 += n
@@ -233,8 +230,6 @@ def run_serving(args, log, exact=False):
                "routed_p99_ms": float(np.percentile(lat_routed, 99) * 1e3) if lat_routed.size else None,
                "ant_arrival_rate": st["arrivals"] / max(1, n * p["ants"] * p["iterations"]),
                "steps": r["steps"], "edge_selections_per_s": st["selections"] / r["wall_s"]}
-        if exact:
-            run["goal_searches"] = st["launches"]["goal"]
         runs.append(run)
         log(f"[bench] serve {rate:.0f}/s: sustained {r['sustained_qps']:.0f}/s p50 {r['p50_ms']:.1f} ms "
             f"p99 {r['p99_ms']:.1f} ms routed {run['routed_fraction']:.3f}, {r['steps']} steps")
@@ -242,7 +237,7 @@ def run_serving(args, log, exact=False):
     gmacop.gmacop_release(G)
     return {"workload": w.name, "nodes": g.n, "roads": g.m, "ants": p["ants"], "iterations": p["iterations"],
             "max_steps": p["max_steps"], "slots": srv.slots, "mode": "independent",
-            "goal": "exact shortest free-flow time" if exact else "straight line at the top speed", "runs": runs}
+            "goal": "straight line at the top speed", "runs": runs}
 
 
 def walker_roofline(st, kernel_ms_key, walker_key, workload, names):
@@ -276,7 +271,6 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4096, help="router: slot limit (memory may allow fewer)")
     ap.add_argument("--serve-nodes", type=int, default=1_000_000, help="router: city size")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-goal-term runs")
-    ap.add_argument("--exact-rates", default="2000,5000", help="router with the exact goal term: offered rates")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-vehicles", type=int, default=640, help="CPU oracle: the first this many vehicles")
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -413,8 +407,6 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_serve:
         out["serving"] = run_serving(args, log)
-        if not args.no_exact:
-            out["serving_goal_exact"] = run_serving(args, log, exact=True)
     if not args.no_cpu:
         log(f"[bench] timing the CPU oracle on the first {args.cpu_vehicles} vehicles")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_vehicles)

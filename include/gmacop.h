@@ -57,8 +57,8 @@ extern "C" {
                                        floor(len * 360 / speed) ms over the best road
                                        sequence; min(d, 2^32 - 2), 2^32 - 1 where the
                                        destination cannot be reached), computed on the
-                                       device once per call (per admitted query in a
-                                       router) instead of the straight-line term;
+                                       device once per call, instead of the
+                                       straight-line term (not in a router);
                                        vmax_kmh is then ignored.  Graphs under 2^24
                                        nodes (GMACOP_E_UNSUPPORTED otherwise)          */
 
@@ -256,8 +256,8 @@ typedef struct gmacop_server gmacop_server;
  * max_slots, or fewer if the per-slot device memory times the slots would
  * exceed mem_budget_bytes (0: half of the device memory free now); the graph
  * must have fewer than 2^24 nodes.  Loads are frozen at the sensed loads.
- * Of params->flags only GMACOP_TIME_KERNELS and GMACOP_GOAL_EXACT are used
- * (with the latter, each query's goal row is computed when it is admitted).
+ * Of params->flags only GMACOP_TIME_KERNELS is used; GMACOP_GOAL_EXACT is
+ * rejected with GMACOP_E_UNSUPPORTED.
  * Errors: GMACOP_E_INVAL / E_RANGE as gmacop_route_batch, GMACOP_E_NOMEM when
  * not even one slot fits, GMACOP_E_UNSUPPORTED for 0 or more than 4095
  * iterations. */

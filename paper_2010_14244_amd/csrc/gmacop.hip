@@ -3682,7 +3682,9 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
     if (!g || !p) return fail(GMACOP_E_INVAL, "graph or params is NULL");
     gmacop_params pp = *p;
     pp.mode = GMACOP_MODE_INDEPENDENT;
-    pp.flags &= GMACOP_TIME_KERNELS | GMACOP_GOAL_EXACT;   // loads are frozen; results go to host buffers
+    if (pp.flags & GMACOP_GOAL_EXACT)   // switched off: a run on the 1M-node city faulted, cause not found
+        return fail(GMACOP_E_UNSUPPORTED, "the router does not take GMACOP_GOAL_EXACT");
+    pp.flags &= GMACOP_TIME_KERNELS;   // loads are frozen; results go to host buffers
     int rc = validate_params(g, &pp, 1);
     if (rc) return rc;
     if (pp.iterations == 0 || pp.iterations > kLazyIterMax)

@@ -175,6 +175,9 @@ def test_exact_goal_raises_arrivals_on_planar():
     assert s2["arrivals"] > s1["arrivals"] and (b["path_len"] > 0).sum() >= (a["path_len"] > 0).sum()
 
 
+@pytest.mark.skip(reason="the router rejects GMACOP_GOAL_EXACT: a router run with it on the 1M-node city "
+                         "faulted the GPU and the cause was not found (the search and the walkers pass their "
+                         "batch tests)")
 def test_exact_goal_router_matches_oracle():
     """Router with the exact term: every query's route equals an
     independent-mode oracle run of that query alone."""
@@ -205,3 +208,16 @@ def test_exact_goal_router_matches_oracle():
         path, cost = results[int(V.qid[v])]
         L = int(want["path_len"][v])
         assert cost == int(want["cost_ms"][v]) and path.tolist() == want["path_edges"][v, :L].tolist(), v
+
+
+def test_router_rejects_exact_goal():
+    rng = np.random.default_rng(46)
+    g = planar_graph(500, rng)
+    p = default_params(ants=8, iterations=3, max_steps=100, mode=gmacop.MODE_INDEPENDENT, flags=gmacop.GOAL_EXACT)
+    G = gmacop.gmacop_graph_create(g)
+    try:
+        with pytest.raises(gmacop.GmacopError) as e:
+            gmacop.Server(G, p, max_slots=4)
+        assert e.value.code == gmacop.E_UNSUPPORTED
+    finally:
+        gmacop.gmacop_release(G)
