@@ -62,6 +62,20 @@ extern "C" {
                                        vmax_kmh is then ignored.  Graphs under 2^24
                                        nodes (GMACOP_E_UNSUPPORTED otherwise)          */
 
+#define GMACOP_RESUME         32u   /* shared mode: start from the pheromone and loads
+                                       the graph holds (left by the previous call or
+                                       set by gmacop_state_set) instead of tau0 and
+                                       base_load, and from the best routes in `out`
+                                       (the previous call's results, passed back
+                                       unchanged) instead of none; with iter_offset =
+                                       the iterations already run, I1 iterations then
+                                       I - I1 resumed ones give the result of I in
+                                       one call.  GMACOP_E_UNSUPPORTED in independent
+                                       mode; GMACOP_E_INVAL for a held route longer
+                                       than max_steps or with a road out of range
+                                       (host buffers; device buffers are not checked,
+                                       such roads are ignored)                          */
+
 /* Opaque handle: the graph, its static per-road data and the pheromone / load
  * state on the device.  Owns all of its device memory. */
 typedef struct gmacop_graph gmacop_graph;
@@ -186,6 +200,17 @@ int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, uint32_t nq,
  * either may be NULL).  Synchronises hip_stream. */
 int gmacop_state_get(gmacop_graph *g, uint32_t *tau_q16, uint32_t *load, void *hip_stream);
 
+/* Replace the shared-mode state the graph holds (host arrays of n_edges
+ * entries; either may be NULL): the pheromone and the current road loads a
+ * call with GMACOP_RESUME starts from.  Synchronises hip_stream. */
+int gmacop_state_set(gmacop_graph *g, const uint32_t *tau_q16, const uint32_t *load, void *hip_stream);
+
+/* A new epoch of sensed loads (Section 4.2: vehicle densities from road
+ * sensors): base_load (host, n_edges entries) replaces the graph's sensed
+ * loads for every later gmacop_route_batch call (the loads a call starts
+ * from, and the base of its load update).  Synchronises hip_stream. */
+int gmacop_set_base_load(gmacop_graph *g, const uint32_t *base_load, void *hip_stream);
+
 /* Independent mode: pheromone of the vehicle at batch position `vehicle` of
  * the last gmacop_route_batch call on this graph, after its last iteration
  * (host array of n_edges entries).  GMACOP_E_INVAL if the last call was not
@@ -282,6 +307,14 @@ int gmacop_server_info(const gmacop_server *s, uint32_t *slots, uint32_t *active
 int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint32_t *n_admit, uint32_t *done_qid,
                        uint32_t *done_len, uint32_t *done_cost, uint32_t *done_paths, uint32_t done_cap,
                        uint32_t *n_done, void *hip_stream);
+
+/* A new epoch of sensed loads for the router (host, n_edges entries): its
+ * frozen loads and road costs follow them from the next step on, for the
+ * queries in flight as for those admitted later (a query admitted after the
+ * call is routed as gmacop_route_batch in independent mode on a graph whose
+ * base_load is this array).  The graph's own sensed loads are unchanged.
+ * Call between steps; synchronises hip_stream. */
+int gmacop_server_set_base_load(gmacop_server *s, const uint32_t *base_load, void *hip_stream);
 
 /* Free the router's device memory (not the graph).  NULL-safe. */
 void gmacop_server_release(gmacop_server *s);

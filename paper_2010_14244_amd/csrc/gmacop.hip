@@ -272,7 +272,7 @@ struct DepView {
 // ---------------------------------------------------------------------------
 
 struct EdgeInitArgs {
-    uint32_t m, tau0, t_max;
+    uint32_t m, tau0, t_max, resume;   // resume: keep the current pheromone and load
     const uint32_t *col, *len_dm, *cycle, *base_load;
     const uint16_t *speed, *green;
     uint32_t *t0, *wf, *tau, *load, *cnt;
@@ -282,7 +282,9 @@ struct EdgeInitArgs {
 
 // Per road: free-flow time t0 = floor(len * 360 / speed) in [1, 2^31];
 // fixed-time wait at the head signal wf = min(T_max, floor(red^2 / (2C)))
-// with red = floor(C * (1000 - green) / 1000); fresh pheromone and load.
+// with red = floor(C * (1000 - green) / 1000); fresh pheromone and load, or
+// (resume) the pheromone and load already held, copied to the global
+// walker's records.
 __global__ void k_init_edges(EdgeInitArgs a)
 {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -298,21 +300,25 @@ __global__ void k_init_edges(EdgeInitArgs a)
         if (w > a.t_max) w = a.t_max;
     }
     a.wf[e] = (uint32_t)w;
-    a.tau[e] = a.tau0;
-    if (a.mir) a.mir[(size_t)e * 8 + 5] = a.tau0;
-    a.load[e] = a.base_load[e];
+    const uint32_t tv = a.resume ? a.tau[e] : a.tau0;
+    a.tau[e] = tv;
+    if (a.mir) a.mir[(size_t)e * 8 + 5] = tv;
+    if (!a.resume) a.load[e] = a.base_load[e];
     a.dep[e] = 0;
     a.cnt[e] = 0;
 }
 
-__global__ void k_init_vehicles(uint32_t nq, uint32_t *best_len, uint32_t *best_cost, uint64_t *iter_key,
-                                uint64_t *steps)
+// Empty best routes (or, resume, the best routes held), no iteration key, no selections yet.
+__global__ void k_init_vehicles(uint32_t nq, uint32_t resume, uint32_t *best_len, uint32_t *best_cost,
+                                uint64_t *iter_key, uint64_t *steps)
 {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v == 0) *steps = 0;
     if (v >= nq) return;
-    best_len[v] = 0;
-    best_cost[v] = kNoCost;
+    if (!resume) {
+        best_len[v] = 0;
+        best_cost[v] = kNoCost;
+    }
     iter_key[v] = kNoKey;
 }
 
@@ -1569,7 +1575,7 @@ __global__ __launch_bounds__(1024) void k_glb_list(GlbListArgs a)
 }
 
 struct BestArgs {
-    uint32_t nq, ants, max_steps, load_update;
+    uint32_t nq, ants, max_steps, load_update, m;
     uint32_t *iter_max;
     uint64_t *counters;
     const uint32_t *path, *ant_len;
@@ -1590,12 +1596,12 @@ __global__ __launch_bounds__(kWave) void k_best(BestArgs a)
     const uint32_t bc = a.best_cost[v];
     const bool improve = key != kNoKey && (uint32_t)(key >> 32) < bc;
     const uint32_t ant = improve ? v * a.ants + (uint32_t)(key & 0xFFFFFFFFu) : 0;
-    const uint32_t len = improve ? a.ant_len[ant] : a.best_len[v];
+    const uint32_t len = min(improve ? a.ant_len[ant] : a.best_len[v], a.max_steps);
     uint32_t *bp = a.best_path + (size_t)v * a.max_steps;
     for (uint32_t s = lane; s < len; s += kWave) {
         const uint32_t e = improve ? a.path[(size_t)s * NA + ant] : bp[s];
         if (improve) bp[s] = e;
-        if (a.load_update) atomicAdd(&a.cnt[e], 1u);
+        if (a.load_update && e < a.m) atomicAdd(&a.cnt[e], 1u);   // (a resumed route from a caller is not trusted)
     }
     if (lane == 0) {
         if (improve) {
@@ -2351,7 +2357,7 @@ int validate_params(const gmacop_graph *g, const gmacop_params *p, uint32_t nq)
         return fail(GMACOP_E_INVAL, "need tau_min <= tau0 <= tau_max");
     if (p->mode > GMACOP_MODE_INDEPENDENT) return fail(GMACOP_E_INVAL, "unknown mode %u", p->mode);
     if (p->flags & ~(GMACOP_NO_LOAD_UPDATE | GMACOP_DEVICE_PTRS | GMACOP_TIME_KERNELS | GMACOP_HIP_GRAPH |
-                     GMACOP_GOAL_EXACT))
+                     GMACOP_GOAL_EXACT | GMACOP_RESUME))
         return fail(GMACOP_E_INVAL, "unknown flags");
     const uint32_t lg = g->max_deg <= 1 ? 0 : bit_length(g->max_deg - 1);
     if ((uint64_t)p->alpha * bit_length(p->tau_max_q16) + 16ull * p->beta + lg > 64)
@@ -2850,6 +2856,17 @@ int route_check(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_p
     if (rc) return rc;
     if (p->mode == GMACOP_MODE_INDEPENDENT && p->iterations > kLazyIterMax)
         return fail(GMACOP_E_UNSUPPORTED, "independent mode supports at most %u iterations", kLazyIterMax);
+    if ((p->flags & GMACOP_RESUME) && p->mode != GMACOP_MODE_SHARED)
+        return fail(GMACOP_E_UNSUPPORTED, "GMACOP_RESUME is for shared mode");
+    if ((p->flags & GMACOP_RESUME) && !(p->flags & GMACOP_DEVICE_PTRS)) {
+        for (uint32_t i = 0; i < nq; ++i) {   // the held best routes are read back to the device
+            if (out->path_len[i] > p->max_steps)
+                return fail(GMACOP_E_INVAL, "resume: path_len[%u] exceeds max_steps", i);
+            for (uint32_t s = 0; s < out->path_len[i]; ++s)
+                if (out->path_edges[(size_t)i * p->max_steps + s] >= g->m)
+                    return fail(GMACOP_E_INVAL, "resume: road %u of vehicle %u out of range", s, i);
+        }
+    }
     if (!(p->flags & GMACOP_DEVICE_PTRS)) {
         for (uint32_t i = 0; i < nq; ++i) {
             if (q[i].qid == 0xFFFFFFFFu) return fail(GMACOP_E_INVAL, "query %u uses the reserved qid", i);
@@ -2970,6 +2987,7 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
         g->city_class_dev = plan.city_class;
     }
 
+    const uint32_t resume = (p->flags & GMACOP_RESUME) ? 1u : 0u;
     const gmacop_od *od = q;
     uint32_t *best_path = w.best_path, *best_len = w.best_len, *best_cost = w.best_cost;
     uint64_t *steps = w.steps;
@@ -2980,13 +2998,19 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
         steps = out->steps_total;
     } else if (nq) {
         HIP_TRY(hipMemcpyAsync(w.od, q, sizeof(gmacop_od) * nq, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));   // the caller's queries are read before any later error returns
+        if (resume) {   // the best routes held from the previous call
+            HIP_TRY(hipMemcpyAsync(best_len, out->path_len, sizeof(uint32_t) * nq, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(best_cost, out->cost_ms, sizeof(uint32_t) * nq, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(best_path, out->path_edges, sizeof(uint32_t) * (size_t)nq * S,
+                                   hipMemcpyHostToDevice, st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));   // the caller's buffers are read before any later error returns
         od = w.od;
     }
 
     const bool load_update = !(p->flags & GMACOP_NO_LOAD_UPDATE);
     uint32_t *mir = (!plan.legacy && plan.glb) ? (uint32_t *)g->rec32 : nullptr;   // the global walker's records
-    EdgeInitArgs ia{g->m, p->tau0_q16, p->t_max_ms, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
+    EdgeInitArgs ia{g->m, p->tau0_q16, p->t_max_ms, resume, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
                     g->t0, g->wf, g->tau, g->load, g->cnt, g->dep, mir};
     CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost, mir};
     PherView pv{};
@@ -3016,7 +3040,7 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
     la.steps = steps; la.counters = g->counters; la.iter_max = g->iter_max;
     la.goal = gp.on ? w.goal : nullptr; la.goal_stride = gp.stride;
     const bool update_loads = load_update && !indep;
-    BestArgs ba{nq, p->ants, S, update_loads ? 1u : 0u, g->iter_max, g->counters, w.path, w.ant_len, w.iter_key,
+    BestArgs ba{nq, p->ants, S, update_loads ? 1u : 0u, g->m, g->iter_max, g->counters, w.path, w.ant_len, w.iter_key,
                 best_path, best_len, best_cost, g->cnt};
     EdgeArgs ea{g->m, p->rho_q16, p->tau_min_q16, p->tau_max_q16, p->theta, update_loads ? 1u : 0u,
                 g->tau, g->load, g->cnt, g->base_load, g->dep, mir};
@@ -3059,7 +3083,7 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
             if ((erc = kt.stop(&tq))) return erc;
         }
         if (indep && nq) hipLaunchKernelGGL(k_next_generation, dim3(1), dim3(64), 0, st, w.dev_gen);
-        hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq,
+        hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq, resume,
                            best_len, best_cost, w.iter_key, steps);
         hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
         if (nq && !plan.legacy) {
@@ -3139,7 +3163,8 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
             (uint64_t)(uintptr_t)w.ant_len, (uint64_t)(uintptr_t)w.ant_cost, (uint64_t)(uintptr_t)w.gbits,
             (uint64_t)(uintptr_t)w.iter_key, nq, p->ants, p->iterations, p->alpha, p->beta, p->max_steps,
             p->rho_q16, p->tau0_q16, p->tau_min_q16, p->tau_max_q16, p->q_deposit, p->theta, p->th_max,
-            p->t_max_ms, p->vmax_kmh, p->mode, p->flags & GMACOP_NO_LOAD_UPDATE, p->seed, p->iter_offset,
+            p->t_max_ms, p->vmax_kmh, p->mode, p->flags & (GMACOP_NO_LOAD_UPDATE | GMACOP_RESUME), p->seed,
+            p->iter_offset,
             plan.legacy, plan.lds_lanes, plan.lds_apb, plan.lds_bpv, plan.maxd, plan.road_maxd,
             (uint64_t)plan.lds_bytes[1], (uint64_t)plan.lds_bytes[2], (uint64_t)plan.lds_bytes[3],
             (uint64_t)plan.lds_bytes[4], (uint64_t)plan.lds_bytes[5], (uint64_t)plan.lds_bytes[6], plan.glb,
@@ -3415,6 +3440,27 @@ extern "C" int gmacop_vehicle_tau_get(gmacop_graph *g, uint32_t vehicle, uint32_
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(tmp);
     if (e != hipSuccess) return fail(GMACOP_E_DEVICE, "vehicle_tau_get: %s", hipGetErrorString(e));
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_state_set(gmacop_graph *g, const uint32_t *tau_q16, const uint32_t *load, void *hip_stream)
+{
+    if (!g) return fail(GMACOP_E_INVAL, "graph is NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (tau_q16) HIP_TRY(hipMemcpyAsync(g->tau, tau_q16, sizeof(uint32_t) * g->m, hipMemcpyHostToDevice, st));
+    if (load) HIP_TRY(hipMemcpyAsync(g->load, load, sizeof(uint32_t) * g->m, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_set_base_load(gmacop_graph *g, const uint32_t *base_load, void *hip_stream)
+{
+    if (!g || !base_load) return fail(GMACOP_E_INVAL, "graph or loads are NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipMemcpyAsync(g->base_load, base_load, sizeof(uint32_t) * g->m, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return GMACOP_OK;
 }
 
@@ -3769,7 +3815,7 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
         }
         HIP_TRY(hipMemcpy(s->rec32, g->rec32, 2 * (size_t)m * sizeof(uint4), hipMemcpyDeviceToDevice));
     }
-    EdgeInitArgs ia{m, pp.tau0_q16, pp.t_max_ms, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
+    EdgeInitArgs ia{m, pp.tau0_q16, pp.t_max_ms, 0u, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
                     s->t0, s->wf, s->tau, s->load, s->cnt, s->dep_shared, (uint32_t *)s->rec32};
     hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(m, 256)), dim3(256), 0, 0, ia);
     CostArgs ca{g->n, pp.theta, pp.th_max, g->rev_ptr, g->rev_edge, g->cycle, s->load, s->t0, s->wf, s->cost,
@@ -3936,7 +3982,7 @@ int server_step_impl(gmacop_server *s, const gmacop_od *admit, uint32_t take, ui
         }
     }
     if ((rc = kt.stop(&tm)) || (rc = kt.start(1, &tm))) return rc;
-    BestArgs ba{NS, A, S, 0u, g->iter_max, g->counters, s->path, s->ant_len, s->iter_key, s->best_path, s->best_len,
+    BestArgs ba{NS, A, S, 0u, g->m, g->iter_max, g->counters, s->path, s->ant_len, s->iter_key, s->best_path, s->best_len,
                 s->best_cost, s->cnt};
     hipLaunchKernelGGL(k_best, dim3(NS), dim3(kWave), 0, st, ba);
     if ((rc = kt.stop(&tm)) || (rc = kt.start(2, &tm))) return rc;
@@ -4026,6 +4072,22 @@ extern "C" int gmacop_server_step(gmacop_server *s, const gmacop_od *admit, uint
         return rc;
     }
     *n_admit = take;
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_server_set_base_load(gmacop_server *s, const uint32_t *base_load, void *hip_stream)
+{
+    if (!s || !base_load) return fail(GMACOP_E_INVAL, "server or loads are NULL");
+    gmacop_graph *g = s->g;
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    // the router's loads become the new sensed loads, and its cost table follows them
+    HIP_TRY(hipMemcpyAsync(s->load, base_load, sizeof(uint32_t) * g->m, hipMemcpyHostToDevice, st));
+    CostArgs ca{g->n, s->p.theta, s->p.th_max, g->rev_ptr, g->rev_edge, g->cycle, s->load, s->t0, s->wf, s->cost,
+                (uint32_t *)s->rec32};
+    hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
     return GMACOP_OK;
 }
 

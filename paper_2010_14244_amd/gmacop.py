@@ -31,8 +31,10 @@ DEVICE_PTRS = 2
 TIME_KERNELS = 4
 HIP_GRAPH = 8
 GOAL_EXACT = 16
+RESUME = 32
 
-EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_route_batch_noalloc", "gmacop_state_get", "gmacop_vehicle_tau_get",
+EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_route_batch_noalloc", "gmacop_state_get", "gmacop_state_set",
+            "gmacop_set_base_load", "gmacop_server_set_base_load", "gmacop_vehicle_tau_get",
             "gmacop_goal_rows", "gmacop_shortest_routes", "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
             "gmacop_server_release", "gmacop_release", "gmacop_last_error")
 KERNELS = ("walk", "best", "edge", "cost", "walk_lds", "walk_glb", "goal")
@@ -101,6 +103,12 @@ def lib():
         L.gmacop_route_batch_noalloc.restype = C.c_int
         L.gmacop_state_get.argtypes = [vp, vp, vp, vp]
         L.gmacop_state_get.restype = C.c_int
+        L.gmacop_state_set.argtypes = [vp, vp, vp, vp]
+        L.gmacop_state_set.restype = C.c_int
+        L.gmacop_set_base_load.argtypes = [vp, vp, vp]
+        L.gmacop_set_base_load.restype = C.c_int
+        L.gmacop_server_set_base_load.argtypes = [vp, vp, vp]
+        L.gmacop_server_set_base_load.restype = C.c_int
         L.gmacop_vehicle_tau_get.argtypes = [vp, C.c_uint32, vp, vp]
         L.gmacop_vehicle_tau_get.restype = C.c_int
         L.gmacop_goal_rows.argtypes = [vp, vp, C.c_uint32, vp, vp]
@@ -178,10 +186,11 @@ def _od_array(veh) -> np.ndarray:
     return od
 
 
-def gmacop_route_batch(g: Graph, veh, p: dict, stream: Optional[int] = None) -> dict:
+def gmacop_route_batch(g: Graph, veh, p: dict, stream: Optional[int] = None, held: Optional[dict] = None) -> dict:
     """Route the vehicles with host buffers (synchronous).  Returns dict with
-    path_edges [V, max_steps], path_len [V], cost_ms [V], steps_total."""
-    return _route_host(lib().gmacop_route_batch, g, veh, p, stream)
+    path_edges [V, max_steps], path_len [V], cost_ms [V], steps_total.  With
+    the RESUME flag, `held` is the previous call's result dict."""
+    return _route_host(lib().gmacop_route_batch, g, veh, p, stream, held)
 
 
 def gmacop_route_batch_noalloc(g: Graph, veh, p: dict, stream: Optional[int] = None) -> dict:
@@ -190,12 +199,16 @@ def gmacop_route_batch_noalloc(g: Graph, veh, p: dict, stream: Optional[int] = N
     return _route_host(lib().gmacop_route_batch_noalloc, g, veh, p, stream)
 
 
-def _route_host(fn, g: Graph, veh, p: dict, stream: Optional[int]) -> dict:
+def _route_host(fn, g: Graph, veh, p: dict, stream: Optional[int], held: Optional[dict] = None) -> dict:
     od = _od_array(veh)
     V, S = od.shape[0], int(p["max_steps"])
     path = np.zeros((V, max(S, 1)), np.uint32)
     plen = np.zeros(V, np.uint32)
     cost = np.zeros(V, np.uint32)
+    if held is not None:   # GMACOP_RESUME: the previous call's results are read back as the best routes held
+        path[:] = held["path_edges"][:, :max(S, 1)]
+        plen[:] = held["path_len"]
+        cost[:] = held["cost_ms"]
     steps = np.zeros(1, np.uint64)
     res = _Result(path.ctypes.data, plen.ctypes.data, cost.ctypes.data, steps.ctypes.data)
     pp = _params(dict(p, flags=int(p.get("flags", 0)) & ~DEVICE_PTRS))
@@ -243,6 +256,25 @@ def gmacop_state_get(g: Graph, stream: Optional[int] = None):
     load = np.zeros(g.m, np.uint32)
     _check(lib().gmacop_state_get(g.handle, tau.ctypes.data, load.ctypes.data, stream))
     return tau, load
+
+
+def gmacop_state_set(g: Graph, tau=None, load=None, stream: Optional[int] = None) -> None:
+    """Replace the shared-mode pheromone and/or current loads the graph holds."""
+    t = None if tau is None else np.ascontiguousarray(tau, np.uint32)
+    l = None if load is None else np.ascontiguousarray(load, np.uint32)
+    for a in (t, l):
+        if a is not None and a.shape != (g.m,):
+            raise ValueError("state arrays need one entry per road")
+    _check(lib().gmacop_state_set(g.handle, None if t is None else t.ctypes.data,
+                                  None if l is None else l.ctypes.data, stream))
+
+
+def gmacop_set_base_load(g: Graph, base_load, stream: Optional[int] = None) -> None:
+    """A new epoch of sensed loads for later calls on the graph."""
+    b = np.ascontiguousarray(base_load, np.uint32)
+    if b.shape != (g.m,):
+        raise ValueError("base_load needs one entry per road")
+    _check(lib().gmacop_set_base_load(g.handle, b.ctypes.data, stream))
 
 
 def gmacop_vehicle_tau_get(g: Graph, vehicle: int, stream: Optional[int] = None) -> np.ndarray:
@@ -331,6 +363,13 @@ class Server:
         done = [(int(self._qid[i]), self._paths[i, :int(self._len[i])].copy(), int(self._cost[i]))
                 for i in range(nd.value)]
         return int(na.value), done
+
+    def set_base_load(self, base_load, stream: Optional[int] = None) -> None:
+        """A new epoch of sensed loads for this router, from its next step on."""
+        b = np.ascontiguousarray(base_load, np.uint32)
+        if b.shape != (self.graph.m,):
+            raise ValueError("base_load needs one entry per road")
+        _check(lib().gmacop_server_set_base_load(self.handle, b.ctypes.data, stream))
 
     def release(self):
         if self.handle:
