@@ -80,6 +80,8 @@ def lib():
         L.orc_goal.argtypes = [vp, vp, u32, u32]
         L.orc_goal.restype = u64
         L.orc_goal_exact.argtypes = [vp, vp, u32, vp]
+        L.orc_greedy.argtypes = [vp, vp, vp, u32, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_greedy.restype = C.c_int
         L.orc_shortest_route.argtypes = [vp, vp, u32, u32, u32, vp]
         L.orc_shortest_route.restype = u32
         L.orc_eta.argtypes = [C.c_int64]
@@ -250,3 +252,27 @@ def route_rc(g, veh, p: dict) -> int:
         return 0
     except ValueError as e:
         return e.args[1]
+
+
+def greedy(g, veh, p: dict) -> dict:
+    """Literal MACO-P vehicle loop (Fig. 3) in synchronous ticks: path_edges
+    [V, max_steps], path_len, cost_ms, steps_total and the final markers."""
+    gr, pp = _GraphRef(g), _params(p)
+    src = np.ascontiguousarray(veh.src, np.uint32)
+    dst = np.ascontiguousarray(veh.dst, np.uint32)
+    V, S = src.shape[0], int(p["max_steps"])
+    off = getattr(g, "inst_node_off", None)
+    city = None
+    if off is not None:
+        city = np.repeat(np.arange(len(off) - 1, dtype=np.uint32), np.diff(np.asarray(off, np.int64))).astype(np.uint32)
+    path = np.zeros((V, max(S, 1)), np.uint32)
+    plen = np.zeros(V, np.uint32)
+    cost = np.zeros(V, np.uint32)
+    mark = np.zeros(gr.m, np.uint32)
+    steps = C.c_uint64(0)
+    rc = lib().orc_greedy(C.byref(gr.s), _ptr(src), _ptr(dst), V, C.byref(pp), _ptr(city), _ptr(path), _ptr(plen),
+                          _ptr(cost), C.byref(steps), _ptr(mark))
+    if rc != 0:
+        raise ValueError("oracle rejected input", rc)
+    return dict(path_edges=path, path_len=plen, cost_ms=cost, steps_total=int(steps.value), marker=mark)
+

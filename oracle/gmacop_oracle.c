@@ -560,3 +560,121 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
 #undef HROW
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Literal MACO-P vehicle loop (Section 4.1, Fig. 3), read for synchronous  */
+/* ticks: at every tick each vehicle still travelling in a city moves one   */
+/* road, all of them on the pheromone markers of the tick's start.          */
+/*  - Candidates (Fig. 3: the adjacent nodes; the prose: among the paths     */
+/*    leading to the destination): the out-roads whose head has a smaller   */
+/*    exact goal term (orc_goal_exact) than the current node.  The term     */
+/*    drops at every move, so a vehicle never revisits a node and reaches   */
+/*    its destination unless the destination is out of reach.              */
+/*  - Choice: the candidate with the least marker, ties to the lowest road  */
+/*    id; when N_t, the vehicles of the city still travelling at the tick's */
+/*    start, exceeds the threshold (theta here), the second least instead   */
+/*    (when there are two candidates or more).                              */
+/*  - Markers start at the sensed loads.  Every move adds one to the chosen */
+/*    road and takes one from every other road of the city (Fig. 3,         */
+/*    Ph_road++ and Ph_[N-road]--); with c_e moves along road e among M     */
+/*    moves of the tick: marker <- max(0, marker + c_e - (M - c_e)).        */
+/*  - A vehicle with no candidate (destination out of reach) stops without  */
+/*    a route; after max_steps ticks the vehicles still travelling stop     */
+/*    without a route.  Route cost = sum of the cost table at the sensed    */
+/*    loads (orc_cost_table), as found.                                     */
+/* city_of_node: [n] city of each node, or NULL for one city.  Outputs as   */
+/* orc_route; marker_out [m] (may be NULL): markers after the last tick.    */
+/* Returns 0, or -1 on invalid input.                                       */
+/* ------------------------------------------------------------------------ */
+int orc_greedy(const orc_graph *g, const uint32_t *src, const uint32_t *dst, uint32_t nv, const orc_params *p,
+               const uint32_t *city_of_node, uint32_t *path_edges, uint32_t *path_len, uint32_t *cost_ms,
+               uint64_t *steps_total, uint32_t *marker_out)
+{
+    const uint32_t n = g->n, m = g->m, S = p->max_steps;
+    if (S == 0 || p->theta == 0) return -1;
+    for (uint32_t v = 0; v < nv; ++v)
+        if (src[v] >= n || dst[v] >= n || src[v] == dst[v]) return -1;
+    uint32_t ncity = 1;
+    if (city_of_node)
+        for (uint32_t x = 0; x < n; ++x)
+            if (city_of_node[x] + 1 > ncity) ncity = city_of_node[x] + 1;
+    uint32_t *t0 = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *wf = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *cost = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    int64_t *mark = (int64_t *)malloc(sizeof(int64_t) * (m + 1));
+    uint32_t *moves = (uint32_t *)calloc(m + 1, sizeof(uint32_t));   /* c_e of the tick */
+    uint32_t *h = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)nv * n + 1));
+    uint32_t *node = (uint32_t *)malloc(sizeof(uint32_t) * (nv + 1));
+    uint32_t *choice = (uint32_t *)malloc(sizeof(uint32_t) * (nv + 1));
+    uint8_t *travelling = (uint8_t *)malloc(nv + 1);
+    uint64_t *csum = (uint64_t *)calloc(nv + 1, sizeof(uint64_t));
+    uint32_t *n_t = (uint32_t *)malloc(sizeof(uint32_t) * ncity);
+    uint32_t *m_t = (uint32_t *)malloc(sizeof(uint32_t) * ncity);
+    orc_edge_static(g, p, t0, wf);
+    orc_cost_table(g, p, g->base_load, t0, wf, cost, NULL);
+    for (uint32_t e = 0; e < m; ++e) mark[e] = g->base_load[e];
+    for (uint32_t v = 0; v < nv; ++v) {
+        orc_goal_exact(g, p, dst[v], h + (size_t)v * n);
+        node[v] = src[v];
+        travelling[v] = 1;
+        path_len[v] = 0;
+        cost_ms[v] = U32_MAX;
+    }
+    uint64_t steps = 0;
+    for (uint32_t t = 0; t < S; ++t) {
+        /* N_t per city: the vehicles still travelling at the tick's start */
+        for (uint32_t c = 0; c < ncity; ++c) n_t[c] = m_t[c] = 0;
+        uint32_t any = 0;
+        for (uint32_t v = 0; v < nv; ++v)
+            if (travelling[v]) { n_t[city_of_node ? city_of_node[src[v]] : 0]++; any = 1; }
+        if (!any) break;
+        /* every travelling vehicle chooses on the markers of the tick's start */
+        for (uint32_t v = 0; v < nv; ++v) {
+            choice[v] = U32_MAX;
+            if (!travelling[v]) continue;
+            const uint32_t *hv = h + (size_t)v * n;
+            const uint32_t u = node[v], c = city_of_node ? city_of_node[u] : 0;
+            uint32_t best = U32_MAX, second = U32_MAX;       /* road ids, ordered by (marker, road id) */
+            for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e) {
+                if (!(hv[g->col[e]] < hv[u])) continue;      /* not leading toward the destination */
+                if (best == U32_MAX || mark[e] < mark[best]) { second = best; best = e; }
+                else if (second == U32_MAX || mark[e] < mark[second]) second = e;
+            }
+            if (best == U32_MAX) { travelling[v] = 0; continue; }      /* destination out of reach */
+            choice[v] = (n_t[c] > p->theta && second != U32_MAX) ? second : best;
+        }
+        /* move, count, and update the markers of each city */
+        for (uint32_t v = 0; v < nv; ++v) {
+            const uint32_t e = choice[v];
+            if (e == U32_MAX) continue;
+            path_edges[(size_t)v * S + path_len[v]++] = e;
+            csum[v] += cost[e];
+            moves[e]++;
+            m_t[city_of_node ? city_of_node[node[v]] : 0]++;
+            steps++;
+            node[v] = g->col[e];
+            if (node[v] == dst[v]) {
+                travelling[v] = 0;
+                cost_ms[v] = csum[v] > PATH_COST_CAP ? PATH_COST_CAP : (uint32_t)csum[v];
+            }
+        }
+        for (uint32_t u = 0; u < n; ++u) {
+            const uint32_t c = city_of_node ? city_of_node[u] : 0;
+            for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e) {
+                const int64_t x = mark[e] + (int64_t)moves[e] - (int64_t)(m_t[c] - moves[e]);
+                mark[e] = x < 0 ? 0 : x;
+                moves[e] = 0;
+            }
+        }
+    }
+    for (uint32_t v = 0; v < nv; ++v)
+        if (travelling[v]) path_len[v] = 0;                  /* still travelling after max_steps ticks */
+        else if (cost_ms[v] == U32_MAX) path_len[v] = 0;     /* stopped without a route */
+    *steps_total = steps;
+    if (marker_out)
+        for (uint32_t e = 0; e < m; ++e) marker_out[e] = mark[e] > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)mark[e];
+    free(t0); free(wf); free(cost); free(mark); free(moves); free(h); free(node); free(choice); free(travelling);
+    free(csum); free(n_t); free(m_t);
+    return 0;
+}
+

@@ -100,6 +100,14 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
               uint32_t *path_edges, uint32_t *path_len, uint32_t *cost_ms, uint64_t *steps_total,
               uint32_t *tau_out, uint32_t *load_out, uint32_t *best_hist);
 
+/* Literal MACO-P vehicle loop of Fig. 3 in synchronous ticks (least-marker
+ * road toward the destination, second least when N_t > theta; markers +1 on
+ * the chosen road, -1 on every other road of the city per move).
+ * city_of_node: [n] or NULL.  Returns 0, or -1 on invalid input. */
+int orc_greedy(const orc_graph *g, const uint32_t *src, const uint32_t *dst, uint32_t nv, const orc_params *p,
+               const uint32_t *city_of_node, uint32_t *path_edges, uint32_t *path_len, uint32_t *cost_ms,
+               uint64_t *steps_total, uint32_t *marker_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,14 @@ MUTANTS = {
     for (uint32_t e = 0; e < m; ++e) { ru[e] = g->col[e]; rw[e] = t0[e]; }"""),
     "shortest_route_last_tight": ("if ((uint64_t)t0[e] + h[g->col[e]] == h[u]) { next = e; break; }",
                                   "if ((uint64_t)t0[e] + h[g->col[e]] == h[u]) { next = e; }"),
+    "greedy_argmax": ("if (best == U32_MAX || mark[e] < mark[best]) { second = best; best = e; }",
+                      "if (best == U32_MAX || mark[e] > mark[best]) { second = best; best = e; }"),
+    "greedy_threshold_inclusive": ("choice[v] = (n_t[c] > p->theta && second != U32_MAX)",
+                                   "choice[v] = (n_t[c] >= p->theta && second != U32_MAX)"),
+    "greedy_no_decrement": ("mark[e] + (int64_t)moves[e] - (int64_t)(m_t[c] - moves[e]);",
+                            "mark[e] + (int64_t)moves[e];"),
+    "greedy_tie_last": ("else if (second == U32_MAX || mark[e] < mark[second]) second = e;",
+                        "else if (second == U32_MAX || mark[e] <= mark[second]) second = e;"),
     "apply_after_load_update": (
         """            for (uint32_t e = 0; e < m; ++e) tau[e] = orc_apply_tau(p, tau[e], dep[e], load[e]);
             if (!(p->flags & ORC_FLAG_NO_LOAD_UPDATE)) {

@@ -881,3 +881,72 @@ def test_shortest_route_ties_and_limits(orc):
     assert orc.shortest_route(g, p, 0, 4, 8).tolist() == []
     assert orc.shortest_route(g, p, 0, 3, 1).tolist() == []
     assert orc.shortest_route(g, p, 0, 1, 1).tolist() == [0]
+
+
+# ---------------------------------------------------------------------------
+# literal MACO-P vehicle loop (Fig. 3) in synchronous ticks
+# ---------------------------------------------------------------------------
+
+def greedy_diamond(base):
+    """0 -> 1 -> 3 -> 4 and 0 -> 2 -> 3 -> 4, equal roads (exact terms 3T, 2T, 2T, T, 0);
+    roads in id order: (0,1), (0,2), (1,3), (2,3), (3,4); `base` = initial markers."""
+    return from_edges(5, [0, 0, 1, 2, 3], [1, 2, 3, 3, 4], len_dm=1000, speed_kmh=50, base_load=base)
+
+
+def test_greedy_hand_derived_ticks(orc):
+    """Vehicles A, B at 0 and C at 1, all to 4; markers (2, 1, 0, 0, 0); theta 2.
+    Tick 0: N = 3 > 2, so A and B take the second least of (e1: 1, e0: 2), e0; C takes e2.
+      M = 3: e0 -> 2 + 2 - 1 = 3, e1 -> max(0, 1 - 3) = 0, e2 -> max(0, 1 - 2) = 0, e3, e4 -> 0.
+    Tick 1: N = 3: A, B take e2 (the only candidate), C takes e4 and arrives.
+      M = 3: e0 -> 0, e2 -> 0 + 2 - 1 = 1, e4 -> max(0, 1 - 2) = 0.
+    Tick 2: N = 2, not above 2: A and B take e4 and arrive.  M = 2: e4 -> 2, e2 -> 0.
+    Routes A, B = (e0, e2, e4), C = (e2, e4); 8 moves; final markers (0, 0, 0, 0, 2)."""
+    g = greedy_diamond([2, 1, 0, 0, 0])
+    p = default_params(theta=2, max_steps=8)
+    r = orc.greedy(g, veh([0, 0, 1], [4, 4, 4]), p)
+    assert r["path_len"].tolist() == [3, 3, 2]
+    assert r["path_edges"][0, :3].tolist() == [0, 2, 4] and r["path_edges"][1, :3].tolist() == [0, 2, 4]
+    assert r["path_edges"][2, :2].tolist() == [2, 4]
+    assert r["steps_total"] == 8
+    assert r["marker"].tolist() == [0, 0, 0, 0, 2]
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    assert r["cost_ms"].tolist() == [int(cost[[0, 2, 4]].sum())] * 2 + [int(cost[[2, 4]].sum())]
+    # N = 3 is not above theta 3: the least marker, e1, for A and B
+    r3 = orc.greedy(g, veh([0, 0, 1], [4, 4, 4]), dict(p, theta=3))
+    assert r3["path_edges"][0, :3].tolist() == [1, 3, 4] and r3["path_edges"][1, :3].tolist() == [1, 3, 4]
+    # equal markers: the lower road id
+    re = orc.greedy(greedy_diamond([1, 1, 0, 0, 0]), veh([0], [4]), dict(p, theta=5))
+    assert re["path_edges"][0, :3].tolist() == [0, 2, 4]
+    # a tie for second place: 0 -> {1, 2, 3} -> 4 with markers (0, 1, 1): least e0, then e1 and e2 tied at 1;
+    # two vehicles (N = 2 above theta 1) take the second least, the lower id e1, then e4
+    fan = from_edges(5, [0, 0, 0, 1, 2, 3], [1, 2, 3, 4, 4, 4], len_dm=1000, speed_kmh=50,
+                     base_load=[0, 1, 1, 0, 0, 0])
+    rt = orc.greedy(fan, veh([0, 0], [4, 4]), dict(p, theta=1))
+    assert rt["path_edges"][0, :2].tolist() == [1, 4] and rt["path_edges"][1, :2].tolist() == [1, 4]
+    # one vehicle, one tick: the chosen road gains one, the others lose one (floored at zero)
+    r1 = orc.greedy(greedy_diamond([4, 4, 4, 4, 4]), veh([0], [1]), dict(p, theta=5))
+    assert r1["path_edges"][0, :1].tolist() == [0] and r1["marker"].tolist() == [5, 3, 3, 3, 3]
+
+
+def test_greedy_routes_descend_to_the_destination(orc):
+    """Every route: simple, connected, the exact term strictly decreasing
+    along it, ending at the destination; cost = cost-table sum; moves =
+    total length; vehicles whose destination is out of reach get none."""
+    rng = np.random.default_rng(24)
+    g = planar_graph(1500, rng)
+    V = random_od(g.n, 40, rng)
+    p = default_params(theta=20, max_steps=4096)
+    r = orc.greedy(g, V, p)
+    cost, _ = orc.cost_table(g, p, g.base_load)
+    _check_paths(g, V, r, p["max_steps"])
+    for v in range(len(V)):
+        L = int(r["path_len"][v])
+        assert L > 0
+        h = orc.goal_exact(g, p, int(V.dst[v])).astype(np.int64)
+        nodes = np.concatenate([[V.src[v]], g.col[r["path_edges"][v, :L]]]).astype(np.int64)
+        assert np.all(np.diff(h[nodes]) < 0)
+        assert r["cost_ms"][v] == int(cost[r["path_edges"][v, :L].astype(np.int64)].astype(np.int64).sum())
+    assert r["steps_total"] == int(r["path_len"].sum())
+    one_way = from_edges(4, [0, 1, 2], [1, 2, 1])            # 3 cannot be reached from 0
+    ru = orc.greedy(one_way, veh([0], [3]), p)
+    assert ru["path_len"].tolist() == [0] and ru["cost_ms"].tolist() == [0xFFFFFFFF]
