@@ -40,6 +40,20 @@ extern "C" {
 /* gmacop_params.mode */
 #define GMACOP_MODE_SHARED      0u  /* all vehicles share pheromone and road loads      */
 #define GMACOP_MODE_INDEPENDENT 1u  /* private pheromone per vehicle, loads frozen      */
+#define GMACOP_MODE_GREEDY      2u  /* the literal MACO-P vehicle loop of Fig. 3: no ants;
+                                       in synchronous ticks every vehicle still travelling
+                                       takes, among the out-roads whose head has a smaller
+                                       exact goal term (GMACOP_GOAL_EXACT), the one with
+                                       the least marker (ties: lowest road id), or the
+                                       second least when more than theta vehicles of its
+                                       city are travelling; each move adds 1 to the chosen
+                                       road's marker and takes 1 from every other road of
+                                       the city (floored at 0); markers start at the
+                                       sensed loads.  At most max_steps ticks; ants,
+                                       iterations, alpha, beta, rho, tau and q_deposit are
+                                       not used.  Route cost = the cost table at the
+                                       sensed loads; gmacop_state_get's tau = the final
+                                       markers                                          */
 
 /* gmacop_params.flags */
 #define GMACOP_NO_LOAD_UPDATE  1u   /* shared mode: keep loads at base_load             */

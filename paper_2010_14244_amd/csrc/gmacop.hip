@@ -2000,6 +2000,149 @@ __global__ void k_shortest_route(const gmacop_od *od, uint32_t nq, uint32_t n, u
     if (L) atomicAdd((unsigned long long *)steps, (unsigned long long)L);
 }
 
+// ---- the literal MACO-P vehicle loop (Fig. 3), synchronous ticks ----
+
+struct GreedyArgs {
+    const gmacop_od *od;
+    uint32_t nq, n, max_steps, theta, stride;
+    const uint32_t *row_ptr, *col, *cost, *node_inst, *inst_off, *inst_eoff, *base_load;
+    const uint32_t *goal;      // [nq][stride] exact goal rows (city-local node ids)
+    uint32_t *node;            // [nq] current node, kGone once stopped
+    uint32_t *choice;          // [nq] road taken in this tick, kGone if none
+    const uint32_t *vcity;     // [nq] city of the vehicle, kGone for an invalid query (k_greedy_prep)
+    uint64_t *csum;            // [nq] cost so far
+    uint64_t *mark, *msum;     // [m] marker, and the city's moves so far when it was set
+    uint32_t *cnt;             // [m] moves along the road in this tick (zero between ticks)
+    uint32_t *mark_out;        // [m] markers after the last tick (saturated to 32 bits)
+    uint32_t *path, *len, *cost_out;   // [nq][max_steps], [nq], [nq] (len 0 / cost kNoCost set beforehand)
+    uint64_t *steps;
+};
+
+constexpr uint32_t kGone = 0xFFFFFFFFu;
+
+// A marker at the city's move count sm: every move since it was set took one from it, floored at zero.
+__device__ __forceinline__ uint64_t marker_at(const GreedyArgs &a, uint32_t e, uint64_t sm)
+{
+    const uint64_t x = __hip_atomic_load(&a.mark[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t d = sm - __hip_atomic_load(&a.msum[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return x > d ? x - d : 0;
+}
+
+// Per vehicle, before k_greedy: its city (kGone for an invalid query), start node, cost so far, no choice.
+__global__ void k_greedy_prep(const gmacop_od *od, uint32_t nq, uint32_t n, const uint32_t *node_inst,
+                              uint32_t *vcity, uint32_t *node, uint32_t *choice, uint64_t *csum)
+{
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nq) return;
+    const gmacop_od q = od[v];
+    const bool valid = q.src < n && q.dst < n && q.src != q.dst;
+    vcity[v] = valid ? node_inst[q.src] : kGone;
+    node[v] = valid ? q.src : kGone;
+    choice[v] = kGone;
+    csum[v] = 0;
+}
+
+// One block per city (Fig. 3, one tick at a time): every vehicle still
+// travelling takes, among the roads whose head has a smaller exact goal
+// term, the one with the least marker (ties: lowest road id), or the second
+// least when the city's travelling vehicles exceed theta; then every road
+// chosen by c of the tick's M moves becomes max(0, marker + c - (M - c)),
+// and every other road loses M (kept lazily: a marker stores the city's move
+// count when it was set).  A vehicle without a candidate, or still travelling
+// after max_steps ticks, has no route.
+__global__ __launch_bounds__(1024) void k_greedy(GreedyArgs a)
+{
+    __shared__ uint32_t s_travel, s_moves;
+    const uint32_t city = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+    const uint32_t n_lo = a.inst_off[city];
+    const uint32_t e_lo = a.inst_eoff[city], e_hi = a.inst_eoff[city + 1];
+    for (uint32_t e = e_lo + tid; e < e_hi; e += nthr) {   // markers start at the sensed loads
+        __hip_atomic_store(&a.mark[e], (uint64_t)a.base_load[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.msum[e], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.cnt[e] = 0;
+    }
+    if (tid == 0) s_travel = 0;
+    __syncthreads();
+    for (uint32_t v = tid; v < a.nq; v += nthr)   // a vehicle is always handled by the same thread
+        if (a.vcity[v] == city) atomicAdd(&s_travel, 1u);
+    __syncthreads();
+    uint64_t sm = 0;
+    for (uint32_t t = 0; t < a.max_steps; ++t) {
+        const uint32_t N = s_travel;   // travelling at the tick's start
+        __syncthreads();
+        if (N == 0) break;
+        if (tid == 0) {
+            s_moves = 0;
+            s_travel = 0;
+        }
+        __syncthreads();
+        for (uint32_t v = tid; v < a.nq; v += nthr) {   // choose and move, on the markers of the tick's start
+            if (a.vcity[v] != city) continue;
+            const uint32_t u = a.node[v];
+            if (u == kGone) continue;
+            const uint32_t *hv = a.goal + (size_t)v * a.stride;
+            const uint32_t hu = hv[u - n_lo];
+            uint32_t best = kGone, second = kGone;
+            uint64_t pb = 0, ps = 0;
+            for (uint32_t e = a.row_ptr[u]; e < a.row_ptr[u + 1]; ++e) {
+                if (!(hv[a.col[e] - n_lo] < hu)) continue;   // not leading toward the destination
+                const uint64_t pe = marker_at(a, e, sm);
+                if (best == kGone || pe < pb) {
+                    second = best;
+                    ps = pb;
+                    best = e;
+                    pb = pe;
+                } else if (second == kGone || pe < ps) {
+                    second = e;
+                    ps = pe;
+                }
+            }
+            if (best == kGone) {   // destination out of reach: stops without a route
+                a.node[v] = kGone;
+                continue;
+            }
+            const uint32_t e = (N > a.theta && second != kGone) ? second : best;
+            const gmacop_od q = a.od[v];
+            a.path[(size_t)v * a.max_steps + a.len[v]] = e;
+            a.len[v] += 1;
+            const uint64_t cs = a.csum[v] + a.cost[e];
+            a.csum[v] = cs;
+            a.choice[v] = e;
+            atomicAdd(&a.cnt[e], 1u);
+            atomicAdd(&s_moves, 1u);
+            const uint32_t x = a.col[e];
+            if (x == q.dst) {
+                a.node[v] = kGone;
+                a.cost_out[v] = cs > kPathCostCap ? kPathCostCap : (uint32_t)cs;
+            } else {
+                a.node[v] = x;
+                atomicAdd(&s_travel, 1u);
+            }
+        }
+        __syncthreads();
+        const uint32_t M = s_moves;
+        for (uint32_t v = tid; v < a.nq; v += nthr) {   // the markers of the roads chosen in this tick
+            const uint32_t e = a.vcity[v] == city ? a.choice[v] : kGone;
+            if (e == kGone) continue;
+            a.choice[v] = kGone;
+            const uint32_t c = atomicExch(&a.cnt[e], 0u);   // the first of its vehicles applies the road's update
+            if (!c) continue;
+            const int64_t x = (int64_t)marker_at(a, e, sm) + (int64_t)c - (int64_t)(M - c);
+            __hip_atomic_store(&a.mark[e], (uint64_t)(x < 0 ? 0 : x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.msum[e], sm + M, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        sm += M;
+        __syncthreads();
+    }
+    for (uint32_t v = tid; v < a.nq; v += nthr)   // still travelling, or stopped without a route: none
+        if (a.vcity[v] == city && a.cost_out[v] == kNoCost) a.len[v] = 0;
+    for (uint32_t e = e_lo + tid; e < e_hi; e += nthr) {
+        const uint64_t x = marker_at(a, e, sm);
+        a.mark_out[e] = x > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)x;
+    }
+    if (tid == 0 && sm) atomicAdd((unsigned long long *)a.steps, (unsigned long long)sm);
+}
+
 // ---- serving: slot admission, advance, result gather ----
 
 // Queries enter free slots: the slot's route starts empty at iteration 0
@@ -2160,6 +2303,10 @@ struct gmacop_graph {
     size_t cap_goal = 0, cap_goal_work = 0;
     uint32_t *goal = nullptr, *goal_work = nullptr, *goal_ctl = nullptr;
     uint32_t mean_t0 = 1;              // mean free-flow road time (ms), the scale of the search's bands
+    // the literal MACO-P loop (GMACOP_MODE_GREEDY): per vehicle and per road state
+    size_t cap_gveh = 0, cap_groad = 0;
+    uint32_t *gnode = nullptr, *gchoice = nullptr, *gvcity = nullptr;
+    uint64_t *gcsum = nullptr, *gmark = nullptr, *gmsum = nullptr;
     uint2 *rev_tw = nullptr;
     // statistics
     uint64_t *counters = nullptr;         // device [kCounters]
@@ -2196,6 +2343,7 @@ struct gmacop_graph {
         dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters); dfree(iter_max);
         dfree(lazy); dfree(dep_ind); dfree(touched); dfree(touched_n); dfree(dev_gen);
         dfree(goal); dfree(goal_work); dfree(goal_ctl); dfree(rev_tw);
+        dfree(gnode); dfree(gchoice); dfree(gvcity); dfree(gcsum); dfree(gmark); dfree(gmsum);
         glb.release();
         for (auto &t : pending) {
             (void)hipEventDestroy(t.a);
@@ -2355,7 +2503,7 @@ int validate_params(const gmacop_graph *g, const gmacop_params *p, uint32_t nq)
     if (p->tau_min_q16 == 0) return fail(GMACOP_E_INVAL, "tau_min_q16 must be >= 1");
     if (p->tau_min_q16 > p->tau0_q16 || p->tau0_q16 > p->tau_max_q16)
         return fail(GMACOP_E_INVAL, "need tau_min <= tau0 <= tau_max");
-    if (p->mode > GMACOP_MODE_INDEPENDENT) return fail(GMACOP_E_INVAL, "unknown mode %u", p->mode);
+    if (p->mode > GMACOP_MODE_GREEDY) return fail(GMACOP_E_INVAL, "unknown mode %u", p->mode);
     if (p->flags & ~(GMACOP_NO_LOAD_UPDATE | GMACOP_DEVICE_PTRS | GMACOP_TIME_KERNELS | GMACOP_HIP_GRAPH |
                      GMACOP_GOAL_EXACT | GMACOP_RESUME))
         return fail(GMACOP_E_INVAL, "unknown flags");
@@ -2789,6 +2937,8 @@ struct CallWork {
     uint64_t *lazy = nullptr, *dep_ind = nullptr;
     uint32_t *touched = nullptr, *touched_n = nullptr, *dev_gen = nullptr;
     uint32_t *goal = nullptr, *goal_work = nullptr, *goal_ctl = nullptr;   // exact goal term (GoalPlan)
+    uint32_t *gnode = nullptr, *gchoice = nullptr, *gvcity = nullptr;   // GMACOP_MODE_GREEDY
+    uint64_t *gcsum = nullptr, *gmark = nullptr, *gmsum = nullptr;
     bool side = false;          // the global walker may run on g->side beside the LDS walkers
     bool allow_graph = false;   // GMACOP_HIP_GRAPH may capture and replay the call
 };
@@ -2842,6 +2992,19 @@ int goal_plan(const gmacop_graph *g, const gmacop_params *p, uint64_t tasks, uin
     blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(1, budget / per_block));
     gp->blocks = (uint32_t)blocks;
     return GMACOP_OK;
+}
+
+// The greedy mode (the literal MACO-P loop) routes each vehicle once, without
+// ants or iterations, and always on the exact goal term.
+gmacop_params effective_params(const gmacop_params &p)
+{
+    gmacop_params e = p;
+    if (p.mode == GMACOP_MODE_GREEDY) {
+        e.ants = 1;
+        e.iterations = 0;
+        e.flags |= GMACOP_GOAL_EXACT;
+    }
+    return e;
 }
 
 // Checks shared by both routing entry points; on success *plan holds the walk schedule.
@@ -2962,6 +3125,20 @@ int route_work_grow(gmacop_graph *g, uint32_t nq, const gmacop_params *p, const 
             HIP_TRY(hipDeviceSynchronize());
         }
         w->goal = g->goal; w->goal_work = g->goal_work; w->goal_ctl = g->goal_ctl;
+    }
+    if (p->mode == GMACOP_MODE_GREEDY) {
+        size_t c1 = g->cap_gveh, c2 = g->cap_gveh, c3 = g->cap_gveh, c4 = g->cap_gveh, r1 = g->cap_groad,
+               r2 = g->cap_groad;
+        if ((rc = grow(&g->gnode, &c1, std::max<size_t>(nq, 1), false)) ||
+            (rc = grow(&g->gchoice, &c2, std::max<size_t>(nq, 1), false)) ||
+            (rc = grow(&g->gvcity, &c3, std::max<size_t>(nq, 1), false)) ||
+            (rc = grow(&g->gcsum, &c4, std::max<size_t>(nq, 1), false)) || (rc = grow(&g->gmark, &r1, g->m, false)) ||
+            (rc = grow(&g->gmsum, &r2, g->m, false)))
+            return rc;
+        g->cap_gveh = std::min(std::min(c1, c2), std::min(c3, c4));
+        g->cap_groad = std::min(r1, r2);
+        w->gnode = g->gnode; w->gchoice = g->gchoice; w->gvcity = g->gvcity; w->gcsum = g->gcsum;
+        w->gmark = g->gmark; w->gmsum = g->gmsum;
     }
     w->side = true;
     w->allow_graph = true;
@@ -3086,6 +3263,22 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
         hipLaunchKernelGGL(k_init_vehicles, dim3(blocks_for(std::max(nq, 1u), 256)), dim3(256), 0, st, nq, resume,
                            best_len, best_cost, w.iter_key, steps);
         hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
+        if (p->mode == GMACOP_MODE_GREEDY) {   // the literal MACO-P loop: one block per city, all ticks
+            if (nq) {
+                hipLaunchKernelGGL(k_greedy_prep, dim3(blocks_for(nq, 256)), dim3(256), 0, st, od, nq, g->n,
+                                   (const uint32_t *)g->node_inst, w.gvcity, w.gnode, w.gchoice, w.gcsum);
+                GreedyArgs gy{};
+                gy.od = od; gy.nq = nq; gy.n = g->n; gy.max_steps = S; gy.theta = p->theta; gy.stride = gp.stride;
+                gy.row_ptr = g->row_ptr; gy.col = g->col; gy.cost = g->cost; gy.node_inst = g->node_inst;
+                gy.inst_off = g->inst_off_dev; gy.inst_eoff = g->inst_eoff_dev; gy.base_load = g->base_load;
+                gy.goal = w.goal; gy.node = w.gnode; gy.choice = w.gchoice; gy.vcity = w.gvcity; gy.csum = w.gcsum;
+                gy.mark = w.gmark; gy.msum = w.gmsum; gy.cnt = g->cnt; gy.mark_out = g->tau;
+                gy.path = best_path; gy.len = best_len; gy.cost_out = best_cost; gy.steps = steps;
+                hipLaunchKernelGGL(k_greedy, dim3(g->n_inst), dim3(1024), 0, st, gy);
+            }
+            HIP_TRY(hipGetLastError());
+            return GMACOP_OK;
+        }
         if (nq && !plan.legacy) {
             hipLaunchKernelGGL(k_classify, dim3(blocks_for(nq, 256)), dim3(256), 0, st, od, nq, g->n,
                                (const uint32_t *)g->node_inst, (const uint8_t *)g->inst_fits, w.vclass);
@@ -3316,6 +3509,14 @@ size_t carve_work(uint8_t *base, gmacop_graph *g, uint32_t nq, const gmacop_para
         x.touched_n = c.take<uint32_t>(nq);
         x.touched = c.take<uint32_t>((size_t)nq * tcap);
     }
+    if (p->mode == GMACOP_MODE_GREEDY) {
+        x.gnode = c.take<uint32_t>(nq);
+        x.gchoice = c.take<uint32_t>(nq);
+        x.gvcity = c.take<uint32_t>(nq);
+        x.gcsum = c.take<uint64_t>(nq);
+        x.gmark = c.take<uint64_t>(g->m);
+        x.gmsum = c.take<uint64_t>(g->m);
+    }
     x.path = c.take<uint32_t>((size_t)S * NA);
     x.ant_len = c.take<uint32_t>(NA);
     x.ant_cost = c.take<uint32_t>(NA);
@@ -3339,9 +3540,12 @@ size_t carve_work(uint8_t *base, gmacop_graph *g, uint32_t nq, const gmacop_para
 
 }  // namespace
 
-extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
+extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *params,
                                   gmacop_result *out, void *hip_stream)
 {
+    if (!params) return fail(GMACOP_E_INVAL, "params is NULL");
+    const gmacop_params pe = effective_params(*params);
+    const gmacop_params *p = &pe;
     WalkPlan plan;
     int rc = route_check(g, q, nq, p, out, &plan);
     if (rc) return rc;
@@ -3353,9 +3557,12 @@ extern "C" int gmacop_route_batch(gmacop_graph *g, const gmacop_od *q, uint32_t 
     return route_run(g, q, nq, p, out, st, plan, gp, w);
 }
 
-extern "C" int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_params *p,
-                                          gmacop_result *out, void *hip_stream)
+extern "C" int gmacop_route_batch_noalloc(gmacop_graph *g, const gmacop_od *q, uint32_t nq,
+                                          const gmacop_params *params, gmacop_result *out, void *hip_stream)
 {
+    if (!params) return fail(GMACOP_E_INVAL, "params is NULL");
+    const gmacop_params pe = effective_params(*params);
+    const gmacop_params *p = &pe;
     if (p && (p->flags & (GMACOP_HIP_GRAPH | GMACOP_TIME_KERNELS)))
         return fail(GMACOP_E_INVAL, "gmacop_route_batch_noalloc takes neither GMACOP_HIP_GRAPH nor GMACOP_TIME_KERNELS");
     WalkPlan plan;

@@ -25,6 +25,7 @@ E_UNSUPPORTED = -5
 
 MODE_SHARED = 0
 MODE_INDEPENDENT = 1
+MODE_GREEDY = 2
 NO_LOAD_UPDATE = 1
 DEVICE_PTRS = 2
 
