@@ -26,6 +26,7 @@ MODE_SHARED = 0
 MODE_INDEPENDENT = 1
 FLAG_NO_LOAD_UPDATE = 1
 FLAG_GOAL_EXACT = 16
+FLAG_SIGNAL_TIMED = 64
 
 E_INVAL = -1
 E_RANGE = -2
@@ -80,6 +81,9 @@ def lib():
         L.orc_goal.argtypes = [vp, vp, u32, u32]
         L.orc_goal.restype = u64
         L.orc_goal_exact.argtypes = [vp, vp, u32, vp]
+        L.orc_signal_windows.argtypes = [vp, vp, vp]
+        L.orc_timed_cost.argtypes = [vp, vp, u32, u64]
+        L.orc_timed_cost.restype = u32
         L.orc_greedy.argtypes = [vp, vp, vp, u32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_greedy.restype = C.c_int
         L.orc_shortest_route.argtypes = [vp, vp, u32, u32, u32, vp]
@@ -182,6 +186,21 @@ def shortest_route(g, p: dict, src: int, dst: int, max_len: int) -> np.ndarray:
     path = np.zeros(max(1, max_len), np.uint32)
     n = lib().orc_shortest_route(C.byref(gr.s), C.byref(pp), int(src), int(dst), int(max_len), _ptr(path))
     return path[:n].copy()
+
+
+def signal_windows(g):
+    """Per road: start (ms, modulo the head's cycle) and length of its approach's green."""
+    gr = _GraphRef(g)
+    s = np.zeros(gr.m, np.uint32)
+    w = np.zeros(gr.m, np.uint32)
+    lib().orc_signal_windows(C.byref(gr.s), _ptr(s), _ptr(w))
+    return s, w
+
+
+def timed_cost(g, p: dict, e: int, clock: int) -> int:
+    """Cost of road e entered at time `clock` with time-dependent signals (sensed loads)."""
+    gr, pp = _GraphRef(g), _params(p)
+    return int(lib().orc_timed_cost(C.byref(gr.s), C.byref(pp), int(e), int(clock)))
 
 
 def eta(delta: int) -> int:

@@ -268,6 +268,81 @@ uint32_t orc_shortest_route(const orc_graph *g, const orc_params *p, uint32_t sr
     return len;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Time-dependent signals (Section 4.1, Fig. 3 signal block with the phases */
+/* run in time).  Green windows: the approaches of an intersection with     */
+/* cycle C take their greens in turn, in road order, each for               */
+/* floor(C * green / 1000) ms; the first window starts at time 0 (the start */
+/* of the call, when every vehicle departs) and each later one where the    */
+/* previous ended, modulo C.                                                 */
+/* ------------------------------------------------------------------------ */
+void orc_signal_windows(const orc_graph *g, uint32_t *start, uint32_t *green)
+{
+    uint64_t *acc = (uint64_t *)calloc(g->n ? g->n : 1, sizeof(uint64_t));
+    for (uint32_t e = 0; e < g->m; ++e) {
+        const uint32_t v = g->col[e];
+        const uint64_t C = g->cycle_ms[v];
+        if (C == 0) { start[e] = green[e] = 0; continue; }
+        const uint64_t len = C * g->green_pm[e] / 1000u;
+        start[e] = (uint32_t)(acc[v] % C);
+        green[e] = (uint32_t)len;
+        acc[v] += len;
+    }
+    free(acc);
+}
+
+/* The wait of a vehicle reaching the signal at the end of road e at time   */
+/* `arrival` (ms since the call's start): none inside the approach's green  */
+/* window, else until the window opens again; an approach that would wait   */
+/* longer than T_max is given the green then (Fig. 3, t_w > T_max).  A road */
+/* whose approach holds the preemptive green (orc_cost_table) waits 0.       */
+typedef struct {
+    const uint32_t *travel;     /* [m] travel time of the road at the current loads (no wait) */
+    const uint8_t *pre;         /* [m] the approach holds the preemptive green                */
+    const uint32_t *wstart, *wgreen;   /* [m] its green window (orc_signal_windows)          */
+} orc_timing;
+
+static uint32_t timed_cost(const orc_graph *g, const orc_params *p, const orc_timing *tm, uint32_t e, uint64_t clock)
+{
+    const uint64_t travel = tm->travel[e];
+    const uint64_t C = g->cycle_ms[g->col[e]];
+    uint64_t wait = 0;
+    if (C && !tm->pre[e]) {
+        const uint64_t q = ((clock + travel) % C + C - tm->wstart[e]) % C;   /* phase from the window's opening */
+        wait = q < tm->wgreen[e] ? 0 : C - q;
+        if (wait > p->t_max_ms) wait = p->t_max_ms;
+    }
+    const uint64_t c = travel + wait;
+    return c > COST_CAP ? COST_CAP : (uint32_t)c;
+}
+
+/* Travel part of the cost table: t0 while load <= theta, else floor(t0 * load / theta). */
+static void travel_table(const orc_graph *g, const orc_params *p, const uint32_t *load, const uint32_t *t0,
+                         uint32_t *travel)
+{
+    for (uint32_t e = 0; e < g->m; ++e) {
+        uint64_t x = load[e] <= p->theta ? t0[e] : (uint64_t)t0[e] * load[e] / p->theta;
+        travel[e] = x > COST_CAP ? COST_CAP : (uint32_t)x;
+    }
+}
+
+uint32_t orc_timed_cost(const orc_graph *g, const orc_params *p, uint32_t e, uint64_t clock)
+{
+    const uint32_t m = g->m;
+    uint32_t *t0 = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1)), *wf = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *cost = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1)), *tr = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *ws = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1)), *wg = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint8_t *pre = (uint8_t *)malloc(m + 1);
+    orc_edge_static(g, p, t0, wf);
+    orc_cost_table(g, p, g->base_load, t0, wf, cost, pre);
+    travel_table(g, p, g->base_load, t0, tr);
+    orc_signal_windows(g, ws, wg);
+    const orc_timing tm = {tr, pre, ws, wg};
+    const uint32_t c = timed_cost(g, p, &tm, e, clock);
+    free(t0); free(wf); free(cost); free(tr); free(ws); free(wg); free(pre);
+    return c;
+}
+
 /* Desirability of a road from its reduced cost delta = cost + h(head) - h(tail):
  * eta = floor(2^26 / max(delta, 1)), clamped to [1, 65535]. */
 uint32_t orc_eta(int64_t delta)
@@ -334,9 +409,9 @@ static int64_t goal_of(const orc_graph *g, const orc_params *p, const uint32_t *
 }
 
 static int walk_impl(const orc_graph *g, const orc_params *p, const uint32_t *tau, const uint32_t *cost,
-                     const uint32_t *hrow, uint32_t qid, uint32_t src, uint32_t dst, uint32_t ant, uint32_t iter,
-                     uint32_t *path, uint32_t *len, uint32_t *cost_sum, uint64_t *selections,
-                     uint64_t *wbuf)
+                     const orc_timing *tm, const uint32_t *hrow, uint32_t qid, uint32_t src, uint32_t dst,
+                     uint32_t ant, uint32_t iter, uint32_t *path, uint32_t *len, uint32_t *cost_sum,
+                     uint64_t *selections, uint64_t *wbuf)
 {
     uint8_t *visited = g_visited;
     uint32_t u = src, s = 0, cs = 0;
@@ -350,7 +425,9 @@ static int walk_impl(const orc_graph *g, const orc_params *p, const uint32_t *ta
         for (uint32_t j = 0; j < d; ++j) {
             const uint32_t e = rs + j, x = g->col[e];
             if (visited[x]) { wbuf[j] = 0; continue; }
-            const int64_t delta = (int64_t)cost[e] + goal_of(g, p, hrow, x, dst) - hu;
+            /* the road's cost: the table's, or with time-dependent signals the one at this ant's clock */
+            const uint32_t ce = tm ? timed_cost(g, p, tm, e, cs) : cost[e];
+            const int64_t delta = (int64_t)ce + goal_of(g, p, hrow, x, dst) - hu;
             wbuf[j] = ipow(tau[e], p->alpha) * ipow(orc_eta(delta), p->beta);
             T += wbuf[j];
         }
@@ -359,7 +436,7 @@ static int walk_impl(const orc_graph *g, const orc_params *p, const uint32_t *ta
         const uint32_t e = rs + j;
         path[s++] = e;
         *selections += 1;
-        const uint64_t c = (uint64_t)cs + cost[e];
+        const uint64_t c = (uint64_t)cs + (tm ? timed_cost(g, p, tm, e, cs) : cost[e]);
         cs = c > PATH_COST_CAP ? PATH_COST_CAP : (uint32_t)c;
         u = g->col[e];
         visited[u] = 1;
@@ -404,9 +481,28 @@ int orc_walk(const orc_graph *g, const orc_params *p, const uint32_t *tau, const
         hrow = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
         orc_goal_exact(g, p, dst, hrow);
     }
-    const int ok = walk_impl(g, p, tau, cost, hrow, qid, src, dst, ant, iter, path, len, cost_sum, selections, wbuf);
+    /* time-dependent signals: travel times and preemption at the sensed loads */
+    uint32_t *t0 = NULL, *wf = NULL, *tc = NULL, *tr = NULL, *ws = NULL, *wg = NULL;
+    uint8_t *pre = NULL;
+    orc_timing tm_store, *tm = NULL;
+    if (p->flags & ORC_FLAG_SIGNAL_TIMED) {
+        const uint32_t m = g->m;
+        t0 = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1)); wf = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+        tc = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1)); tr = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+        ws = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1)); wg = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+        pre = (uint8_t *)malloc(m + 1);
+        orc_edge_static(g, p, t0, wf);
+        orc_cost_table(g, p, g->base_load, t0, wf, tc, pre);
+        travel_table(g, p, g->base_load, t0, tr);
+        orc_signal_windows(g, ws, wg);
+        tm_store = (orc_timing){tr, pre, ws, wg};
+        tm = &tm_store;
+    }
+    const int ok = walk_impl(g, p, tau, cost, tm, hrow, qid, src, dst, ant, iter, path, len, cost_sum, selections,
+                             wbuf);
     free(wbuf);
     free(hrow);
+    free(t0); free(wf); free(tc); free(tr); free(ws); free(wg); free(pre);
     return ok;
 }
 
@@ -449,6 +545,7 @@ typedef struct {
     uint32_t *ant_path, *iter_path;
     uint64_t *wbuf;
     uint64_t steps;
+    const orc_timing *tm;      /* time-dependent signals, or NULL */
 } route_ctx;
 
 static void vehicle_iteration(route_ctx *c, uint32_t qid, uint32_t src, uint32_t dst, uint32_t t,
@@ -460,7 +557,8 @@ static void vehicle_iteration(route_ctx *c, uint32_t qid, uint32_t src, uint32_t
     uint32_t iter_len = 0;
     for (uint32_t k = 0; k < p->ants; ++k) {
         uint32_t len, cs;
-        if (!walk_impl(c->g, p, tau, cost, hrow, qid, src, dst, k, t, c->ant_path, &len, &cs, &c->steps, c->wbuf))
+        if (!walk_impl(c->g, p, tau, cost, c->tm, hrow, qid, src, dst, k, t, c->ant_path, &len, &cs, &c->steps,
+                       c->wbuf))
             continue;
         const uint64_t key = ((uint64_t)cs << 32) | k;
         if (key < iter_key) {
@@ -496,7 +594,7 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
     if (rc) return rc;
     const uint32_t m = g->m, S = p->max_steps;
     ensure_visited(g->n);
-    route_ctx c = {g, p, S, NULL, NULL, NULL, 0};
+    route_ctx c = {g, p, S, NULL, NULL, NULL, 0, NULL};
     c.wbuf = (uint64_t *)malloc(sizeof(uint64_t) * (max_out_degree(g) + 1));
     c.ant_path = (uint32_t *)malloc(sizeof(uint32_t) * S);
     c.iter_path = (uint32_t *)malloc(sizeof(uint32_t) * S);
@@ -519,12 +617,24 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
 
     orc_edge_static(g, p, t0, wf);
     for (uint32_t e = 0; e < m; ++e) load[e] = g->base_load[e];
+    /* time-dependent signals: green windows, and per cost table the travel times and preemption */
+    uint32_t *tr = NULL, *ws = NULL, *wg = NULL;
+    uint8_t *pre = NULL;
+    orc_timing tm_store;
+    if (p->flags & ORC_FLAG_SIGNAL_TIMED) {
+        tr = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1)); ws = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+        wg = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1)); pre = (uint8_t *)malloc(m + 1);
+        orc_signal_windows(g, ws, wg);
+        tm_store = (orc_timing){tr, pre, ws, wg};
+        c.tm = &tm_store;
+    }
     for (size_t i = 0; i < (size_t)n_tau * m; ++i) tau[i] = p->tau0_q16;
     for (uint32_t v = 0; v < nv; ++v) { path_len[v] = 0; cost_ms[v] = U32_MAX; }
 
     if (shared) {
         for (uint32_t t = 0; t < p->iterations; ++t) {
-            orc_cost_table(g, p, load, t0, wf, cost, NULL);
+            orc_cost_table(g, p, load, t0, wf, cost, pre);
+            if (pre) travel_table(g, p, load, t0, tr);
             memset(dep, 0, sizeof(uint64_t) * m);
             for (uint32_t v = 0; v < nv; ++v) {
                 vehicle_iteration(&c, qid[v], src[v], dst[v], t, tau, cost, HROW(v), dep,
@@ -539,7 +649,8 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
             }
         }
     } else {
-        orc_cost_table(g, p, load, t0, wf, cost, NULL);
+        orc_cost_table(g, p, load, t0, wf, cost, pre);
+        if (pre) travel_table(g, p, load, t0, tr);
         for (uint32_t v = 0; v < nv; ++v) {
             uint32_t *tv = tau + (size_t)v * m;
             for (uint32_t t = 0; t < p->iterations; ++t) {
@@ -556,7 +667,8 @@ int orc_route(const orc_graph *g, const uint32_t *qid, const uint32_t *src, cons
     if (tau_out) memcpy(tau_out, tau, sizeof(uint32_t) * (size_t)n_tau * m);
     if (load_out) memcpy(load_out, load, sizeof(uint32_t) * m);
     free(c.wbuf); free(c.ant_path); free(c.iter_path);
-    free(t0); free(wf); free(cost); free(load); free(dep); free(tau); free(hrows);
+    free(t0); free(wf); free(cost); free(load); free(dep); free(tau); free(hrows); free(tr); free(ws); free(wg);
+    free(pre);
 #undef HROW
     return 0;
 }

@@ -54,6 +54,7 @@ typedef struct {
 #define ORC_MODE_INDEPENDENT 1u
 #define ORC_FLAG_NO_LOAD_UPDATE 1u
 #define ORC_FLAG_GOAL_EXACT 16u   /* goal term = exact shortest free-flow time to dst */
+#define ORC_FLAG_SIGNAL_TIMED 64u /* signal waits at the ant's arrival time in the green windows */
 
 /* Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -76,6 +77,12 @@ void orc_goal_exact(const orc_graph *g, const orc_params *p, uint32_t dst, uint3
  * longer than max_len. */
 uint32_t orc_shortest_route(const orc_graph *g, const orc_params *p, uint32_t src, uint32_t dst,
                             uint32_t max_len, uint32_t *path);
+/* Green windows of the time-dependent signals: per road e, the start (ms, mod
+ * the head's cycle) and length of its approach's green. */
+void orc_signal_windows(const orc_graph *g, uint32_t *start, uint32_t *green);
+/* Cost of road e entered at time `clock` (ms since the call's start) with
+ * time-dependent signals, at the sensed loads. */
+uint32_t orc_timed_cost(const orc_graph *g, const orc_params *p, uint32_t e, uint64_t clock);
 /* Heuristic desirability of a road from its reduced cost. */
 uint32_t orc_eta(int64_t delta);
 /* Roulette: index chosen among d weights by a 64-bit random word. */

@@ -61,6 +61,11 @@ MUTANTS = {
                             "mark[e] + (int64_t)moves[e];"),
     "greedy_tie_last": ("else if (second == U32_MAX || mark[e] < mark[second]) second = e;",
                         "else if (second == U32_MAX || mark[e] <= mark[second]) second = e;"),
+    "timed_windows_not_accumulated": ("start[e] = (uint32_t)(acc[v] % C);", "start[e] = 0;"),
+    "timed_no_cap": ("if (wait > p->t_max_ms) wait = p->t_max_ms;", ""),
+    "timed_entry_instead_of_arrival": ("const uint64_t q = ((clock + travel) % C + C - tm->wstart[e]) % C;",
+                                       "const uint64_t q = (clock % C + C - tm->wstart[e]) % C;"),
+    "timed_preemption_ignored": ("if (C && !tm->pre[e]) {", "if (C) {"),
     "apply_after_load_update": (
         """            for (uint32_t e = 0; e < m; ++e) tau[e] = orc_apply_tau(p, tau[e], dep[e], load[e]);
             if (!(p->flags & ORC_FLAG_NO_LOAD_UPDATE)) {

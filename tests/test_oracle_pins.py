@@ -950,3 +950,81 @@ def test_greedy_routes_descend_to_the_destination(orc):
     one_way = from_edges(4, [0, 1, 2], [1, 2, 1])            # 3 cannot be reached from 0
     ru = orc.greedy(one_way, veh([0], [3]), p)
     assert ru["path_len"].tolist() == [0] and ru["cost_ms"].tolist() == [0xFFFFFFFF]
+
+
+# ---------------------------------------------------------------------------
+# time-dependent signals (green windows, the ant's clock, the T_max guard)
+# ---------------------------------------------------------------------------
+
+def signal_star():
+    """Roads 0->3, 1->3, 2->3 into a 100 s signal (greens 500, 300, 200 per
+    mille), 3->4 and 4->5 into a 90 s signal at 5 (greens 700 then 600, which
+    overrun the cycle), 5->6 unsignalised; every road 10 s of free flow
+    (len 1000 dm at 36 km/h)."""
+    return from_edges(7, [0, 1, 2, 3, 4, 3, 5], [3, 3, 3, 4, 5, 5, 6], len_dm=1000, speed_kmh=36,
+                      green_pm=[500, 300, 200, 1000, 700, 600, 1000], cycle_ms=[0, 0, 0, 100000, 0, 90000, 0])
+
+
+def test_signal_windows_by_hand(orc):
+    """Node 3: windows [0, 50 s), [50, 80 s), [80, 100 s).  Node 5 (C = 90 s):
+    roads 3->5 (600) and 4->5 (700) in road order: 3->5 is road 4, so
+    [0, 54 s), then 4->5 from 54 s for 63 s (wrapping)."""
+    g = signal_star()
+    s, w = orc.signal_windows(g)
+    order = list(zip(g.tail().tolist(), g.col.tolist()))
+    got = {order[e]: (int(s[e]), int(w[e])) for e in range(g.m)}
+    assert got[(0, 3)] == (0, 50000) and got[(1, 3)] == (50000, 30000) and got[(2, 3)] == (80000, 20000)
+    assert got[(3, 5)] == (0, 54000) and got[(4, 5)] == (54000, 63000)
+    assert got[(3, 4)] == (0, 0) and got[(5, 6)] == (0, 0)
+
+
+def test_timed_wait_by_hand(orc):
+    """Road 1->3 (window [50, 80 s) of 100 s, 10 s of travel): entered at
+    35 s it reaches the signal at 45 s and waits 5 s; entered at 45 s it
+    arrives in the green; entered at 80 s it would wait 60 s and is given the
+    green after T_max = 20 s.  With the approach preempted (the longest
+    queue) it never waits."""
+    g = signal_star()
+    p = default_params(t_max_ms=20000)
+    e = [i for i, (a, b) in enumerate(zip(g.tail().tolist(), g.col.tolist())) if (a, b) == (1, 3)][0]
+    assert orc.timed_cost(g, p, e, 35000) == 15000
+    assert orc.timed_cost(g, p, e, 45000) == 10000
+    assert orc.timed_cost(g, p, e, 80000) == 30000
+    assert orc.timed_cost(g, p, e, 35000 + 3 * 100000) == 15000
+    gl = from_edges(7, [0, 1, 2, 3, 4, 3, 5], [3, 3, 3, 4, 5, 5, 6], len_dm=1000, speed_kmh=36,
+                    green_pm=[500, 300, 200, 1000, 700, 600, 1000], cycle_ms=[0, 0, 0, 100000, 0, 90000, 0],
+                    base_load=[0, 3, 0, 0, 0, 0, 0])
+    assert orc.timed_cost(gl, p, e, 35000) == 10000 and orc.timed_cost(gl, p, e, 80000) == 10000
+
+
+def test_timed_waits_average_to_the_fixed_wait(orc):
+    """Over one cycle of integer arrival times the waits of an approach with
+    red time r sum to r(r+1)/2 (the uniform-arrival expectation behind the
+    fixed-time wait floor(r^2 / 2C), up to the half-step)."""
+    C, green = 2000, 300
+    g = from_edges(3, [0, 1], [1, 2], len_dm=[1000, 1000], speed_kmh=36, green_pm=[green, 1000],
+                   cycle_ms=[0, C, 0])
+    p = default_params(t_max_ms=10 ** 6)
+    travel = 10000
+    total = sum(orc.timed_cost(g, p, 0, clock) - travel for clock in range(C))
+    r = C - C * green // 1000
+    assert total == r * (r + 1) // 2
+
+
+def test_timed_route_costs_follow_the_clock(orc):
+    """Whole runs with time-dependent signals and frozen loads: each reported
+    route cost equals its roads' costs re-evaluated along the route with the
+    clock (the cost so far) as entry time; the optimum of a tiny grid is
+    reached under the timed costs too."""
+    w = grid32(vehicles=12, ants=16, iterations=5)
+    g, V = w.graph, w.vehicles
+    p = dict(w.params, flags=orc.FLAG_NO_LOAD_UPDATE | orc.FLAG_SIGNAL_TIMED)
+    res = orc.route(g, V, p)
+    _check_paths(g, V, res, p["max_steps"])
+    for v in range(len(V)):
+        L = int(res["path_len"][v])
+        assert L > 0
+        clock = 0
+        for e in res["path_edges"][v, :L].tolist():
+            clock += orc.timed_cost(g, p, e, clock)
+        assert res["cost_ms"][v] == clock
