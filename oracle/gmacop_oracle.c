@@ -101,6 +101,13 @@ void orc_edge_static(const orc_graph *g, const orc_params *p, uint32_t *t0, uint
     }
 }
 
+/* Congestion: a road carrying more than theta vehicles is slowed in        */
+/* proportion to its load, floor(t0 * load / theta); below that, t0.        */
+static uint64_t travel_ms(uint32_t t0, uint32_t load, uint32_t theta)
+{
+    return load <= theta ? t0 : (uint64_t)t0 * load / theta;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Cost table (Section 4.2: Calc_Dens, Comp_Thres, Eval_Rout; Fig. 3).      */
 /* A phase of an intersection is one incoming road; its queue is the road's */
@@ -127,8 +134,7 @@ void orc_cost_table(const orc_graph *g, const orc_params *p, const uint32_t *loa
                           (load[e] > p->th_max || best_edge[v] == e);
         if (preempted) preempted[e] = (uint8_t)green;
         const uint64_t wait = green ? 0 : wf[e];
-        const uint64_t travel = load[e] <= p->theta ? t0[e] : (uint64_t)t0[e] * load[e] / p->theta;
-        uint64_t c = travel + wait;
+        uint64_t c = travel_ms(t0[e], load[e], p->theta) + wait;
         if (c > COST_CAP) c = COST_CAP;
         cost[e] = (uint32_t)c;
     }
@@ -321,7 +327,7 @@ static void travel_table(const orc_graph *g, const orc_params *p, const uint32_t
                          uint32_t *travel)
 {
     for (uint32_t e = 0; e < g->m; ++e) {
-        uint64_t x = load[e] <= p->theta ? t0[e] : (uint64_t)t0[e] * load[e] / p->theta;
+        const uint64_t x = travel_ms(t0[e], load[e], p->theta);
         travel[e] = x > COST_CAP ? COST_CAP : (uint32_t)x;
     }
 }

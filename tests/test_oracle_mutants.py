@@ -19,7 +19,7 @@ MUTANTS = {
     "red_wait_formula": ("red * red / (2 * C)", "red * red / C"),
     "preempt_tie_break": ("load[e] > load[best_edge[v]]", "load[e] >= load[best_edge[v]]"),
     "th_max_comparison": ("load[e] > p->th_max", "load[e] >= p->th_max"),
-    "congestion_divisor": ("(uint64_t)t0[e] * load[e] / p->theta", "(uint64_t)t0[e] * load[e] / (p->theta + 1)"),
+    "congestion_divisor": ("(uint64_t)t0 * load / theta", "(uint64_t)t0 * load / (theta + 1)"),
     "goal_sign": ("(int64_t)g->x_dm[node] - g->x_dm[dst]", "(int64_t)g->x_dm[node] + g->x_dm[dst]"),
     "eta_scale": ("((uint64_t)1 << 26) / d", "((uint64_t)1 << 25) / d"),
     "roulette_strict": ("if (prefix > target) return j;", "if (prefix >= target) return j;"),
