@@ -90,6 +90,21 @@ extern "C" {
                                        (host buffers; device buffers are not checked,
                                        such roads are ignored)                          */
 
+#define GMACOP_SIGNAL_TIMED   64u   /* time-dependent signals (Section 4.1, Fig. 3 signal
+                                       block run in time): the approaches of an
+                                       intersection with cycle C take their greens in
+                                       turn, in road order, each for
+                                       floor(C * green_pm / 1000) ms, the first from time
+                                       0 of the call (every vehicle departs then); an
+                                       ant's clock is its cost so far, and a road's cost
+                                       is its travel time plus the wait from its arrival
+                                       at the head's signal to the next green of its
+                                       approach, capped at t_max_ms (Fig. 3
+                                       "t_w > T_max"), none for the preemptive green.
+                                       Served by the global-memory walker.  Not with
+                                       GMACOP_MODE_GREEDY, in a router, or on graphs of
+                                       2^24 nodes or more (GMACOP_E_UNSUPPORTED)        */
+
 /* Opaque handle: the graph, its static per-road data and the pheromone / load
  * state on the device.  Owns all of its device memory. */
 typedef struct gmacop_graph gmacop_graph;

@@ -327,6 +327,7 @@ struct CostArgs {
     const uint32_t *rev_ptr, *rev_edge, *cycle, *load, *t0, *wf;
     uint32_t *cost;
     uint32_t *mir;             // road records of the global walker (8 words per road) or NULL
+    uint32_t timed;            // time-dependent signals: cost = travel only, the green flag into the records
 };
 
 // Per intersection v: the approach (incoming road) with the longest
@@ -343,10 +344,13 @@ __device__ __forceinline__ void store_cost(const CostArgs &a, uint32_t e, uint32
                                            bool green)
 {
     const uint64_t travel = L <= a.theta ? t0 : (uint64_t)t0 * L / a.theta;
-    uint64_t c = travel + (green ? 0u : wf);
+    uint64_t c = travel + (green || a.timed ? 0u : wf);   // timed: the walker adds the wait at the ant's clock
     c = c > kRoadCostCap ? kRoadCostCap : c;
     a.cost[e] = (uint32_t)c;
-    if (a.mir) a.mir[(size_t)e * 8 + 4] = (uint32_t)c;
+    if (a.mir) {
+        a.mir[(size_t)e * 8 + 4] = (uint32_t)c;
+        if (a.timed) a.mir[(size_t)e * 8 + 6] = green ? 1u : 0u;
+    }
 }
 
 // One thread per intersection.  The first kCostBatch approaches are read
@@ -1180,9 +1184,29 @@ struct GlbWalkArgs {
     uint32_t *iter_max;
     const uint32_t *goal;      // exact goal rows [nq][goal_stride] (city-local node ids), or NULL: straight line
     uint32_t goal_stride;
+    const uint4 *sig;          // time-dependent signals: per road (head's cycle, green start, green length, 0), or NULL
+    uint32_t t_max;
 };
 
 constexpr uint8_t kWalkerNone = 0, kWalkerGlobal = 8;   // 1..6: LDS walker classes
+
+// Cost of a road entered at `clock` (ms since the call's start) under
+// time-dependent signals: its travel time, plus the wait from its arrival at
+// the head's signal to the next opening of its approach's green window
+// (s = cycle, window start, window length), capped at T_max; none when the
+// approach holds the preemptive green or the head has no signal.  Capped at
+// 2^31 like every road cost.
+__device__ __forceinline__ uint32_t timed_cost(uint32_t travel, uint32_t green, uint4 s, uint64_t clock, uint32_t t_max)
+{
+    uint64_t wait = 0;
+    if (s.x && !green) {
+        const uint64_t q = ((clock + travel) % s.x + s.x - s.y) % s.x;   // phase from the window's opening
+        wait = q < s.z ? 0 : s.x - q;
+        wait = wait > t_max ? t_max : wait;
+    }
+    const uint64_t c = travel + wait;
+    return c > kRoadCostCap ? kRoadCostCap : (uint32_t)c;
+}
 
 __device__ __forceinline__ uint32_t bloom_h1(uint32_t x, uint32_t lg) { return (x * 0x9E3779B1u) >> (32 - lg); }
 __device__ __forceinline__ uint32_t bloom_h2(uint32_t x, uint32_t lg)
@@ -1218,7 +1242,7 @@ struct GlbWalk {
 // same lane's later reads of the word come after the write).  A word written
 // by an earlier walk carries an older epoch and counts as empty, so nothing
 // is cleared between walks.
-template <int L, int CH, int SL>
+template <int L, int CH, int SL, bool TM>
 __device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, GlbWalk &w, uint32_t *bloom, uint64_t *gw,
                                          uint32_t epoch, uint32_t j, uint64_t myr)
 {
@@ -1226,20 +1250,24 @@ __device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, GlbWalk &w, uint3
     const uint32_t lg = a.bloom_log2;
     uint64_t wt[CH], incl[CH];
     uint4 rec[CH];
-    uint32_t cst[CH];
+    uint32_t cst[CH], grn[CH];
+    uint4 sg[CH];   // TM: the heads' signal windows
     int64_t hx[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {   // lanes past the out-degree load nothing
         const uint32_t o = (uint32_t)(c * L) + j, idx = w.rs + o;
         uint4 r0 = make_uint4(0, 0, 0, 0), r1 = make_uint4(0, 0, 0, 0);
         uint32_t tl = 0;
+        sg[c] = make_uint4(0, 0, 0, 0);
         if (o < w.d) {
             r0 = a.rec32[2 * (size_t)idx];
             r1 = a.rec32[2 * (size_t)idx + 1];
             if (!w.tau.dense) tl = w.tau(idx);
+            if constexpr (TM) sg[c] = a.sig[idx];
         }
         rec[c] = r0;
         cst[c] = r1.x;
+        grn[c] = r1.z;
         wt[c] = w.tau.dense ? r1.y : tl;
     }
     if (w.pw) {   // group lane 0: the visited bit of the node entered last step
@@ -1264,6 +1292,8 @@ __device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, GlbWalk &w, uint3
         }
         hx[c] = 0;
         if (live) {
+            if constexpr (TM)   // time-dependent signals: the road's cost at this ant's clock (its capped cost so far)
+                cst[c] = timed_cost(cst[c], grn[c], sg[c], w.cs > kPathCostCap ? kPathCostCap : w.cs, a.t_max);
             hx[c] = a.goal ? (int64_t)w.grow[xh - w.n_lo]
                            : goal_ms((int32_t)rec[c].z, (int32_t)rec[c].w, w.dx, w.dy, a.kgoal);
             const uint32_t eta = eta_of((int64_t)cst[c] + hx[c] - w.hu);
@@ -1329,12 +1359,12 @@ __device__ __forceinline__ bool glb_step(const GlbWalkArgs &a, GlbWalk &w, uint3
     return true;
 }
 
-template <int L, int CH, int SL>
+template <int L, int CH, int SL, bool TM>
 __device__ __forceinline__ bool glb_steps(const GlbWalkArgs &a, GlbWalk &w, uint32_t *bloom, uint64_t *gw,
                                           uint32_t epoch, uint32_t j, uint64_t myr)
 {
-    if (w.s >= a.max_steps || !glb_step<L, CH, SL>(a, w, bloom, gw, epoch, j, myr)) return false;
-    if constexpr (SL + 1 < L) return glb_steps<L, CH, SL + 1>(a, w, bloom, gw, epoch, j, myr);
+    if (w.s >= a.max_steps || !glb_step<L, CH, SL, TM>(a, w, bloom, gw, epoch, j, myr)) return false;
+    if constexpr (SL + 1 < L) return glb_steps<L, CH, SL + 1, TM>(a, w, bloom, gw, epoch, j, myr);
     return true;
 }
 
@@ -1345,8 +1375,8 @@ __device__ __forceinline__ bool glb_steps(const GlbWalkArgs &a, GlbWalk &w, uint
 // wait for the longest walk of their wave or block.  The groups of a wave
 // that need an ant take their tickets together, from a per-wave range that
 // is refilled one atomic at a time.  The last wave out resets the counters
-// for the next launch.
-template <int L, int CH>
+// for the next launch.  TM: roads cost by the time-dependent signal rule (a.sig).
+template <int L, int CH, bool TM>
 __global__ __launch_bounds__(256) void k_walk_glb(GlbWalkArgs a)
 {
     constexpr uint32_t kGroups = kWave / L;   // groups per wave = tickets per refill
@@ -1428,7 +1458,7 @@ __global__ __launch_bounds__(256) void k_walk_glb(GlbWalkArgs a)
         if (__ballot(!done) == 0) break;   // no group of the wave has work left
         if (!have) continue;
         const uint64_t myr = philox_u64(w.qid, w.k, w.it, w.s + j, a.seed_lo, a.seed_hi);
-        if (glb_steps<L, CH, 0>(a, w, bloom, gw, epoch, j, myr)) continue;
+        if (glb_steps<L, CH, 0, TM>(a, w, bloom, gw, epoch, j, myr)) continue;
         // the walk is over
         const uint32_t ant = w.v * a.ants + w.k;
         const uint32_t cs = w.cs > kPathCostCap ? kPathCostCap : (uint32_t)w.cs;
@@ -2308,6 +2338,7 @@ struct gmacop_graph {
     uint32_t *gnode = nullptr, *gchoice = nullptr, *gvcity = nullptr;
     uint64_t *gcsum = nullptr, *gmark = nullptr, *gmsum = nullptr;
     uint2 *rev_tw = nullptr;
+    uint4 *sig = nullptr;              // [m] time-dependent signals: head's cycle, green window start and length
     // statistics
     uint64_t *counters = nullptr;         // device [kCounters]
     uint32_t *iter_max = nullptr;         // device [1]
@@ -2342,7 +2373,7 @@ struct gmacop_graph {
         dfree(path); dfree(ant_len); dfree(ant_cost); dfree(gbits); dfree(iter_key); dfree(steps);
         dfree(best_path); dfree(best_len); dfree(best_cost); dfree(od); dfree(counters); dfree(iter_max);
         dfree(lazy); dfree(dep_ind); dfree(touched); dfree(touched_n); dfree(dev_gen);
-        dfree(goal); dfree(goal_work); dfree(goal_ctl); dfree(rev_tw);
+        dfree(goal); dfree(goal_work); dfree(goal_ctl); dfree(rev_tw); dfree(sig);
         dfree(gnode); dfree(gchoice); dfree(gvcity); dfree(gcsum); dfree(gmark); dfree(gmsum);
         glb.release();
         for (auto &t : pending) {
@@ -2505,7 +2536,7 @@ int validate_params(const gmacop_graph *g, const gmacop_params *p, uint32_t nq)
         return fail(GMACOP_E_INVAL, "need tau_min <= tau0 <= tau_max");
     if (p->mode > GMACOP_MODE_GREEDY) return fail(GMACOP_E_INVAL, "unknown mode %u", p->mode);
     if (p->flags & ~(GMACOP_NO_LOAD_UPDATE | GMACOP_DEVICE_PTRS | GMACOP_TIME_KERNELS | GMACOP_HIP_GRAPH |
-                     GMACOP_GOAL_EXACT | GMACOP_RESUME))
+                     GMACOP_GOAL_EXACT | GMACOP_RESUME | GMACOP_SIGNAL_TIMED))
         return fail(GMACOP_E_INVAL, "unknown flags");
     const uint32_t lg = g->max_deg <= 1 ? 0 : bit_length(g->max_deg - 1);
     if ((uint64_t)p->alpha * bit_length(p->tau_max_q16) + 16ull * p->beta + lg > 64)
@@ -2540,6 +2571,7 @@ struct WalkPlan {
     uint32_t road_maxd = 4;               // candidate and in-road bound of k_walk_ldsr
     size_t lds_bytes[kLdsClasses + 1] = {};   // [c]: dynamic LDS of LDS class c's launch, 0 = none
     bool glb = false;              // some city is served by k_walk_glb
+    bool timed = false;            // k_walk_glb costs roads by the time-dependent signal rule
     uint32_t glb_lanes = 4, glb_apb = 0, bloom_log2 = 11, glb_nwords = 0;
     uint32_t glb_blocks = 0;       // resident grid of k_walk_glb (glb_grid)
     size_t glb_lds_bytes = 0;
@@ -2622,7 +2654,12 @@ template <int L, int MAXD>
 int launch_walk_glb(const GlbWalkArgs &wa, const WalkPlan &pl, hipStream_t st)
 {
     constexpr int CH = (MAXD + L - 1) / L;
-    hipLaunchKernelGGL((k_walk_glb<L, CH>), dim3(pl.glb_blocks), dim3(pl.glb_apb * L), pl.glb_lds_bytes, st, wa);
+    if (pl.timed)
+        hipLaunchKernelGGL((k_walk_glb<L, CH, true>), dim3(pl.glb_blocks), dim3(pl.glb_apb * L), pl.glb_lds_bytes, st,
+                           wa);
+    else
+        hipLaunchKernelGGL((k_walk_glb<L, CH, false>), dim3(pl.glb_blocks), dim3(pl.glb_apb * L), pl.glb_lds_bytes,
+                           st, wa);
     HIP_TRY(hipGetLastError());
     return GMACOP_OK;
 }
@@ -2649,17 +2686,17 @@ int launch_walk_glb_any(const GlbWalkArgs &wa, const WalkPlan &pl, hipStream_t s
 }
 
 template <int L, int MAXD>
-const void *glb_kernel()
+const void *glb_kernel(bool tm)
 {
     constexpr int CH = (MAXD + L - 1) / L;
-    return (const void *)k_walk_glb<L, CH>;
+    return tm ? (const void *)k_walk_glb<L, CH, true> : (const void *)k_walk_glb<L, CH, false>;
 }
 
 template <int L>
-const void *glb_kernel_d(uint32_t maxd)
+const void *glb_kernel_d(uint32_t maxd, bool tm)
 {
-    return maxd <= 4 ? glb_kernel<L, 4>() : maxd <= 8 ? glb_kernel<L, 8>() : maxd <= 16 ? glb_kernel<L, 16>()
-                                                                                       : glb_kernel<L, 32>();
+    return maxd <= 4 ? glb_kernel<L, 4>(tm) : maxd <= 8 ? glb_kernel<L, 8>(tm) : maxd <= 16 ? glb_kernel<L, 16>(tm)
+                                                                                          : glb_kernel<L, 32>(tm);
 }
 
 // The persistent grid of k_walk_glb: as many blocks as stay resident on the
@@ -2668,8 +2705,8 @@ const void *glb_kernel_d(uint32_t maxd)
 int glb_grid(int device, WalkPlan &pl, uint64_t NA)
 {
     const uint32_t L = pl.glb_lanes;
-    const void *kern = L == 1 ? glb_kernel_d<1>(pl.maxd) : L == 2 ? glb_kernel_d<2>(pl.maxd)
-                       : L == 4 ? glb_kernel_d<4>(pl.maxd) : glb_kernel_d<8>(pl.maxd);
+    const void *kern = L == 1 ? glb_kernel_d<1>(pl.maxd, pl.timed) : L == 2 ? glb_kernel_d<2>(pl.maxd, pl.timed)
+                       : L == 4 ? glb_kernel_d<4>(pl.maxd, pl.timed) : glb_kernel_d<8>(pl.maxd, pl.timed);
     int nb = 0, cus = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, (int)(pl.glb_apb * L), pl.glb_lds_bytes));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
@@ -2705,8 +2742,11 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     WalkPlan pl;
     pl.maxd = g->max_deg <= 4 ? 4 : g->max_deg <= 8 ? 8 : g->max_deg <= 16 ? 16 : 32;
     const char *kind = getenv("GMACOP_WALK_KERNEL");
-    const bool force_global = kind && strcmp(kind, "global") == 0;
+    // time-dependent signals make a road's weight depend on the ant's clock: only the global walker
+    // computes weights per ant
+    const bool force_global = (kind && strcmp(kind, "global") == 0) || (p->flags & GMACOP_SIGNAL_TIMED);
     pl.legacy = (kind && strcmp(kind, "legacy") == 0) || g->n >= (1u << 24);
+    pl.timed = (p->flags & GMACOP_SIGNAL_TIMED) != 0;
     pl.city_class.assign(g->n_inst, 0);
     if (pl.legacy) return pl;
     pl.lds_lanes = lanes_or(env_u32("GMACOP_WALK_LANES", 4), 4);
@@ -2892,6 +2932,28 @@ extern "C" int gmacop_graph_create(const gmacop_graph_desc *d, gmacop_graph **ou
         delete g;
         return fail(GMACOP_E_DEVICE, "hipMemset of counters failed");
     }
+    {   // green windows of the time-dependent signals: an intersection's approaches take their greens in turn,
+        // in road order, each for floor(C * green / 1000) ms, the first from time 0
+        std::vector<uint4> sig(m);
+        std::vector<uint64_t> acc(n, 0);
+        for (uint32_t e = 0; e < m; ++e) {
+            const uint32_t v = d->col[e];
+            const uint64_t C = d->cycle_ms[v];
+            if (!C) {
+                sig[e] = make_uint4(0, 0, 0, 0);
+                continue;
+            }
+            const uint64_t len = C * d->green_pm[e] / 1000u;
+            sig[e] = make_uint4((uint32_t)C, (uint32_t)(acc[v] % C), (uint32_t)len, 0);
+            acc[v] += len;
+        }
+        if ((rc = upload(&g->sig, sig.data(), m))) {
+            std::string keep = t_err;
+            delete g;
+            t_err = keep;
+            return rc;
+        }
+    }
     {   // the mean free-flow road time, the band width scale of the exact goal search
         long double sum = 0;
         for (uint32_t e = 0; e < m; ++e) {
@@ -3041,8 +3103,10 @@ int route_check(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_p
     }
     HIP_TRY(hipSetDevice(g->device));
     *plan = plan_walk(g, p, g->max_lds);
-    if (plan->legacy && (p->flags & GMACOP_GOAL_EXACT))
-        return fail(GMACOP_E_UNSUPPORTED, "the exact goal term needs a graph under 2^24 nodes");
+    if (plan->legacy && (p->flags & (GMACOP_GOAL_EXACT | GMACOP_SIGNAL_TIMED)))
+        return fail(GMACOP_E_UNSUPPORTED, "the exact goal term and timed signals need a graph under 2^24 nodes");
+    if (p->mode == GMACOP_MODE_GREEDY && (p->flags & GMACOP_SIGNAL_TIMED))
+        return fail(GMACOP_E_UNSUPPORTED, "GMACOP_MODE_GREEDY does not take GMACOP_SIGNAL_TIMED");
     if (!plan->legacy && plan->glb && (rc = glb_grid(g->device, *plan, (uint64_t)nq * p->ants))) return rc;
     return GMACOP_OK;
 }
@@ -3189,7 +3253,9 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
     uint32_t *mir = (!plan.legacy && plan.glb) ? (uint32_t *)g->rec32 : nullptr;   // the global walker's records
     EdgeInitArgs ia{g->m, p->tau0_q16, p->t_max_ms, resume, g->col, g->len_dm, g->cycle, g->base_load, g->speed, g->green,
                     g->t0, g->wf, g->tau, g->load, g->cnt, g->dep, mir};
-    CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost, mir};
+    const uint32_t timed = (p->flags & GMACOP_SIGNAL_TIMED) ? 1u : 0u;
+    CostArgs ca{g->n, p->theta, p->th_max, g->rev_ptr, g->rev_edge, g->cycle, g->load, g->t0, g->wf, g->cost, mir,
+                timed};
     PherView pv{};
     pv.dense = indep ? nullptr : g->tau;
     pv.lazy = w.lazy;
@@ -3234,6 +3300,7 @@ int route_run(gmacop_graph *g, const gmacop_od *q, uint32_t nq, const gmacop_par
     ga.ant_cost = w.ant_cost; ga.iter_key = w.iter_key; ga.steps = steps;
     ga.counters = g->counters; ga.iter_max = g->iter_max;
     ga.goal = la.goal; ga.goal_stride = gp.stride;
+    ga.sig = timed ? g->sig : nullptr; ga.t_max = p->t_max_ms;
     const GlbListArgs gla{od, w.vclass, g->row_ptr, g->node_lo, g->x, g->y, nq, p->ants, wa.kgoal,
                           w.gvrec, w.gveh, w.gctl, w.gvlen, w.ant_len, w.ant_cost, la.goal, gp.stride};
     GoalArgs goa{};
@@ -3937,6 +4004,8 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
     pp.mode = GMACOP_MODE_INDEPENDENT;
     if (pp.flags & GMACOP_GOAL_EXACT)   // switched off: a run on the 1M-node city faulted, cause not found
         return fail(GMACOP_E_UNSUPPORTED, "the router does not take GMACOP_GOAL_EXACT");
+    if (pp.flags & GMACOP_SIGNAL_TIMED)
+        return fail(GMACOP_E_UNSUPPORTED, "the router does not take GMACOP_SIGNAL_TIMED");
     pp.flags &= GMACOP_TIME_KERNELS;   // loads are frozen; results go to host buffers
     int rc = validate_params(g, &pp, 1);
     if (rc) return rc;
@@ -4026,7 +4095,7 @@ extern "C" int gmacop_server_create(gmacop_graph *g, const gmacop_params *p, uin
                     s->t0, s->wf, s->tau, s->load, s->cnt, s->dep_shared, (uint32_t *)s->rec32};
     hipLaunchKernelGGL(k_init_edges, dim3(blocks_for(m, 256)), dim3(256), 0, 0, ia);
     CostArgs ca{g->n, pp.theta, pp.th_max, g->rev_ptr, g->rev_edge, g->cycle, s->load, s->t0, s->wf, s->cost,
-                (uint32_t *)s->rec32};
+                (uint32_t *)s->rec32, 0u};
     hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, 0, ca);
     const hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -4291,7 +4360,7 @@ extern "C" int gmacop_server_set_base_load(gmacop_server *s, const uint32_t *bas
     // the router's loads become the new sensed loads, and its cost table follows them
     HIP_TRY(hipMemcpyAsync(s->load, base_load, sizeof(uint32_t) * g->m, hipMemcpyHostToDevice, st));
     CostArgs ca{g->n, s->p.theta, s->p.th_max, g->rev_ptr, g->rev_edge, g->cycle, s->load, s->t0, s->wf, s->cost,
-                (uint32_t *)s->rec32};
+                (uint32_t *)s->rec32, 0u};
     hipLaunchKernelGGL(k_cost, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, ca);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));

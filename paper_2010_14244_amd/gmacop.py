@@ -33,6 +33,7 @@ TIME_KERNELS = 4
 HIP_GRAPH = 8
 GOAL_EXACT = 16
 RESUME = 32
+SIGNAL_TIMED = 64
 
 EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_route_batch_noalloc", "gmacop_state_get", "gmacop_state_set",
             "gmacop_set_base_load", "gmacop_server_set_base_load", "gmacop_vehicle_tau_get",
