@@ -2708,6 +2708,8 @@ int glb_grid(int device, WalkPlan &pl, uint64_t NA)
     const void *kern = L == 1 ? glb_kernel_d<1>(pl.maxd, pl.timed) : L == 2 ? glb_kernel_d<2>(pl.maxd, pl.timed)
                        : L == 4 ? glb_kernel_d<4>(pl.maxd, pl.timed) : glb_kernel_d<8>(pl.maxd, pl.timed);
     int nb = 0, cus = 0;
+    if (pl.glb_lds_bytes > 65536)   // Bloom filters beyond the default dynamic-LDS limit
+        HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.glb_lds_bytes));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, (int)(pl.glb_apb * L), pl.glb_lds_bytes));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
     uint64_t blocks = (uint64_t)std::max(nb, 1) * (uint64_t)std::max(cus, 1);
@@ -2815,7 +2817,9 @@ WalkPlan plan_walk(const gmacop_graph *g, const gmacop_params *p, int max_lds)
     pl.glb_lanes = lanes_or(env_u32("GMACOP_GLB_LANES", 4), 4);
     pl.glb_apb = 256 / pl.glb_lanes;
     pl.bloom_log2 = std::min<uint32_t>(16, std::max<uint32_t>(8, env_u32("GMACOP_BLOOM_LOG2", 11)));
-    pl.glb_lds_bytes = (size_t)pl.glb_apb * ((1u << (pl.bloom_log2 - 5)) | 1u) * 4;
+    auto bloom_bytes = [&] { return (size_t)pl.glb_apb * ((1u << (pl.bloom_log2 - 5)) | 1u) * 4; };
+    while (pl.bloom_log2 > 8 && bloom_bytes() > (size_t)max_lds) --pl.bloom_log2;   // within a block's LDS
+    pl.glb_lds_bytes = bloom_bytes();
     pl.glb_nwords = (glb_nodes + 31) / 32;
     return pl;
 }

@@ -6,7 +6,8 @@ workload generators; the GPU library is never involved.
 
 Stores, per workload: selections, per-vehicle best cost and length, and
 SHA-256 digests of the best routes (each row truncated to its length), the
-final pheromone and the final loads.
+final pheromone (independent mode: every vehicle's row, in vehicle order)
+and the final loads.
 """
 import hashlib
 import json
@@ -36,20 +37,31 @@ def digest(a) -> str:
     return hashlib.sha256(np.ascontiguousarray(a, dtype=np.uint32).tobytes()).hexdigest()
 
 
-WORKLOADS = {
-    "grid32": lambda: workloads.grid32(),
-    "planar100k": lambda: workloads.planar100k(),
-    "multicity": lambda: workloads.multi_city(),
+def with_params(w, **kw):
+    return workloads.Workload(w.name, w.graph, w.vehicles, dict(w.params, **kw))
+
+
+WORKLOADS = {   # name: (generator call as stored, workload)
+    "grid32": ("workloads.grid32()", lambda: workloads.grid32()),
+    "planar100k": ("workloads.planar100k()", lambda: workloads.planar100k()),
+    "multicity": ("workloads.multi_city()", lambda: workloads.multi_city()),
+    # independent mode (private pheromone per vehicle, frozen loads), 256 vehicles
+    "planar100k_indep256": ("workloads.planar100k(vehicles=256), mode=1",
+                            lambda: with_params(workloads.planar100k(vehicles=256), mode=1)),
+    # the exact goal term (flag 16) on the 64 packed cities
+    "multicity_exact": ("workloads.multi_city(), flags=16",
+                        lambda: with_params(workloads.multi_city(), flags=oracle.FLAG_GOAL_EXACT)),
 }
 
 
 def main(names):
     for name in names:
-        w = WORKLOADS[name]()
+        gen, make = WORKLOADS[name]
+        w = make()
         t = time.time()
         r = oracle.route(w.graph, w.vehicles, w.params)
         dt = time.time() - t
-        out = dict(workload=w.name, generator=f"workloads.{name}()", params=w.params,
+        out = dict(workload=w.name, generator=gen, params=w.params,
                    steps_total=r["steps_total"], cost_ms=r["cost_ms"].tolist(), path_len=r["path_len"].tolist(),
                    routes_sha256=digest_routes(r["path_edges"], r["path_len"]),
                    tau_sha256=digest(r["tau"]), load_sha256=digest(r["load"]),

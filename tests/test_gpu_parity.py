@@ -262,25 +262,50 @@ def _digest_routes(path_edges, path_len):
     return h.hexdigest()
 
 
-@pytest.mark.parametrize("name", ["grid32", "planar100k", "multicity"])
+def _full_workload(name):
+    from workloads import Workload, multi_city, planar100k
+    if name == "planar100k_indep256":
+        w = planar100k(vehicles=256)
+        return Workload(w.name, w.graph, w.vehicles, dict(w.params, mode=gmacop.MODE_INDEPENDENT))
+    if name == "multicity_exact":
+        w = multi_city()
+        return Workload(w.name, w.graph, w.vehicles, dict(w.params, flags=gmacop.GOAL_EXACT))
+    return {"grid32": grid32, "planar100k": planar100k, "multicity": multi_city}[name]()
+
+
+@pytest.mark.parametrize("name", ["grid32", "planar100k", "multicity", "planar100k_indep256", "multicity_exact"])
 def test_full_workload_against_stored_oracle_results(name):
     """Full-size workloads (32x32 grid: 256 vehicles x 128 ants x 100 it;
-    100k-node planar city: 4096 x 64 x 50; 64 packed cities: 10466 x 32 x 30)
-    against the oracle's results stored by tests/golden/make_expected.py."""
-    from workloads import multi_city, planar100k
+    100k-node planar city: 4096 x 64 x 50, and 256 vehicles in independent
+    mode; 64 packed cities: 10466 x 32 x 30, also with the exact goal term)
+    against the oracle's results stored by tests/golden/make_expected.py.
+    Independent mode: every vehicle's final pheromone row, in vehicle order."""
     path = os.path.join(HERE, "golden", f"{name}_expected.json")
     with open(path) as f:
         want = json.load(f)
-    w = {"grid32": grid32, "planar100k": planar100k, "multicity": multi_city}[name]()
+    w = _full_workload(name)
     assert w.name == want["workload"] and w.params == want["params"]
-    announce(w.name)
-    got = run_gpu(w.graph, w.vehicles, w.params)
-    assert got["steps_total"] == want["steps_total"]
-    assert got["cost_ms"].tolist() == want["cost_ms"]
-    assert got["path_len"].tolist() == want["path_len"]
-    assert _digest_routes(got["path_edges"], got["path_len"]) == want["routes_sha256"]
-    assert hashlib.sha256(got["tau"].tobytes()).hexdigest() == want["tau_sha256"]
-    assert hashlib.sha256(got["load"].tobytes()).hexdigest() == want["load_sha256"]
+    announce(f"{name}: {w.name}")
+    G = gmacop.gmacop_graph_create(w.graph)
+    try:
+        got = gmacop.gmacop_route_batch(G, w.vehicles, w.params)
+        assert got["steps_total"] == want["steps_total"]
+        assert got["cost_ms"].tolist() == want["cost_ms"]
+        assert got["path_len"].tolist() == want["path_len"]
+        assert _digest_routes(got["path_edges"], got["path_len"]) == want["routes_sha256"]
+        if w.params["mode"] == gmacop.MODE_SHARED:
+            tau, load = gmacop.gmacop_state_get(G)
+            assert hashlib.sha256(tau.tobytes()).hexdigest() == want["tau_sha256"]
+            assert hashlib.sha256(load.tobytes()).hexdigest() == want["load_sha256"]
+        else:
+            h = hashlib.sha256()
+            for v in range(len(w.vehicles)):
+                h.update(np.ascontiguousarray(gmacop.gmacop_vehicle_tau_get(G, v), np.uint32).tobytes())
+            assert h.hexdigest() == want["tau_sha256"]
+            assert hashlib.sha256(np.ascontiguousarray(w.graph.base_load, np.uint32).tobytes()).hexdigest() \
+                == want["load_sha256"]        # loads stay frozen
+    finally:
+        gmacop.gmacop_release(G)
 
 @pytest.mark.parametrize("kernel,lanes,bloom,variant", [
     ("legacy", 1, 11, ""), ("global", 1, 11, ""), ("global", 2, 11, ""), ("global", 4, 11, ""),
