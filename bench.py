@@ -34,30 +34,86 @@ BYTES_PER_SELECTION = 12
 BYTES_PER_CANDIDATE = 20
 BYTES_PER_DEPOSIT_ROAD = 12
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_14244_amd", "csrc", "gmacop.hip")
+KERNEL_LIBRARY = os.path.join(ROOT, "paper_2010_14244_amd", "libgmacop.so")
+LLVM_BIN = "/opt/rocm/llvm/bin"
 # walker kinds of the library's statistics: (stats kernel key, stats walker key, kernel names)
 WALKER_KINDS = {"lds": ("walk_lds", "lds", "k_walk_ldsr / k_walk_lds"), "glb": ("walk_glb", "glb", "k_walk_glb")}
 
 
-def source_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_isa_hash(lib_path, symbol_re):
+    """SHA-256 prefix of one kernel's gfx950 machine code in a built library:
+    the code object is taken from the library's offload bundle, disassembled
+    with llvm-objdump, and the instructions of the first symbol matching
+    `symbol_re` are hashed as text, with the offsets of the loads from the
+    kernel-argument block masked (adding an argument moves them; what the
+    kernel does is unchanged).  None when the tools or the kernel are missing."""
+    import re
+    import struct
+    import subprocess
+    import tempfile
+    try:
+        sec = subprocess.run([os.path.join(LLVM_BIN, "llvm-readelf"), "-S", "-W", lib_path],
+                             capture_output=True, text=True, check=True).stdout
+        off = size = None
+        for line in sec.splitlines():
+            f = line.replace("[ ", "[").split()
+            if ".hip_fatbin" in f:
+                i = f.index(".hip_fatbin")
+                off, size = int(f[i + 3], 16), int(f[i + 4], 16)
+        if off is None:
+            return None
+        with open(lib_path, "rb") as fh:
+            fh.seek(off)
+            b = fh.read(size)
+        if b[:24] != b"__CLANG_OFFLOAD_BUNDLE__":
+            return None
+        code, p = None, 32
+        for _ in range(struct.unpack_from("<Q", b, 24)[0]):
+            o, n, tl = struct.unpack_from("<QQQ", b, p)
+            if "gfx950" in b[p + 24:p + 24 + tl].decode():
+                code = b[o:o + n]
+            p += 24 + tl
+        if code is None:
+            return None
+        with tempfile.NamedTemporaryFile(suffix=".co") as tf:
+            tf.write(code)
+            tf.flush()
+            dis = subprocess.run([os.path.join(LLVM_BIN, "llvm-objdump"), "-d", tf.name],
+                                 capture_output=True, text=True, check=True).stdout
+    except (OSError, subprocess.CalledProcessError, ValueError, struct.error, UnicodeDecodeError):
+        return None
+    sym, body = re.compile(symbol_re), None
+    kernarg = re.compile(r"^(s_load_\w+\s+[^,]+,\s*s\[0:1\],\s*)0x[0-9a-f]+$")
+    for line in dis.splitlines():
+        if line.endswith(">:"):
+            if body is not None:
+                break
+            if sym.search(line):
+                body = []
+            continue
+        if body is not None:
+            t = line.split("//")[0].strip()
+            if t:
+                body.append(kernarg.sub(r"\1OFF", t))
+    if not body:
+        return None
+    return hashlib.sha256("\n".join(body).encode()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the committed PMC
     profile (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel
-    calibration), or None when there is none or the kernel source has changed
-    since the counters were taken."""
+    calibration), or None when there is none or the kernel's machine code in
+    the built library differs from the one the counters were taken on."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     try:
         vals = {}
         with open(path) as f:
             for line in f:
-                if ":" in line and line.split(":")[0].strip().startswith(("pmc_", "source_sha256")):
+                if ":" in line and line.split(":")[0].strip().startswith(("pmc_", "kernel_isa", "kernel_symbol")):
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
-        if vals.get("source_sha256_prefix") != source_hash():
+        if kernel_isa_hash(KERNEL_LIBRARY, vals["kernel_symbol_re"]) != vals["kernel_isa_sha256_prefix"]:
             return None
         return (float(vals["pmc_walk_fetch_kib"]) * float(vals["pmc_fetch_scale"]) +
                 float(vals["pmc_walk_write_kib"]) * float(vals["pmc_write_scale"])) * 1024.0
@@ -282,7 +338,13 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the plain-per-query vs batched comparison (independent mode)")
     ap.add_argument("--forms-vehicles", type=int, default=512, help="plain vs batched: the first this many vehicles")
+    ap.add_argument("--kernel-isa-hash", nargs=2, metavar=("LIBRARY", "SYMBOL_RE"),
+                    help="print the machine-code hash of a kernel in a built library (as the profiles record it) "
+                         "and exit")
     args = ap.parse_args()
+    if args.kernel_isa_hash:
+        print(kernel_isa_hash(*args.kernel_isa_hash))
+        return
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is designed but not implemented)", file=sys.stderr)

@@ -90,3 +90,24 @@ def test_null_arguments(L):
     assert L.gmacop_route_batch(None, None, 0, None, None, None) == gmacop.E_INVAL
     L.gmacop_release(None)    # NULL-safe
     assert L.gmacop_state_get(None, None, None, None) == gmacop.E_INVAL
+
+
+def test_kernel_machine_code_hash_of_the_built_library():
+    """bench.py decides whether a profile's counters still hold from a hash
+    of the kernel's gfx950 instructions in the built library: every walker
+    kind is found, instantiations differ, and a missing kernel gives None."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    if not os.path.exists(os.path.join(bench.LLVM_BIN, "llvm-objdump")):
+        pytest.skip("ROCm LLVM tools not installed")
+    lib = gmacop.library_path()
+    h42 = bench.kernel_isa_hash(lib, r"k_walk_glbILi4ELi2ELb0EE")
+    h42t = bench.kernel_isa_hash(lib, r"k_walk_glbILi4ELi2ELb1EE")
+    h41 = bench.kernel_isa_hash(lib, r"k_walk_glbILi4ELi1ELb0EE")
+    hl = bench.kernel_isa_hash(lib, r"k_walk_ldsrILi4ELi1EEE")
+    for h in (h42, h42t, h41, hl):
+        assert h is not None and re.fullmatch(r"[0-9a-f]{16}", h)
+    assert len({h42, h42t, h41, hl}) == 4
+    assert bench.kernel_isa_hash(lib, r"no_such_kernel_name") is None
+    assert bench.kernel_isa_hash(os.path.join(ROOT, "bench.py"), r"k_walk_glb") is None
