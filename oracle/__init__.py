@@ -98,6 +98,8 @@ def lib():
         L.orc_walk.restype = C.c_int
         L.orc_route.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_route.restype = C.c_int
+        L.orc_simulate.argtypes = [vp, vp, vp, u32, vp, vp, u32, u32, u32, vp, vp, vp]
+        L.orc_simulate.restype = C.c_int
         _lib = L
     return _lib
 
@@ -295,3 +297,30 @@ def greedy(g, veh, p: dict) -> dict:
         raise ValueError("oracle rejected input", rc)
     return dict(path_edges=path, path_len=plen, cost_ms=cost, steps_total=int(steps.value), marker=mark)
 
+
+
+def simulate(g, p: dict, path_edges, path_len, speed_kmh, *, tick_ms: int = 1000, max_ticks: int = 100000) -> dict:
+    """Traffic simulation of the vehicles' trips along their routes (Section
+    5; orc_simulate): arrival_ms and wait_ms per vehicle (arrival 2^32-1: no
+    route or not arrived), ticks run, and over the vehicles that arrived the
+    mean and the last arrival time (the overall travel time, ms)."""
+    gr, pp = _GraphRef(g), _params(p)
+    path = np.ascontiguousarray(path_edges, np.uint32)
+    if path.ndim != 2:
+        raise ValueError("path_edges must be [vehicles, stride]")
+    V, S = path.shape
+    plen = np.ascontiguousarray(path_len, np.uint32)
+    spd = np.ascontiguousarray(speed_kmh, np.uint32)
+    if plen.shape != (V,) or spd.shape != (V,):
+        raise ValueError("path_len and speed_kmh need one entry per vehicle")
+    arr = np.zeros(V, np.uint32)
+    wait = np.zeros(V, np.uint32)
+    ticks = C.c_uint32(0)
+    rc = lib().orc_simulate(C.byref(gr.s), C.byref(pp), _ptr(path), S, _ptr(plen), _ptr(spd), V, int(tick_ms),
+                            int(max_ticks), _ptr(arr), _ptr(wait), C.byref(ticks))
+    if rc != 0:
+        raise ValueError("oracle rejected input", rc)
+    done = arr != 0xFFFFFFFF
+    return dict(arrival_ms=arr, wait_ms=wait, ticks=int(ticks.value), arrived=int(done.sum()),
+                mean_ms=float(arr[done].astype(np.float64).mean()) if done.any() else None,
+                last_ms=int(arr[done].max()) if done.any() else None)

@@ -796,3 +796,122 @@ int orc_greedy(const orc_graph *g, const uint32_t *src, const uint32_t *dst, uin
     return 0;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* Traffic simulation of the vehicles' trips (Section 5: vehicles drive     */
+/* their routes at their own speeds, the preemptive signal rule of Fig. 3   */
+/* applied at every signal they meet; the overall travel time).             */
+/* Synchronous ticks of tick_ms; every vehicle with a route departs at time */
+/* 0 from the start of its first road.  At tick k (t = k * tick_ms), from   */
+/* the state at the tick's start, with N_e the vehicles on road e and Q_e   */
+/* those stopped at its end:                                                */
+/*  - a vehicle stopped at the end of e passes the head's signal when it is */
+/*    green for e or when it has waited T_max there, and enters the next    */
+/*    road of its route (the pass takes the tick); else it waits the tick;  */
+/*  - green for e: the head has no signal, or t lies in e's green window    */
+/*    (orc_signal_windows), or Q_e is the largest non-empty queue among the */
+/*    head's approaches (ties: the lowest road id), or Q_e > Th_max;        */
+/*  - a moving vehicle covers min(its speed, the road's) km/h for tick_ms,  */
+/*    slowed to max(1, floor(speed * theta / N_e)) when N_e > theta; at the */
+/*    end of its road it stops, or, at the end of its route, arrives at     */
+/*    t + tick_ms.                                                          */
+/* Positions count 1/360 dm, so v km/h covers v * tick_ms of them a tick.   */
+/* ------------------------------------------------------------------------ */
+int orc_simulate(const orc_graph *g, const orc_params *p, const uint32_t *path, uint32_t stride,
+                 const uint32_t *path_len, const uint32_t *speed_kmh, uint32_t nv, uint32_t tick_ms,
+                 uint32_t max_ticks, uint32_t *arrival_ms, uint32_t *wait_ms, uint32_t *ticks_run)
+{
+    if (tick_ms == 0 || p->theta == 0) return -1;
+    uint32_t *tail = (uint32_t *)malloc(sizeof(uint32_t) * (g->m ? g->m : 1));
+    for (uint32_t v = 0; v < g->n; ++v)
+        for (uint32_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e) tail[e] = v;
+    for (uint32_t i = 0; i < nv; ++i) {   /* routes: roads in range, each starting where the last ended */
+        const uint32_t L = path_len[i];
+        int ok = L <= stride && (L == 0 || speed_kmh[i] > 0);
+        for (uint32_t r = 0; ok && r < L; ++r) {
+            const uint32_t e = path[(size_t)i * stride + r];
+            ok = e < g->m && (r == 0 || tail[e] == g->col[path[(size_t)i * stride + r - 1]]);
+        }
+        if (!ok) {
+            free(tail);
+            return -1;
+        }
+    }
+    uint32_t *ws = (uint32_t *)malloc(sizeof(uint32_t) * (g->m ? g->m : 1));
+    uint32_t *wg = (uint32_t *)malloc(sizeof(uint32_t) * (g->m ? g->m : 1));
+    orc_signal_windows(g, ws, wg);
+    uint32_t *N = (uint32_t *)calloc(g->m ? g->m : 1, sizeof(uint32_t));
+    uint32_t *Q = (uint32_t *)calloc(g->m ? g->m : 1, sizeof(uint32_t));
+    uint32_t *best = (uint32_t *)malloc(sizeof(uint32_t) * (g->n ? g->n : 1));
+    uint32_t *road = (uint32_t *)calloc(nv ? nv : 1, sizeof(uint32_t));      /* index into the route */
+    uint64_t *pos = (uint64_t *)calloc(nv ? nv : 1, sizeof(uint64_t));      /* 1/360 dm from the road's start */
+    uint8_t *stopped = (uint8_t *)calloc(nv ? nv : 1, 1);
+    uint8_t *active = (uint8_t *)calloc(nv ? nv : 1, 1);
+    uint32_t *waited = (uint32_t *)calloc(nv ? nv : 1, sizeof(uint32_t));   /* at the current stop */
+    uint32_t remaining = 0;
+    for (uint32_t i = 0; i < nv; ++i) {
+        arrival_ms[i] = U32_MAX;
+        wait_ms[i] = 0;
+        active[i] = path_len[i] > 0;
+        remaining += active[i];
+    }
+    uint32_t k = 0;
+    for (; k < max_ticks && remaining; ++k) {
+        const uint64_t t = (uint64_t)k * tick_ms;
+        memset(N, 0, sizeof(uint32_t) * g->m);
+        memset(Q, 0, sizeof(uint32_t) * g->m);
+        for (uint32_t i = 0; i < nv; ++i)
+            if (active[i]) {
+                const uint32_t e = path[(size_t)i * stride + road[i]];
+                N[e]++;
+                Q[e] += stopped[i];
+            }
+        for (uint32_t v = 0; v < g->n; ++v) best[v] = U32_MAX;
+        for (uint32_t e = 0; e < g->m; ++e) {   /* ascending e: the first of equal queues wins */
+            const uint32_t v = g->col[e];
+            if (Q[e] > 0 && (best[v] == U32_MAX || Q[e] > Q[best[v]])) best[v] = e;
+        }
+        for (uint32_t i = 0; i < nv; ++i) {
+            if (!active[i]) continue;
+            const uint32_t *route = path + (size_t)i * stride;
+            const uint32_t e = route[road[i]], head = g->col[e];
+            if (stopped[i]) {
+                const uint64_t C = g->cycle_ms[head];
+                int green = C == 0 || best[head] == e || Q[e] > p->th_max;
+                if (!green) green = ((t % C + C - ws[e]) % C) < wg[e];
+                if (green || waited[i] >= p->t_max_ms) {
+                    road[i]++;
+                    pos[i] = 0;
+                    stopped[i] = 0;
+                    waited[i] = 0;
+                } else {
+                    waited[i] += tick_ms;
+                    wait_ms[i] += tick_ms;
+                }
+                continue;
+            }
+            uint64_t v = speed_kmh[i] < g->speed_kmh[e] ? speed_kmh[i] : g->speed_kmh[e];
+            if (N[e] > p->theta) {
+                v = v * p->theta / N[e];
+                if (v == 0) v = 1;
+            }
+            pos[i] += v * tick_ms;
+            if (pos[i] >= (uint64_t)g->len_dm[e] * 360u) {
+                if (road[i] + 1 == path_len[i]) {
+                    const uint64_t a = t + tick_ms;
+                    arrival_ms[i] = a > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)a;
+                    active[i] = 0;
+                    remaining--;
+                } else {
+                    pos[i] = (uint64_t)g->len_dm[e] * 360u;
+                    stopped[i] = 1;
+                    waited[i] = 0;
+                }
+            }
+        }
+    }
+    *ticks_run = k;
+    free(tail); free(ws); free(wg); free(N); free(Q); free(best); free(road); free(pos); free(stopped);
+    free(active); free(waited);
+    return 0;
+}

@@ -115,6 +115,17 @@ int orc_greedy(const orc_graph *g, const uint32_t *src, const uint32_t *dst, uin
                const uint32_t *city_of_node, uint32_t *path_edges, uint32_t *path_len, uint32_t *cost_ms,
                uint64_t *steps_total, uint32_t *marker_out);
 
+/* Traffic simulation of the vehicles' trips along their routes (Section 5):
+ * synchronous ticks of tick_ms, congestion slowing a road above theta
+ * vehicles, the preemptive signal rule at every signal (green window, longest
+ * queue, queue above Th_max, or a wait of T_max).  path: [nv][stride] roads,
+ * path_len[nv] (0 = no route), speed_kmh[nv].  Outputs per vehicle: arrival
+ * time in ms (UINT32_MAX = no route, or not arrived within max_ticks) and total
+ * signal wait; the ticks run.  Returns 0, or -1 on invalid input. */
+int orc_simulate(const orc_graph *g, const orc_params *p, const uint32_t *path, uint32_t stride,
+                 const uint32_t *path_len, const uint32_t *speed_kmh, uint32_t nv, uint32_t tick_ms,
+                 uint32_t max_ticks, uint32_t *arrival_ms, uint32_t *wait_ms, uint32_t *ticks_run);
+
 #ifdef __cplusplus
 }
 #endif

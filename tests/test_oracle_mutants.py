@@ -66,6 +66,15 @@ MUTANTS = {
     "timed_entry_instead_of_arrival": ("const uint64_t q = ((clock + travel) % C + C - tm->wstart[e]) % C;",
                                        "const uint64_t q = (clock % C + C - tm->wstart[e]) % C;"),
     "timed_preemption_ignored": ("if (C && !tm->pre[e]) {", "if (C) {"),
+    "sim_queue_tie_to_last": ("if (Q[e] > 0 && (best[v] == U32_MAX || Q[e] > Q[best[v]])) best[v] = e;",
+                              "if (Q[e] > 0 && (best[v] == U32_MAX || Q[e] >= Q[best[v]])) best[v] = e;"),
+    "sim_window_ignored": ("if (!green) green = ((t % C + C - ws[e]) % C) < wg[e];", ""),
+    "sim_no_t_max": ("if (green || waited[i] >= p->t_max_ms) {", "if (green) {"),
+    "sim_no_congestion": ("if (N[e] > p->theta) {\n                v = v * p->theta / N[e];",
+                          "if (0) {\n                v = v * p->theta / N[e];"),
+    "sim_arrival_at_tick_start": ("const uint64_t a = t + tick_ms;", "const uint64_t a = t;"),
+    "sim_own_speed_only": ("uint64_t v = speed_kmh[i] < g->speed_kmh[e] ? speed_kmh[i] : g->speed_kmh[e];",
+                           "uint64_t v = speed_kmh[i];"),
     "apply_after_load_update": (
         """            for (uint32_t e = 0; e < m; ++e) tau[e] = orc_apply_tau(p, tau[e], dep[e], load[e]);
             if (!(p->flags & ORC_FLAG_NO_LOAD_UPDATE)) {

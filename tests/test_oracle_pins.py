@@ -1028,3 +1028,130 @@ def test_timed_route_costs_follow_the_clock(orc):
         for e in res["path_edges"][v, :L].tolist():
             clock += orc.timed_cost(g, p, e, clock)
         assert res["cost_ms"][v] == clock
+
+
+# ---------------------------------------------------------------------------
+# traffic simulation of the trips (Section 5: routes driven through the
+# preemptive signals; overall travel time)
+# ---------------------------------------------------------------------------
+
+def merge_graph(green_e0, green_e1, cycle=100000, speed=36):
+    """Roads e0 = 0->2, e1 = 1->2, e2 = 2->3 (road ids in that order), 1000 dm
+    each; node 2 signalised with the given greens (per mille) of a 100 s cycle,
+    so e0's window is [0, C*g0/1000) and e1's follows it."""
+    return from_edges(4, [0, 1, 2], [2, 2, 3], len_dm=1000, speed_kmh=speed,
+                      green_pm=[green_e0, green_e1, 1000], cycle_ms=[0, 0, cycle, 0])
+
+
+def test_sim_one_road_by_hand(orc):
+    """1000 dm at 36 km/h: 360000 units of 1/360 dm, 36000 a tick: 10 ticks;
+    at 30 km/h (the vehicle slower than the road) 12; 1001 dm at 36 km/h 11."""
+    g = from_edges(2, [0], [1], len_dm=[1000], speed_kmh=36)
+    p = default_params()
+    assert orc.simulate(g, p, np.array([[0]]), [1], [36])["arrival_ms"].tolist() == [10000]
+    assert orc.simulate(g, p, np.array([[0]]), [1], [30])["arrival_ms"].tolist() == [12000]
+    assert orc.simulate(g, p, np.array([[0]]), [1], [90])["arrival_ms"].tolist() == [10000]   # the road's limit
+    g1 = from_edges(2, [0], [1], len_dm=[1001], speed_kmh=36)
+    r = orc.simulate(g1, p, np.array([[0]]), [1], [36])
+    assert r["arrival_ms"].tolist() == [11000] and r["ticks"] == 11 and r["last_ms"] == 11000
+
+
+def test_sim_unsignalised_crossing_takes_a_tick(orc):
+    g = from_edges(3, [0, 1], [1, 2], len_dm=1000, speed_kmh=36)
+    r = orc.simulate(g, default_params(), np.array([[0, 1]]), [2], [36])
+    assert r["arrival_ms"].tolist() == [21000] and r["wait_ms"].tolist() == [0]
+
+
+def test_sim_longest_queue_and_window(orc):
+    """A on e0 and B1, B2 on e1 reach the stop line together (tick 10).
+    e0's window [0, 10 s) has closed and B's queue (2) is the longest, so A
+    waits one tick, then holds the only queue and passes: 22 s against 21 s.
+    With Th_max = 0, A's queue of 1 exceeds it: green at once.  With the
+    windows swapped (e0 [0, 90 s)), A passes in its window although B's queue
+    is longer."""
+    paths = np.array([[0, 2], [1, 2], [1, 2]])
+    p = default_params()
+    r = orc.simulate(merge_graph(100, 900), p, paths, [2, 2, 2], [36, 36, 36])
+    assert r["arrival_ms"].tolist() == [22000, 21000, 21000] and r["wait_ms"].tolist() == [1000, 0, 0]
+    r = orc.simulate(merge_graph(100, 900), dict(p, th_max=0), paths, [2, 2, 2], [36, 36, 36])
+    assert r["arrival_ms"].tolist() == [21000, 21000, 21000]
+    r = orc.simulate(merge_graph(900, 100), p, paths, [2, 2, 2], [36, 36, 36])
+    assert r["arrival_ms"].tolist() == [21000, 21000, 21000] and r["mean_ms"] == 21000.0
+
+
+def test_sim_t_max_guard(orc):
+    """B1..B4 on e0 reach the stop line at ticks 10, 11, 12, 13 (36, 33, 30,
+    28 km/h: 10, 11, 12, 13 ticks of travel), A on e1 at tick 10.  Every
+    tick both queues hold one vehicle and the tie goes to e0, the lower road
+    id; A's window [90, 100 s) is closed.  T_max = 3 s: A has waited 3 s at
+    tick 13 and goes: 24 s.  T_max = 20 s: A goes at tick 14, once e0 is
+    empty: 25 s.  The B's pass as they arrive and drive e2 at their own
+    speeds too (10, 11, 12, 13 ticks): 21, 23, 25, 27 s."""
+    g = merge_graph(900, 100)
+    paths = np.array([[1, 2], [0, 2], [0, 2], [0, 2], [0, 2]])
+    spd = [36, 36, 33, 30, 28]
+    p = default_params(theta=1000)
+    r = orc.simulate(g, dict(p, t_max_ms=3000), paths, [2] * 5, spd)
+    assert r["arrival_ms"].tolist() == [24000, 21000, 23000, 25000, 27000]
+    assert r["wait_ms"].tolist() == [3000, 0, 0, 0, 0]
+    r = orc.simulate(g, dict(p, t_max_ms=20000), paths, [2] * 5, spd)
+    assert r["arrival_ms"].tolist() == [25000, 21000, 23000, 25000, 27000] and r["wait_ms"][0] == 4000
+    assert r["last_ms"] == 27000
+
+
+def test_sim_congestion(orc):
+    """Five vehicles on one road: above theta = 4 each covers
+    floor(36 * 4 / 5) = 28 km/h, so ceil(360000 / 28000) = 13 ticks; at
+    theta = 5 the road is not congested: 10 ticks."""
+    g = from_edges(2, [0], [1], len_dm=1000, speed_kmh=36)
+    paths = np.zeros((5, 1), np.uint32)
+    assert orc.simulate(g, default_params(theta=4), paths, [1] * 5, [36] * 5)["arrival_ms"].tolist() == [13000] * 5
+    assert orc.simulate(g, default_params(theta=5), paths, [1] * 5, [36] * 5)["arrival_ms"].tolist() == [10000] * 5
+    r = orc.simulate(g, default_params(theta=1), paths, [1] * 5, [36] * 5)   # floor(36/5) = 7: 52 ticks
+    assert r["arrival_ms"].tolist() == [52000] * 5
+
+
+def test_sim_free_flow_closed_form(orc):
+    """No signals, no congestion: a vehicle's trip is, road by road, the
+    ticks its speed needs to cover the road, plus one tick per crossing."""
+    rng = np.random.default_rng(91)
+    g = grid_graph(6, 6, rng)
+    g.cycle_ms[:] = 0
+    p = default_params(theta=10**6)
+    V = random_od(g.n, 40, rng)
+    S = 64
+    paths = np.zeros((len(V), S), np.uint32)
+    plen = np.zeros(len(V), np.uint32)
+    for i in range(len(V)):
+        r = orc.shortest_route(g, p, int(V.src[i]), int(V.dst[i]), S)
+        paths[i, :len(r)] = r
+        plen[i] = len(r)
+    spd = rng.integers(50, 81, size=len(V)).astype(np.uint32)
+    tick = 700
+    res = orc.simulate(g, p, paths, plen, spd, tick_ms=tick)
+    for i in range(len(V)):
+        if plen[i] == 0:
+            assert res["arrival_ms"][i] == 0xFFFFFFFF
+            continue
+        ticks = int(plen[i]) - 1
+        for e in paths[i, :plen[i]]:
+            v = min(int(spd[i]), int(g.speed_kmh[e]))
+            ticks += -(-int(g.len_dm[e]) * 360 // (v * tick))
+        assert int(res["arrival_ms"][i]) == ticks * tick, i
+    assert res["wait_ms"].sum() == 0
+
+
+def test_sim_no_route_limit_and_rejections(orc):
+    g = from_edges(3, [0, 1], [1, 2], len_dm=1000, speed_kmh=36)
+    p = default_params()
+    paths = np.array([[0, 1], [0, 0], [1, 0]])
+    r = orc.simulate(g, p, paths, [2, 0, 1], [36, 36, 36])
+    assert r["arrival_ms"].tolist() == [21000, 0xFFFFFFFF, 10000] and r["arrived"] == 2
+    r = orc.simulate(g, p, paths[:1], [2], [36], max_ticks=15)          # cut before the end
+    assert r["arrival_ms"].tolist() == [0xFFFFFFFF] and r["ticks"] == 15 and r["mean_ms"] is None
+    for bad_paths, bad_len, bad_spd in ((np.array([[1, 0]]), [2], [36]),      # not connected
+                                        (np.array([[0, 7]]), [2], [36]),      # road out of range
+                                        (np.array([[0, 1]]), [2], [0]),       # no speed
+                                        (np.array([[0, 1]]), [3], [36])):     # longer than its row
+        with pytest.raises(ValueError):
+            orc.simulate(g, p, bad_paths, bad_len, bad_spd)
