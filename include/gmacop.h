@@ -267,6 +267,40 @@ int gmacop_goal_rows(gmacop_graph *g, const uint32_t *dst, uint32_t nd, uint32_t
 int gmacop_shortest_routes(gmacop_graph *g, const gmacop_od *q, uint32_t nq, uint32_t max_steps,
                            gmacop_result *out, void *hip_stream);
 
+/* Traffic simulation of trips along given routes (Section 5: vehicles drive
+ * their routes at their own speeds and the preemptive signal rule of Fig. 3
+ * applies at every signal they meet; the overall travel time of Table 1).
+ * Synchronous ticks of tick_ms; every vehicle with a route departs at time 0
+ * from the start of its first road.  A moving vehicle covers min(its speed,
+ * the road's) km/h per tick, slowed to max(1, floor(v * theta / N)) when its
+ * road carries N > p->theta vehicles; at the end of a road it stops, at the
+ * end of its route it arrives.  A stopped vehicle passes the next tick when
+ * its approach is green -- the head has no signal, or the tick's start time
+ * lies in the approach's green window (the windows of GMACOP_SIGNAL_TIMED),
+ * or its queue is the largest non-empty one at the intersection (ties: the
+ * lowest road id), or its queue exceeds p->th_max -- or once it has waited
+ * p->t_max_ms; the crossing takes the tick.  Only theta, th_max and t_max_ms
+ * of p are used; the sensed loads are not (the vehicles themselves load the
+ * roads).
+ *
+ * Scenarios: vehicles scen_off[b] .. scen_off[b+1]-1 form scenario b (b <
+ * nscen), simulated on their own (one workgroup each), so many runs of the
+ * same network go in one call.  Host arrays: path[v * stride + r] the r-th
+ * road of vehicle v's route (roads in range, each starting at the node where
+ * the previous one ends), path_len[v] <= stride (0: no route, the vehicle
+ * stays out), speed_kmh[v] >= 1 when it has a route, scen_off[nscen + 1]
+ * (scen_off[0] = 0, non-decreasing).  Outputs (host): arrival_ms[v] (ms;
+ * 0xFFFFFFFF without a route or when max_ticks ticks ended first), wait_ms[v]
+ * (ms stopped at signals), ticks_run[b].  GMACOP_E_INVAL for any check above,
+ * p->theta = 0 or tick_ms = 0, before any device work.  Synchronous on
+ * hip_stream; uses temporary device memory (road counts in LDS when 8 bytes
+ * per road fit, else nscen * 8 bytes per road, at most 16 GiB:
+ * GMACOP_E_NOMEM beyond). */
+int gmacop_simulate(gmacop_graph *g, const gmacop_params *p, const uint32_t *path, uint32_t stride,
+                    const uint32_t *path_len, const uint32_t *speed_kmh, const uint32_t *scen_off, uint32_t nscen,
+                    uint32_t tick_ms, uint32_t max_ticks, uint32_t *arrival_ms, uint32_t *wait_ms,
+                    uint32_t *ticks_run, void *hip_stream);
+
 /* Work counters and kernel times accumulated over gmacop_route_batch calls
  * since the last reset.  Kernel index: 0 = walk phase (tour construction and
  * deposit, all walkers of an iteration), 1 = best-route reduction, 2 =

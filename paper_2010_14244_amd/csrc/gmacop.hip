@@ -1984,6 +1984,154 @@ __global__ __launch_bounds__(1024) void k_goal_sssp(GoalArgs a)
     }
 }
 
+// ---- traffic simulation of trips along routes (Section 5) ----
+
+struct SimArgs {
+    const uint32_t *path;        // [vehicles][stride] roads of each route
+    const uint32_t *path_len;    // [vehicles] (0: no route, the vehicle stays out)
+    const uint32_t *spd;         // [vehicles] km/h
+    const uint32_t *scen_off;    // [nscen + 1] first vehicle of each scenario
+    uint32_t stride, nscen, m, tick_ms, max_ticks, theta, th_max, t_max;
+    const uint32_t *col, *len_dm, *rev_ptr, *rev_edge;
+    const uint16_t *speed;
+    const uint4 *sig;            // per road: head's cycle, green window start and length
+    uint32_t *counts;            // [nscen][2][m] vehicles on / stopped at the end of each road, or NULL: in LDS
+    uint64_t *pos;               // [vehicles] position on the current road, 1/360 dm
+    uint32_t *road, *waited;     // [vehicles] index into the route; wait at the current stop line
+    uint8_t *stopped, *active, *act;   // [vehicles] flags; this tick's change (1 passed, 2 stopped, 3 arrived)
+    uint32_t *arrival, *wait_total;    // [vehicles] results: arrival time (ms), total signal wait (ms)
+    uint32_t *ticks;             // [nscen] ticks run
+};
+
+constexpr uint32_t kNoArrival = 0xFFFFFFFFu;
+
+// One workgroup per scenario, every tick of it in one launch: a tick first
+// decides every vehicle's move from the counts at the tick's start (vehicles
+// on each road, and stopped at its end), then applies the changes to the
+// counts, with a barrier after each half.  The counts sit in LDS when the
+// roads fit, else in a global slice of the scenario (read at device scope,
+// since the atomics that change them bypass the CU's cache).  A vehicle
+// stopped at the end of road e passes when its approach is green -- the head
+// has no signal, e's queue is the longest non-empty one at the head (ties:
+// lowest road id) or exceeds Th_max, or the time lies in e's green window --
+// or when it has waited T_max; a moving vehicle covers min(its speed, the
+// road's) km/h, slowed by theta / N above theta vehicles.
+__global__ __launch_bounds__(1024) void k_simulate(SimArgs a)
+{
+    extern __shared__ uint32_t s_cnt[];   // [2][m] when the roads fit
+    __shared__ uint32_t s_rem;
+    const uint32_t b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    if (b >= a.nscen) return;
+    const uint32_t v0 = a.scen_off[b], v1 = a.scen_off[b + 1];
+    const bool in_lds = a.counts == nullptr;
+    uint32_t *N = in_lds ? s_cnt : a.counts + (size_t)b * 2 * a.m;
+    uint32_t *Q = N + a.m;
+    auto rd = [&](const uint32_t *c, uint32_t e) { return in_lds ? c[e] : ld_agent(c + e); };
+    auto barrier = [&] {   // global counts: every atomic and store complete at device scope first
+        if (!in_lds) __threadfence();
+        __syncthreads();
+    };
+    for (uint32_t e = tid; e < 2 * a.m; e += nt) {
+        if (in_lds) N[e] = 0;
+        else st_agent(N + e, 0u);
+    }
+    if (tid == 0) s_rem = 0;
+    barrier();
+    for (uint32_t i = v0 + tid; i < v1; i += nt) {
+        const bool go = a.path_len[i] > 0;
+        a.pos[i] = 0;
+        a.road[i] = 0;
+        a.waited[i] = 0;
+        a.wait_total[i] = 0;
+        a.stopped[i] = 0;
+        a.active[i] = go ? 1 : 0;
+        a.arrival[i] = kNoArrival;
+        if (go) {
+            atomicAdd(&N[a.path[(size_t)i * a.stride]], 1u);
+            atomicAdd(&s_rem, 1u);
+        }
+    }
+    barrier();
+    uint32_t k = 0;
+    for (; k < a.max_ticks; ++k) {
+        if (s_rem == 0) break;   // read by every thread after the barrier: the same value
+        const uint64_t t = (uint64_t)k * a.tick_ms;
+        for (uint32_t i = v0 + tid; i < v1; i += nt) {   // decide
+            a.act[i] = 0;
+            if (!a.active[i]) continue;
+            const uint32_t *route = a.path + (size_t)i * a.stride;
+            const uint32_t r = a.road[i], e = route[r];
+            if (a.stopped[i]) {
+                const uint4 sg = a.sig[e];
+                const uint32_t qe = rd(Q, e);
+                bool green = sg.x == 0 || qe > a.th_max;
+                if (!green) {   // the longest queue at the head; e's own queue holds this vehicle
+                    const uint32_t head = a.col[e];
+                    bool first = true;
+                    for (uint32_t j = a.rev_ptr[head]; j < a.rev_ptr[head + 1] && first; ++j) {
+                        const uint32_t f = a.rev_edge[j];
+                        if (f == e) continue;
+                        const uint32_t qf = rd(Q, f);
+                        first = qf < qe || (qf == qe && f > e);
+                    }
+                    green = first;
+                }
+                if (!green) green = ((t % sg.x + sg.x - sg.y) % sg.x) < sg.z;
+                if (green || a.waited[i] >= a.t_max) {
+                    a.road[i] = r + 1;
+                    a.pos[i] = 0;
+                    a.stopped[i] = 0;
+                    a.waited[i] = 0;
+                    a.act[i] = 1;
+                } else {
+                    a.waited[i] += a.tick_ms;
+                    a.wait_total[i] += a.tick_ms;
+                }
+                continue;
+            }
+            uint64_t v = min(a.spd[i], (uint32_t)a.speed[e]);
+            const uint32_t ne = rd(N, e);
+            if (ne > a.theta) {
+                v = v * a.theta / ne;
+                if (v == 0) v = 1;
+            }
+            const uint64_t np = a.pos[i] + v * a.tick_ms, L = (uint64_t)a.len_dm[e] * 360u;
+            if (np < L) {
+                a.pos[i] = np;
+            } else if (r + 1 == a.path_len[i]) {
+                const uint64_t at = t + a.tick_ms;
+                a.arrival[i] = at > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)at;
+                a.active[i] = 0;
+                a.act[i] = 3;
+            } else {
+                a.pos[i] = L;
+                a.stopped[i] = 1;
+                a.waited[i] = 0;
+                a.act[i] = 2;
+            }
+        }
+        barrier();
+        for (uint32_t i = v0 + tid; i < v1; i += nt) {   // apply the tick's changes to the counts
+            const uint8_t c = a.act[i];
+            if (!c) continue;
+            const uint32_t *route = a.path + (size_t)i * a.stride;
+            const uint32_t r = a.road[i];
+            if (c == 1) {   // left road r - 1 from its stop line, now on road r
+                atomicSub(&N[route[r - 1]], 1u);
+                atomicSub(&Q[route[r - 1]], 1u);
+                atomicAdd(&N[route[r]], 1u);
+            } else if (c == 2) {
+                atomicAdd(&Q[route[r]], 1u);
+            } else {
+                atomicSub(&N[route[r]], 1u);
+                atomicSub(&s_rem, 1u);
+            }
+        }
+        barrier();
+    }
+    if (tid == 0) a.ticks[b] = k;
+}
+
 // The shortest free-flow route of each vehicle (the Dijkstra baseline of
 // Table 1), one lane per vehicle: from the source, repeatedly the first
 // out-road in road order whose free-flow time equals the drop of the exact
@@ -2339,6 +2487,7 @@ struct gmacop_graph {
     uint64_t *gcsum = nullptr, *gmark = nullptr, *gmsum = nullptr;
     uint2 *rev_tw = nullptr;
     uint4 *sig = nullptr;              // [m] time-dependent signals: head's cycle, green window start and length
+    std::vector<uint32_t> col_host, tail_host;   // head and tail of each road, copied on first need (route checks)
     // statistics
     uint64_t *counters = nullptr;         // device [kCounters]
     uint32_t *iter_max = nullptr;         // device [1]
@@ -3875,6 +4024,96 @@ extern "C" int gmacop_shortest_routes(gmacop_graph *g, const gmacop_od *q, uint3
     dfree(dq); dfree(dpath); dfree(dlen); dfree(dcost); dfree(dsteps);
     if (rc) return rc;
     if (e != hipSuccess) return fail(GMACOP_E_DEVICE, "gmacop_shortest_routes: %s", hipGetErrorString(e));
+    return GMACOP_OK;
+}
+
+extern "C" int gmacop_simulate(gmacop_graph *g, const gmacop_params *p, const uint32_t *path, uint32_t stride,
+                               const uint32_t *path_len, const uint32_t *speed_kmh, const uint32_t *scen_off,
+                               uint32_t nscen, uint32_t tick_ms, uint32_t max_ticks, uint32_t *arrival_ms,
+                               uint32_t *wait_ms, uint32_t *ticks_run, void *hip_stream)
+{
+    if (!g || !p) return fail(GMACOP_E_INVAL, "graph or params is NULL");
+    if (!nscen) return GMACOP_OK;
+    if (!scen_off || !ticks_run) return fail(GMACOP_E_INVAL, "scenario offsets or ticks_run is NULL");
+    if (tick_ms == 0) return fail(GMACOP_E_INVAL, "tick_ms must be >= 1");
+    if (p->theta == 0) return fail(GMACOP_E_INVAL, "theta must be >= 1");
+    if (scen_off[0] != 0) return fail(GMACOP_E_INVAL, "scen_off[0] must be 0");
+    uint32_t most = 0;
+    for (uint32_t b = 0; b < nscen; ++b) {
+        if (scen_off[b + 1] < scen_off[b]) return fail(GMACOP_E_INVAL, "scen_off decreases at %u", b);
+        most = std::max(most, scen_off[b + 1] - scen_off[b]);
+    }
+    const uint32_t nv = scen_off[nscen];
+    if (nv && (!path || !path_len || !speed_kmh || !arrival_ms || !wait_ms))
+        return fail(GMACOP_E_INVAL, "vehicle arrays are NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    if (g->col_host.size() != g->m) {
+        std::vector<uint32_t> col(g->m), tail(g->m);
+        HIP_TRY(hipMemcpy(col.data(), g->col, 4ull * g->m, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(tail.data(), g->tail, 4ull * g->m, hipMemcpyDeviceToHost));
+        g->col_host.swap(col);
+        g->tail_host.swap(tail);
+    }
+    for (uint32_t i = 0; i < nv; ++i) {   // routes: roads in range, each starting where the last one ended
+        const uint32_t L = path_len[i];
+        if (L > stride) return fail(GMACOP_E_INVAL, "vehicle %u: route longer than its row", i);
+        if (L && speed_kmh[i] == 0) return fail(GMACOP_E_INVAL, "vehicle %u: speed 0", i);
+        for (uint32_t r = 0; r < L; ++r) {
+            const uint32_t e = path[(size_t)i * stride + r];
+            if (e >= g->m) return fail(GMACOP_E_INVAL, "vehicle %u: road out of range", i);
+            if (r && g->tail_host[e] != g->col_host[path[(size_t)i * stride + r - 1]])
+                return fail(GMACOP_E_INVAL, "vehicle %u: route not connected at road %u", i, r);
+        }
+    }
+    // counts of each scenario in LDS when the roads fit, else a global slice per scenario
+    const size_t lds_bytes = (size_t)8 * g->m;
+    const bool in_lds = lds_bytes + 64 <= (size_t)g->max_lds && env_u32("GMACOP_SIM_GLOBAL", 0) == 0;
+    if (!in_lds && (size_t)nscen * 2 * g->m > (4ull << 30))
+        return fail(GMACOP_E_NOMEM, "road counts of %u scenarios exceed 16 GiB", nscen);
+    const uint32_t threads = std::min<uint32_t>(1024, std::max<uint32_t>(kWave, (most + kWave - 1) / kWave * kWave));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t NV = std::max<uint32_t>(nv, 1), SP = (size_t)std::max<uint32_t>(stride, 1) * NV;
+    uint32_t *dpath = nullptr, *dlen = nullptr, *dspd = nullptr, *doff = nullptr, *dcounts = nullptr;
+    uint32_t *droad = nullptr, *dwaited = nullptr, *darr = nullptr, *dwait = nullptr, *dticks = nullptr;
+    uint64_t *dpos = nullptr;
+    uint8_t *dflags = nullptr;
+    int rc;
+    hipError_t e = hipSuccess;
+    if (!(rc = dalloc(&dpath, SP)) && !(rc = dalloc(&dlen, NV)) && !(rc = dalloc(&dspd, NV)) &&
+        !(rc = dalloc(&doff, nscen + 1)) && !(rc = dalloc(&droad, NV)) && !(rc = dalloc(&dwaited, NV)) &&
+        !(rc = dalloc(&darr, NV)) && !(rc = dalloc(&dwait, NV)) && !(rc = dalloc(&dticks, nscen)) &&
+        !(rc = dalloc(&dpos, NV)) && !(rc = dalloc(&dflags, 3 * NV)) &&
+        !(rc = in_lds ? GMACOP_OK : dalloc(&dcounts, (size_t)nscen * 2 * g->m))) {
+        if (nv) e = hipMemcpyAsync(dpath, path, 4 * (size_t)nv * stride, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && nv) e = hipMemcpyAsync(dlen, path_len, 4ull * nv, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && nv) e = hipMemcpyAsync(dspd, speed_kmh, 4ull * nv, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(doff, scen_off, 4ull * (nscen + 1), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && in_lds && lds_bytes > 65536)
+            e = hipFuncSetAttribute((const void *)k_simulate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds_bytes);
+        if (e == hipSuccess) {
+            SimArgs a{};
+            a.path = dpath; a.path_len = dlen; a.spd = dspd; a.scen_off = doff;
+            a.stride = std::max<uint32_t>(stride, 1); a.nscen = nscen; a.m = g->m; a.tick_ms = tick_ms;
+            a.max_ticks = max_ticks; a.theta = p->theta; a.th_max = p->th_max; a.t_max = p->t_max_ms;
+            a.col = g->col; a.len_dm = g->len_dm; a.rev_ptr = g->rev_ptr; a.rev_edge = g->rev_edge;
+            a.speed = g->speed; a.sig = g->sig; a.counts = in_lds ? nullptr : dcounts;
+            a.pos = dpos; a.road = droad; a.waited = dwaited;
+            a.stopped = dflags; a.active = dflags + NV; a.act = dflags + 2 * NV;
+            a.arrival = darr; a.wait_total = dwait; a.ticks = dticks;
+            hipLaunchKernelGGL(k_simulate, dim3(nscen), dim3(threads), in_lds ? lds_bytes : 0, st, a);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && nv) e = hipMemcpyAsync(arrival_ms, darr, 4ull * nv, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && nv) e = hipMemcpyAsync(wait_ms, dwait, 4ull * nv, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(ticks_run, dticks, 4ull * nscen, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    (void)hipStreamSynchronize(st);   // nothing may still use the buffers freed below
+    dfree(dpath); dfree(dlen); dfree(dspd); dfree(doff); dfree(dcounts); dfree(droad); dfree(dwaited);
+    dfree(darr); dfree(dwait); dfree(dticks); dfree(dpos); dfree(dflags);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(GMACOP_E_DEVICE, "gmacop_simulate: %s", hipGetErrorString(e));
     return GMACOP_OK;
 }
 

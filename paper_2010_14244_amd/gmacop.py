@@ -37,7 +37,7 @@ SIGNAL_TIMED = 64
 
 EXPORTED = ("gmacop_graph_create", "gmacop_route_batch", "gmacop_route_batch_noalloc", "gmacop_state_get", "gmacop_state_set",
             "gmacop_set_base_load", "gmacop_server_set_base_load", "gmacop_vehicle_tau_get",
-            "gmacop_goal_rows", "gmacop_shortest_routes", "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
+            "gmacop_goal_rows", "gmacop_shortest_routes", "gmacop_simulate", "gmacop_stats_get", "gmacop_server_create", "gmacop_server_info", "gmacop_server_step",
             "gmacop_server_release", "gmacop_release", "gmacop_last_error")
 KERNELS = ("walk", "best", "edge", "cost", "walk_lds", "walk_glb", "goal")
 WALKERS = ("lds", "glb", "first")
@@ -117,6 +117,9 @@ def lib():
         L.gmacop_goal_rows.restype = C.c_int
         L.gmacop_shortest_routes.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.POINTER(_Result), vp]
         L.gmacop_shortest_routes.restype = C.c_int
+        L.gmacop_simulate.argtypes = [vp, C.POINTER(_Params), vp, C.c_uint32, vp, vp, vp, C.c_uint32, C.c_uint32,
+                                      C.c_uint32, vp, vp, vp, vp]
+        L.gmacop_simulate.restype = C.c_int
         L.gmacop_stats_get.argtypes = [vp, C.POINTER(_Stats), C.c_int, vp]
         L.gmacop_stats_get.restype = C.c_int
         u32p = C.POINTER(C.c_uint32)
@@ -308,6 +311,35 @@ def gmacop_shortest_routes(g: Graph, veh, max_steps: int, stream: Optional[int] 
     res = _Result(path.ctypes.data, plen.ctypes.data, cost.ctypes.data, steps.ctypes.data)
     _check(lib().gmacop_shortest_routes(g.handle, od.ctypes.data if V else None, V, S, C.byref(res), stream))
     return dict(path_edges=path, path_len=plen, cost_ms=cost, steps_total=int(steps[0]))
+
+
+def gmacop_simulate(g: Graph, p: dict, path_edges, path_len, speed_kmh, scen_off=None, *, tick_ms: int = 1000,
+                    max_ticks: int = 100000, stream: Optional[int] = None) -> dict:
+    """Traffic simulation of trips along given routes (gmacop_simulate).
+    path_edges [V, stride] roads, path_len [V], speed_kmh [V]; scen_off
+    [S + 1] splits the vehicles into scenarios simulated on their own (one
+    scenario when None).  Returns arrival_ms and wait_ms per vehicle and
+    ticks per scenario."""
+    path = np.ascontiguousarray(path_edges, np.uint32)
+    if path.ndim != 2:
+        raise ValueError("path_edges must be [vehicles, stride]")
+    V, S = path.shape
+    plen = np.ascontiguousarray(path_len, np.uint32)
+    spd = np.ascontiguousarray(speed_kmh, np.uint32)
+    if plen.shape != (V,) or spd.shape != (V,):
+        raise ValueError("path_len and speed_kmh need one entry per vehicle")
+    off = np.ascontiguousarray([0, V] if scen_off is None else scen_off, np.uint32)
+    if off.ndim != 1 or off.shape[0] < 2 or int(off[-1]) != V:
+        raise ValueError("scen_off must run from 0 to the vehicle count")
+    nscen = off.shape[0] - 1
+    arr = np.zeros(max(V, 1), np.uint32)
+    wait = np.zeros(max(V, 1), np.uint32)
+    ticks = np.zeros(nscen, np.uint32)
+    pp = _params(p)
+    _check(lib().gmacop_simulate(g.handle, C.byref(pp), path.ctypes.data, S, plen.ctypes.data, spd.ctypes.data,
+                                 off.ctypes.data, nscen, int(tick_ms), int(max_ticks), arr.ctypes.data,
+                                 wait.ctypes.data, ticks.ctypes.data, stream))
+    return dict(arrival_ms=arr[:V], wait_ms=wait[:V], ticks=ticks)
 
 
 def gmacop_stats_get(g: Graph, reset: bool = False, stream: Optional[int] = None) -> dict:
