@@ -173,6 +173,24 @@ def cpu_baseline(w, vehicles):
                       f"({r['steps_total']} selections in {dt:.1f} s, single thread)"}
 
 
+def cpu_serving_baseline(w, od, count):
+    """The oracle on the router's own query stream, one query at a time
+    (independent mode: each query's result depends on it alone): its
+    sequential query rate, one thread."""
+    import oracle
+    from workloads import Vehicles
+    oracle.build(force=False)
+    k = min(count, od.shape[0])
+    t = time.perf_counter()
+    sel = 0
+    for i in range(k):
+        one = Vehicles(qid=od[i:i + 1, 0].copy(), src=od[i:i + 1, 1].copy(), dst=od[i:i + 1, 2].copy())
+        sel += oracle.route(w.graph, one, w.params, want_state=False)["steps_total"]
+    dt = time.perf_counter() - t
+    return {"qps": k / dt, "edge_selections_per_s": sel / dt, "cores": 1, "kind": "oracle",
+            "sample": f"{w.name}: the first {k} queries of the router's stream, one at a time ({dt:.1f} s)"}
+
+
 def measure_forms(gmacop, G, w, stream_obj, max_vehicles):
     """Independent-mode routing of the first `max_vehicles` vehicles, two
     ways: the plain per-query form (one gmacop_route_batch per vehicle,
@@ -266,10 +284,12 @@ def run_serving(args, log):
     stream = stream_obj.cuda_stream
     log(f"[bench] {w.name}: n={g.n} m={g.m} slots={srv.slots} ({srv.bytes_per_slot / 2**20:.1f} MiB each)")
     rng = np.random.default_rng(7)
-    qid0, runs = 0, []
+    qid0, runs, first_od = 0, [], None
     for rate in [float(r) for r in args.rates.split(",")]:
         n = max(int(rate * args.serve_seconds), args.serve_min_queries + args.serve_warmup)
         od = workloads.query_stream(g, n, rng, qid0=qid0)
+        if first_od is None:
+            first_od = od
         qid0 += n
         arr = serve.poisson_arrivals(n, rate, rng)
         gmacop.gmacop_stats_get(G, reset=True)
@@ -291,9 +311,10 @@ def run_serving(args, log):
             f"p99 {r['p99_ms']:.1f} ms routed {run['routed_fraction']:.3f}, {r['steps']} steps")
     srv.release()
     gmacop.gmacop_release(G)
-    return {"workload": w.name, "nodes": g.n, "roads": g.m, "ants": p["ants"], "iterations": p["iterations"],
-            "max_steps": p["max_steps"], "slots": srv.slots, "mode": "independent",
-            "goal": "straight line at the top speed", "runs": runs}
+    out = {"workload": w.name, "nodes": g.n, "roads": g.m, "ants": p["ants"], "iterations": p["iterations"],
+           "max_steps": p["max_steps"], "slots": srv.slots, "mode": "independent",
+           "goal": "straight line at the top speed", "runs": runs}
+    return out, (w, first_od)
 
 
 def walker_roofline(st, kernel_ms_key, walker_key, workload, names):
@@ -330,6 +351,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-vehicles", type=int, default=1280,
                     help="CPU oracle: the first this many vehicles (about 14 s of one core on the 64 cities)")
+    ap.add_argument("--cpu-serve-queries", type=int, default=16,
+                    help="CPU oracle: router queries timed one at a time (0: none)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed pass (roofline becomes null)")
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
@@ -468,11 +491,17 @@ def main():
     gmacop.gmacop_release(G)
     del b
     torch.cuda.empty_cache()
+    served = None
     if not args.no_serve:
-        out["serving"] = run_serving(args, log)
+        out["serving"], served = run_serving(args, log)
     if not args.no_cpu:
         log(f"[bench] timing the CPU oracle on the first {args.cpu_vehicles} vehicles")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_vehicles)
+        cb = cpu_baseline(w, args.cpu_vehicles)
+        cb["extrapolated_full_call_s"] = out["config"]["selections_per_step"] / cb["value"]
+        if served is not None and served[1] is not None and args.cpu_serve_queries:
+            log(f"[bench] timing the CPU oracle on {args.cpu_serve_queries} router queries")
+            cb["serving"] = cpu_serving_baseline(served[0], served[1], args.cpu_serve_queries)
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
