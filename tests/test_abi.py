@@ -111,3 +111,17 @@ def test_kernel_machine_code_hash_of_the_built_library():
     assert len({h42, h42t, h41, hl}) == 4
     assert bench.kernel_isa_hash(lib, r"no_such_kernel_name") is None
     assert bench.kernel_isa_hash(os.path.join(ROOT, "bench.py"), r"k_walk_glb") is None
+
+
+def test_simulate_binding_checks_before_the_library():
+    """gmacop_simulate's binding rejects malformed arrays itself (no device
+    work, no graph needed)."""
+    class NoGraph:
+        handle = None
+    p = grid8().params
+    with pytest.raises(ValueError):
+        gmacop.gmacop_simulate(NoGraph(), p, np.zeros(4, np.uint32), [1], [36])            # not [V, stride]
+    with pytest.raises(ValueError):
+        gmacop.gmacop_simulate(NoGraph(), p, np.zeros((2, 3), np.uint32), [1], [36, 36])   # lengths per vehicle
+    with pytest.raises(ValueError):
+        gmacop.gmacop_simulate(NoGraph(), p, np.zeros((2, 3), np.uint32), [1, 1], [36, 36], scen_off=[0, 1])
